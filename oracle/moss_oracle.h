@@ -1,0 +1,113 @@
+/* Moss oracle: plain, slow, single-purpose CPU reference of the Moss estimators
+ * (Wang, Tao, Zhao, Guan: "Moss: A Scalable Tool for Efficiently Sampling and
+ * Counting 4- and 5-Node Graphlets", arXiv 1509.08089).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no source,
+ * header, table or generator with the GPU library.
+ *
+ * Every function cites the passage of the paper it follows.  Where the paper
+ * leaves a choice open (the random number generator, how a random number is
+ * mapped to an outcome, how an excluded element is skipped), the oracle follows
+ * one fixed sampling contract:
+ *   words    B(k, j) = Philox4x64-10(counter = (k, j, 0, 0), key = (seed, tag)),
+ *            tag 0x4 for MOSS-4, 0x51 for T-5, 0x52 for Path-5, k the sample index
+ *   bounded  U(x, N) = floor(x * N / 2^64)
+ *   pick     pick(A, x) = min{ i : A[i] > U(x, A[L-1]) } over an inclusive prefix A
+ *   skips    an index draw that must avoid positions a < b is shifted past them in
+ *            ascending order; "a neighbour of u other than v" reads the sorted row
+ *            and steps over v.
+ */
+#ifndef MOSS_ORACLE_H
+#define MOSS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ORC_OK = 0, ORC_E_ARG = -1, ORC_E_UNSORTED = -2, ORC_E_SELF_LOOP = -3,
+  ORC_E_DUPLICATE = -4, ORC_E_ASYMMETRIC = -5, ORC_E_OVERFLOW = -6, ORC_E_NOMEM = -7
+};
+
+/* sampler ids */
+enum { ORC_MOSS4 = 4, ORC_T5 = 0x51, ORC_PATH5 = 0x52 };
+
+/* mix modes for 5-node finals */
+enum { ORC_MIX_POOLED = 0, ORC_MIX_PAPER = 1 };
+
+typedef struct orc_graph orc_graph;
+
+/* tables that can be copied out (orc_table) */
+enum {
+  ORC_TAB_S = 0,        /* u64[n]  sum_{x in N_v} (d_x - 1)                      */
+  ORC_TAB_Q = 1,        /* u64[n]  sum_{x in N_v} (d_x - 1)^2                    */
+  ORC_TAB_GAMMA = 2,    /* u64[n]  Gamma_v                                       */
+  ORC_TAB_GAMMA1 = 3,   /* u64[n]  Gamma^(1)_v                                   */
+  ORC_TAB_GAMMA2 = 4,   /* u64[n]  Gamma^(2)_v                                   */
+  ORC_TAB_ACC_GAMMA = 5,  /* u64[n] inclusive prefix of Gamma_v                   */
+  ORC_TAB_ACC_GAMMA1 = 6, /* u64[n]                                               */
+  ORC_TAB_ACC_GAMMA2 = 7, /* u64[n]                                               */
+  ORC_TAB_ACC_SIGMA = 8,  /* u32[nnz] row-local inclusive prefix of (d_x - 1)     */
+  ORC_TAB_ACC_TAU = 9     /* u64[nnz] row-local inclusive prefix of the tau weights */
+};
+
+typedef struct {
+  uint64_t gamma, gamma1, gamma2, lambda3, lambda4;
+} orc_totals;
+
+typedef struct {
+  int32_t k;                 /* 4 or 5 */
+  int32_t n_motifs;          /* 6 or 21 */
+  uint64_t K[2];             /* k=4: K[0]; k=5: K1 (T-5), K2 (Path-5) */
+  uint64_t hits[2][22];      /* [sampler][0] rejected, [sampler][i] class i */
+  double estimate[21];       /* estimate[i-1] for motif i */
+  double variance[21];
+} orc_result;
+
+int orc_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
+              int validate, orc_graph **out);
+void orc_free(orc_graph *g);
+int orc_totals_get(const orc_graph *g, orc_totals *t);
+int orc_table(const orc_graph *g, int which, void *out);
+
+/* primitives, exposed for the contract's own checks */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+uint64_t orc_bounded(uint64_t x, uint64_t n);
+int64_t orc_pick_u64(const uint64_t *acc, int64_t len, uint64_t x);
+int orc_classify(int k, const uint8_t *adj /* k*k row-major 0/1 */);
+
+/* one sample by index; nodes[] gets v,u,w,r(,t); returns class (0 = rejected),
+   or a negative status */
+int orc_sample(const orc_graph *g, int sampler, uint64_t seed, uint64_t k, int32_t nodes[5]);
+
+/* hits over sample indices [k0, k1) of one sampler, split over nthreads threads */
+int orc_run(const orc_graph *g, int sampler, uint64_t seed, uint64_t k0, uint64_t k1,
+            int nthreads, uint64_t hits[22]);
+
+/* estimator finals from hits (Thm 3 and Thm 10 with the readings above) */
+int orc_finals4(uint64_t K, const uint64_t hits[7], uint64_t gamma, uint64_t lambda3,
+                double est[6], double var[6]);
+int orc_finals5(uint64_t K1, uint64_t K2, const uint64_t hits1[22], const uint64_t hits2[22],
+                uint64_t gamma1, uint64_t gamma2, uint64_t lambda4, int mix,
+                double est[21], double var[21], double *cov /* 21*21 or NULL */);
+
+/* the whole estimate: k=4 -> MOSS-4 with K samples; k=5 -> T-5 with ceil(K/2) and
+   Path-5 with floor(K/2) samples, then the mix */
+int orc_estimate(const orc_graph *g, int k, uint64_t n_samples, uint64_t seed, int mix,
+                 int nthreads, orc_result *res);
+
+/* exact counts of k-node connected induced subgraphs per class (ESU enumeration) */
+int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]);
+
+/* mean number of distinct 64-byte lines one sample reads when every search is a
+   plain binary search and nothing is reused between samples; arrays are taken to
+   start on 64-byte boundaries with the widths of the sampling tables */
+int orc_line_count(const orc_graph *g, int sampler, uint64_t seed, uint64_t k0, uint64_t k1,
+                   double *mean_lines);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
