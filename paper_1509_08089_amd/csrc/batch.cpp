@@ -1,0 +1,397 @@
+// Batched estimation: many (graph, k, budget, seed) requests drained by one
+// persistent kernel launch, replayed from a captured hipGraph.
+#include "batch.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+namespace moss {
+
+namespace {
+std::mutex g_tune_mu;
+Tuning g_tuning;
+
+std::mutex g_runner_mu;
+std::map<int, std::unique_ptr<BatchRunner>> g_runners;
+
+constexpr uint32_t kDefaultTile = 16384;
+}  // namespace
+
+Tuning current_tuning() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tuning;
+}
+
+BatchRunner* batch_runner(int device) {
+  std::lock_guard<std::mutex> lk(g_runner_mu);
+  auto it = g_runners.find(device);
+  if (it != g_runners.end()) return it->second.get();
+  auto r = std::make_unique<BatchRunner>(device);
+  BatchRunner* p = r.get();
+  g_runners[device] = std::move(r);
+  return p;
+}
+
+void result_header(const moss_graph* g, int32_t k, uint64_t n_samples, uint32_t flags, moss_result* r) {
+  std::memset(r, 0, sizeof(*r));
+  r->k = k;
+  r->flags = flags;
+  r->n_samples = n_samples;
+  if (k == 4) {
+    r->n_motifs = 6;
+    r->K[0] = n_samples;
+    r->gamma[0] = g->total[0];
+    r->lambda = g->lambda3;
+  } else {
+    r->n_motifs = 21;
+    r->K[0] = (n_samples + 1) / 2;
+    r->K[1] = n_samples / 2;
+    r->gamma[0] = g->total[1];
+    r->gamma[1] = g->total[2];
+    r->lambda = g->lambda4;
+  }
+}
+
+BatchRunner::BatchRunner(int device) : device_(device) {}
+
+BatchRunner::~BatchRunner() {
+  // The per-device runners live until process exit, when the runtime may already be
+  // gone; owners that end earlier (servers) call release() first.
+}
+
+void BatchRunner::release() {
+  DeviceScope scope(device_);
+  if (stream_) (void)hipStreamSynchronize(stream_);
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+  exec_ = nullptr;
+  graph_ = nullptr;
+  graph_grid_ = graph_block_ = 0;
+  if (d_views_) (void)hipFree(d_views_);
+  if (d_tiles_) (void)hipFree(d_tiles_);
+  if (d_ctl_) (void)hipFree(d_ctl_);
+  if (d_bins_) (void)hipFree(d_bins_);
+  d_views_ = nullptr;
+  d_tiles_ = nullptr;
+  d_ctl_ = nullptr;
+  d_bins_ = nullptr;
+  cap_views_ = cap_tiles_ = cap_slots_ = 0;
+  if (h_in_) (void)hipHostFree(h_in_);
+  if (h_bins_) (void)hipHostFree(h_bins_);
+  h_in_ = nullptr;
+  h_bins_ = nullptr;
+  cap_in_ = 0;
+  if (ev0_) (void)hipEventDestroy(ev0_);
+  if (ev1_) (void)hipEventDestroy(ev1_);
+  if (ev_wait_) (void)hipEventDestroy(ev_wait_);
+  ev0_ = ev1_ = ev_wait_ = nullptr;
+  if (stream_) (void)hipStreamDestroy(stream_);
+  stream_ = nullptr;
+}
+
+moss_status BatchRunner::reserve(size_t views, size_t tiles, size_t slots) {
+  bool changed = false;
+  auto grow = [&](size_t need, size_t& cap, auto** ptr, size_t elem) -> moss_status {
+    if (need <= cap) return MOSS_OK;
+    size_t c = std::max<size_t>(need, cap * 2);
+    if (*ptr) (void)hipFree((void*)*ptr);
+    *ptr = nullptr;
+    if (hipMalloc((void**)ptr, c * elem) != hipSuccess) {
+      *ptr = nullptr;
+      cap = 0;
+      return MOSS_E_NOMEM;
+    }
+    cap = c;
+    changed = true;
+    return MOSS_OK;
+  };
+  moss_status st = grow(std::max<size_t>(views, 64), cap_views_, &d_views_, sizeof(SamplerView));
+  if (st == MOSS_OK) st = grow(std::max<size_t>(tiles, 1024), cap_tiles_, &d_tiles_, sizeof(Tile));
+  if (st == MOSS_OK) {
+    const size_t old = cap_slots_;
+    st = grow(std::max<size_t>(slots, 512), cap_slots_, &d_bins_, 22 * sizeof(unsigned long long));
+    if (st == MOSS_OK && cap_slots_ != old) {
+      if (h_bins_) (void)hipHostFree(h_bins_);
+      h_bins_ = nullptr;
+      if (hipHostMalloc((void**)&h_bins_, cap_slots_ * 22 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+        h_bins_ = nullptr;
+        return MOSS_E_NOMEM;
+      }
+    }
+  }
+  if (st != MOSS_OK) return st;
+  if (!d_ctl_) {
+    if (hipMalloc((void**)&d_ctl_, 4 * sizeof(uint32_t)) != hipSuccess) {
+      d_ctl_ = nullptr;
+      return MOSS_E_NOMEM;
+    }
+    changed = true;
+  }
+  const size_t in_bytes = cap_views_ * sizeof(SamplerView) + cap_tiles_ * sizeof(Tile) + 64;
+  if (in_bytes > cap_in_) {
+    if (h_in_) (void)hipHostFree(h_in_);
+    h_in_ = nullptr;
+    if (hipHostMalloc((void**)&h_in_, in_bytes, hipHostMallocDefault) != hipSuccess) {
+      h_in_ = nullptr;
+      cap_in_ = 0;
+      return MOSS_E_NOMEM;
+    }
+    cap_in_ = in_bytes;
+  }
+  if (changed && exec_) {
+    (void)hipGraphExecDestroy(exec_);
+    (void)hipGraphDestroy(graph_);
+    exec_ = nullptr;
+    graph_ = nullptr;
+  }
+  return MOSS_OK;
+}
+
+// Captures: clear all histogram slots and the tile counter (fill kernels), then the
+// persistent kernel.  Its arguments are the fixed buffers above, so one capture
+// serves every batch until a buffer is reallocated or the launch shape changes.
+moss_status BatchRunner::capture(int grid, int block) {
+  if (exec_ && grid == graph_grid_ && block == graph_block_) return MOSS_OK;
+  if (exec_) {
+    (void)hipGraphExecDestroy(exec_);
+    (void)hipGraphDestroy(graph_);
+    exec_ = nullptr;
+    graph_ = nullptr;
+  }
+  hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return status_of(e);
+  hipError_t e1 = launch_fill_u64((uint64_t*)d_bins_, 0, (int64_t)cap_slots_ * 22, stream_);
+  if (e1 == hipSuccess) e1 = launch_fill_u32(d_ctl_ + 1, 0, 1, stream_);
+  if (e1 == hipSuccess) e1 = launch_batch(d_views_, d_tiles_, d_ctl_, d_ctl_ + 1, d_bins_, grid, block, stream_);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(stream_, &g);
+  if (e1 != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return status_of(e1 != hipSuccess ? e1 : e);
+  }
+  e = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    exec_ = nullptr;
+    return status_of(e);
+  }
+  graph_ = g;
+  graph_grid_ = grid;
+  graph_block_ = block;
+  return MOSS_OK;
+}
+
+moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots, uint64_t* bins_out,
+                             double* device_ms, hipStream_t wait_on, uint32_t tile_samples, uint32_t blocks_per_cu) {
+  DeviceScope scope(device_);
+  if (!scope.ok()) return MOSS_E_DEVICE;
+  if (!stream_) {
+    if (hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess) return MOSS_E_DEVICE;
+    if (hipEventCreate(&ev0_) != hipSuccess || hipEventCreate(&ev1_) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_wait_, hipEventDisableTiming) != hipSuccess)
+      return MOSS_E_DEVICE;
+  }
+  const Tuning tune = current_tuning();
+  uint32_t T = tile_samples ? tile_samples : (tune.tile_samples ? tune.tile_samples : kDefaultTile);
+  const int block = tune.threads_per_block ? (int)tune.threads_per_block : 256;
+  int bpc = blocks_per_cu ? (int)blocks_per_cu : (int)tune.blocks_per_cu;
+  if (bpc == 0) bpc = std::max(1, std::min(8, sample_kernel_blocks_per_cu(0, block)));
+  const int grid = device_cus(device_) * bpc;
+
+  // views: one per distinct (graph, sampler)
+  std::vector<SamplerView> views;
+  std::map<std::pair<const moss_graph*, int>, uint32_t> view_of;
+  struct PendingTile {
+    Tile t;
+    uint64_t cost;
+  };
+  std::vector<PendingTile> tiles;
+  for (const WorkItem& w : work) {
+    if (w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
+    auto key = std::make_pair((const moss_graph*)w.g, w.sampler);
+    auto it = view_of.find(key);
+    uint32_t vi;
+    if (it == view_of.end()) {
+      vi = (uint32_t)views.size();
+      views.push_back(sampler_view(w.g, w.sampler));
+      view_of[key] = vi;
+    } else {
+      vi = it->second;
+    }
+    const uint64_t weight = w.sampler == kMoss4 ? 2 : 3;
+    for (uint64_t a = w.k0; a < w.k1; a += T) {
+      const uint64_t b = std::min<uint64_t>(w.k1, a + T);
+      Tile t{};
+      t.view = vi;
+      t.sampler = (uint32_t)w.sampler;
+      t.out = w.slot;
+      t.seed = w.seed;
+      t.k0 = a;
+      t.k1 = b;
+      tiles.push_back({t, (b - a) * weight});
+    }
+  }
+  // costliest tiles first so the last tiles drawn from the counter are the short ones
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [](const PendingTile& x, const PendingTile& y) { return x.cost > y.cost; });
+  if (tiles.size() >= 0xFFFFFFFFull) return MOSS_E_ARG;
+  moss_status st = reserve(views.size(), tiles.size(), n_slots);
+  if (st != MOSS_OK) return st;
+  st = capture(grid, block);
+  if (st != MOSS_OK) return st;
+
+  // stage views | tiles | n_tiles in pinned memory and copy in one transfer each
+  unsigned char* p = h_in_;
+  const size_t vbytes = views.size() * sizeof(SamplerView), tbytes = tiles.size() * sizeof(Tile);
+  std::memcpy(p, views.data(), vbytes);
+  Tile* tp = (Tile*)(p + vbytes);
+  for (size_t i = 0; i < tiles.size(); ++i) tp[i] = tiles[i].t;
+  uint32_t* np = (uint32_t*)(p + vbytes + tbytes);
+  np[0] = (uint32_t)tiles.size();
+
+  hipError_t e = hipSuccess;
+  if (wait_on) {
+    e = hipEventRecord(ev_wait_, wait_on);
+    if (e == hipSuccess) e = hipStreamWaitEvent(stream_, ev_wait_, 0);
+  }
+  if (e == hipSuccess && vbytes) e = hipMemcpyAsync(d_views_, p, vbytes, hipMemcpyHostToDevice, stream_);
+  if (e == hipSuccess && tbytes) e = hipMemcpyAsync(d_tiles_, p + vbytes, tbytes, hipMemcpyHostToDevice, stream_);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_ctl_, np, sizeof(uint32_t), hipMemcpyHostToDevice, stream_);
+  if (e == hipSuccess) e = hipEventRecord(ev0_, stream_);
+  if (e == hipSuccess) e = hipGraphLaunch(exec_, stream_);
+  if (e == hipSuccess) e = hipEventRecord(ev1_, stream_);
+  if (e == hipSuccess && n_slots)
+    e = hipMemcpyAsync(h_bins_, d_bins_, (size_t)n_slots * 22 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream_);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+  if (e != hipSuccess) return status_of(e);
+  std::memcpy(bins_out, h_bins_, (size_t)n_slots * 22 * sizeof(uint64_t));
+  if (device_ms) {
+    float ms = 0.f;
+    *device_ms = hipEventElapsedTime(&ms, ev0_, ev1_) == hipSuccess ? (double)ms : 0.0;
+  }
+  return MOSS_OK;
+}
+
+namespace {
+
+std::mutex g_batch_mu;  // one batch at a time per process (the runner is shared)
+
+moss_status batch_impl(const moss_request* reqs, int32_t n, moss_result* out, hipStream_t wait_on,
+                       uint32_t tile_samples, uint32_t blocks_per_cu, double* device_ms) {
+  if (n < 0 || (n > 0 && (!reqs || !out))) return MOSS_E_ARG;
+  if (n == 0) return MOSS_OK;
+  const int device = reqs[0].g ? reqs[0].g->device : -1;
+  for (int32_t i = 0; i < n; ++i) {
+    const moss_request& q = reqs[i];
+    if (!q.g || q.g->device != device || (q.k != 4 && q.k != 5) || (q.flags & ~MOSS_MIX_PAPER)) return MOSS_E_ARG;
+    if ((q.k == 4 && q.n_samples < 1) || (q.k == 5 && q.n_samples < 2)) return MOSS_E_ARG;
+  }
+  // build missing tables (each graph once)
+  for (int32_t i = 0; i < n; ++i) {
+    moss_graph* g = reqs[i].g;
+    const uint32_t mask = reqs[i].k == 4 ? MOSS_TABLES_K4 : MOSS_TABLES_K5;
+    if ((g->built & mask) == mask) continue;
+    GraphClaim claim(g);
+    if (!claim.ok()) return MOSS_E_BUSY;
+    moss_status st = build_tables(g, mask);
+    if (st != MOSS_OK) return st;
+  }
+  std::vector<WorkItem> work;
+  work.reserve((size_t)n * 2);
+  for (int32_t i = 0; i < n; ++i) {
+    const moss_request& q = reqs[i];
+    moss_result& r = out[i];
+    result_header(q.g, q.k, q.n_samples, q.flags, &r);
+    if (q.k == 4) {
+      work.push_back({q.g, kMoss4, q.seed, 0, r.K[0], (uint32_t)(2 * i)});
+    } else {
+      work.push_back({q.g, kT5, q.seed, 0, r.K[0], (uint32_t)(2 * i)});
+      work.push_back({q.g, kPath5, q.seed, 0, r.K[1], (uint32_t)(2 * i + 1)});
+    }
+  }
+  std::vector<uint64_t> bins((size_t)n * 2 * 22);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchRunner* runner = batch_runner(device);
+  double ms = 0.0;
+  moss_status st = runner->run(work, (uint32_t)(2 * n), bins.data(), &ms, wait_on, tile_samples, blocks_per_cu);
+  if (st != MOSS_OK) return st;
+  for (int32_t i = 0; i < n; ++i) {
+    moss_result& r = out[i];
+    std::memcpy(r.hits[0], &bins[(size_t)(2 * i) * 22], 22 * sizeof(uint64_t));
+    std::memcpy(r.hits[1], &bins[(size_t)(2 * i + 1) * 22], 22 * sizeof(uint64_t));
+    r.device_ms = ms;
+    st = moss_finals(&r);
+    if (st != MOSS_OK) return st;
+  }
+  if (device_ms) *device_ms = ms;
+  return MOSS_OK;
+}
+
+}  // namespace
+}  // namespace moss
+
+using namespace moss;
+
+extern "C" {
+
+moss_status moss_estimate_batch(const moss_request* reqs, int32_t n, moss_result* out, void* hip_stream) {
+  return batch_impl(reqs, n, out, (hipStream_t)hip_stream, 0, 0, nullptr);
+}
+
+moss_status moss_set_tuning(const moss_tuning* t) {
+  if (!t) return MOSS_E_ARG;
+  if (t->threads_per_block && (t->threads_per_block % 64 != 0 || t->threads_per_block > 256)) return MOSS_E_ARG;
+  if (t->blocks_per_cu > 64) return MOSS_E_ARG;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuning.tile_samples = t->tile_samples;
+  g_tuning.blocks_per_cu = t->blocks_per_cu;
+  g_tuning.threads_per_block = t->threads_per_block;
+  return MOSS_OK;
+}
+
+moss_status moss_get_tuning(moss_tuning* t) {
+  if (!t) return MOSS_E_ARG;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  t->tile_samples = g_tuning.tile_samples;
+  t->blocks_per_cu = g_tuning.blocks_per_cu;
+  t->threads_per_block = g_tuning.threads_per_block;
+  t->reserved = 0;
+  return MOSS_OK;
+}
+
+moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best, double* best_ms) {
+  if (!reqs || n <= 0 || !best) return MOSS_E_ARG;
+  static const uint32_t kTiles[] = {4096, 16384, 65536, 262144};
+  static const uint32_t kBpc[] = {2, 4, 8};
+  std::vector<moss_result> ref((size_t)n), cur((size_t)n);
+  moss_status st = batch_impl(reqs, n, ref.data(), nullptr, kDefaultTile, 4, nullptr);  // warm-up, reference
+  if (st != MOSS_OK) return st;
+  double best_t = 1e300;
+  moss_tuning b{};
+  for (uint32_t T : kTiles) {
+    for (uint32_t bpc : kBpc) {
+      double ms = 0.0;
+      st = batch_impl(reqs, n, cur.data(), nullptr, T, bpc, &ms);
+      if (st != MOSS_OK) return st;
+      for (int32_t i = 0; i < n; ++i)
+        if (std::memcmp(cur[i].hits, ref[i].hits, sizeof(ref[i].hits)) != 0) return MOSS_E_DEVICE;
+      if (ms < best_t) {
+        best_t = ms;
+        b.tile_samples = T;
+        b.blocks_per_cu = bpc;
+        b.threads_per_block = 256;
+      }
+    }
+  }
+  st = moss_set_tuning(&b);
+  if (st != MOSS_OK) return st;
+  *best = b;
+  if (best_ms) *best_ms = best_t;
+  return MOSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Device helpers for the Moss sampling kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace moss {
+
+// Philox4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC 2011).  Each round
+// takes the 128-bit products of words 0 and 2 with two odd multipliers; the next
+// state is (hi(M1 x2) ^ x1 ^ k0, lo(M1 x2), hi(M0 x0) ^ x3 ^ k1, lo(M0 x0)); the key
+// advances by two Weyl increments between rounds.
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+// Random words of block `blk` of sample `k`: counter (k, blk, 0, 0), key (seed, tag).
+__device__ __forceinline__ void philox_block(uint64_t k, uint64_t blk, uint64_t seed, uint64_t tag,
+                                             uint64_t out[4]) {
+  uint64_t x0 = k, x1 = blk, x2 = 0, x3 = 0;
+  uint64_t k0 = seed, k1 = tag;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    const uint64_t hi0 = __umul64hi(kPhiloxM0, x0), lo0 = kPhiloxM0 * x0;
+    const uint64_t hi1 = __umul64hi(kPhiloxM1, x2), lo1 = kPhiloxM1 * x2;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+// floor(x * n / 2^64): a uniform index in [0, n) from one 64-bit word.
+__device__ __forceinline__ uint64_t bounded(uint64_t x, uint64_t n) { return __umul64hi(x, n); }
+
+// Smallest i in [lo, hi] with acc[i] > r, given acc[hi] > r (inverse CDF over an
+// inclusive prefix; Section 4.1.3 "WeightRandomVertex", step 2).
+template <typename T>
+__device__ __forceinline__ int32_t first_above(const T* __restrict__ acc, int32_t lo, int32_t hi, uint64_t r) {
+  int32_t n = hi - lo;
+  while (n > 0) {
+    const int32_t half = n >> 1;
+    if (static_cast<uint64_t>(acc[lo + half]) <= r) {
+      lo += half + 1;
+      n -= half + 1;
+    } else {
+      n = half;
+    }
+  }
+  return lo;
+}
+
+// Is key in the sorted row col[base .. base+len)?
+__device__ __forceinline__ bool row_has(const int32_t* __restrict__ col, int32_t base, int32_t len, int32_t key) {
+  int32_t lo = base, n = len;
+  while (n > 1) {
+    const int32_t half = n >> 1;
+    if (col[lo + half] <= key) lo += half;
+    n -= half;
+  }
+  return n == 1 && col[lo] == key;
+}
+
+// Edge test between a (row ra, length da) and b: search the shorter row.
+__device__ __forceinline__ bool adjacent(const int32_t* __restrict__ col, int32_t ra, int32_t da, int32_t a,
+                                         int32_t rb, int32_t db, int32_t b) {
+  return da <= db ? row_has(col, ra, da, b) : row_has(col, rb, db, a);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Inclusive scan over the 64 lanes of a wave; `wrapped` is set on any 64-bit wrap.
+__device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t x, bool& wrapped) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(x, off, 64);
+    if (lane >= off) {
+      const uint64_t z = x + y;
+      wrapped |= z < x;
+      x = z;
+    }
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x |= __shfl_xor(x, off, 64);
+  return x;
+}
+
+// C(d, 3) and C(d, 4) for d < 2^31, exactly: the factorial denominators are
+// divided out of the consecutive factors before multiplying, so only the final
+// product can exceed 64 bits, which sets `over`.
+__device__ __forceinline__ uint64_t choose3(uint64_t d, bool& over) {
+  if (d < 3) return 0;
+  uint64_t f0 = d, f1 = d - 1, f2 = d - 2;
+  if ((f0 & 1) == 0) f0 >>= 1; else f1 >>= 1;
+  if (f0 % 3 == 0) f0 /= 3; else if (f1 % 3 == 0) f1 /= 3; else f2 /= 3;
+  const uint64_t p = f0 * f1;
+  over |= __umul64hi(p, f2) != 0;
+  return p * f2;
+}
+
+__device__ __forceinline__ uint64_t choose4(uint64_t d, bool& over) {
+  if (d < 4) return 0;
+  uint64_t f[4] = {d, d - 1, d - 2, d - 3};
+  // one of four consecutive numbers is a multiple of 4, the one two away is even
+  int i4 = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (f[i] % 4 == 0) i4 = i;
+  f[i4] /= 4;
+  f[i4 < 2 ? i4 + 2 : i4 - 2] /= 2;
+  bool done = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (!done && f[i] % 3 == 0) {
+      f[i] /= 3;
+      done = true;
+    }
+  const uint64_t p = f[0] * f[1], q = f[2] * f[3];
+  over |= __umul64hi(p, q) != 0;
+  return p * q;
+}
+
+}  // namespace moss

@@ -1,0 +1,121 @@
+// Estimator finals in double precision (host).
+//
+// MOSS-4, Section 4.1.2 / Theorems 2-3:
+//   p_i = 2 phi^(1)_i / Gamma, phi^(1) = (1, 0, 4, 2, 6, 12)
+//   n_i = m_i / (K p_i), i in {1,3,4,5,6};   n_2 = Lambda_3 - n_4 - 2 n_5 - 4 n_6
+//   Var(n_i) = n_i / K (1/p_i - n_i)
+//   Var(n_2) = (n_4/p_4 + 4 n_5/p_5 + 16 n_6/p_6 - (n_4 + 2 n_5 + 4 n_6)^2) / K
+// MOSS-5, Sections 5.1.1-5.1.3 / Theorems 6-10, for sampler l (1 = T-5, 2 = Path-5):
+//   p^(l)_i = 2 phi^(l)_i / Gamma^(l)   (Table 2)
+//   mix weights lambda^(l)_i: pooled (default) K_l p^(l)_i / sum_l K_l p^(l)_i, which
+//   turns the mix into (m^(1)_i + m^(2)_i) / (K_1 p^(1)_i + K_2 p^(2)_i); or the paper's
+//   inverse-variance weights with Var(eta^(l)_i) = eta_i / K_l (1/p^(l)_i - eta_i) taken at
+//   the pooled estimate.  Classes seen by one sampler only get weight 1 on it.
+//   Cov(eta_i, eta_j) = -eta_i eta_j sum_l lambda^(l)_i lambda^(l)_j / K_l (i != j)
+//   eta_2 = Lambda_4 - sum_{i in Omega_3*} phi^(3)_i eta_i,
+//   Var(eta_2) = sum_{i,j in Omega_3*} phi^(3)_i phi^(3)_j Cov(eta_i, eta_j)
+// The unknown counts inside the variance formulas are replaced by the estimates;
+// reported variances are clamped at zero.
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kPhi4[7] = {0, 1, 0, 4, 2, 6, 12};
+// Table 2, rows phi^(1) (forks), phi^(2) (4-paths), phi^(3) (4-stars); index 0 unused
+constexpr int kPhi5[3][22] = {
+    {0, 0, 0, 1, 1, 2, 0, 2, 2, 4, 4, 5, 4, 6, 10, 9, 12, 10, 20, 20, 36, 60},
+    {0, 1, 0, 0, 2, 2, 5, 1, 0, 4, 7, 2, 4, 6, 10, 6, 6, 14, 24, 18, 36, 60},
+    {0, 0, 1, 0, 0, 0, 0, 0, 1, 0, 0, 1, 1, 0, 1, 1, 2, 0, 1, 2, 3, 5},
+};
+
+double nonneg(double x) { return x > 0.0 ? x : 0.0; }
+
+void finals4(moss_result* r) {
+  const double K = (double)r->K[0];
+  const uint64_t G = r->gamma[0];
+  double p[7] = {};
+  double n[7] = {};
+  for (int i = 1; i <= 6; ++i) {
+    if (kPhi4[i] == 0 || G == 0) continue;
+    p[i] = 2.0 * kPhi4[i] / (double)G;
+    n[i] = (double)r->hits[0][i] / (K * p[i]);
+    r->estimate[i - 1] = n[i];
+    r->variance[i - 1] = nonneg(n[i] / K * (1.0 / p[i] - n[i]));
+  }
+  r->estimate[1] = (double)r->lambda - n[4] - 2.0 * n[5] - 4.0 * n[6];
+  if (G != 0) {
+    const double s = n[4] + 2.0 * n[5] + 4.0 * n[6];
+    r->variance[1] = nonneg((n[4] / p[4] + 4.0 * n[5] / p[5] + 16.0 * n[6] / p[6] - s * s) / K);
+  }
+}
+
+void finals5(moss_result* r) {
+  const double K[2] = {(double)r->K[0], (double)r->K[1]};
+  double lam[2][22] = {};
+  double eta[22] = {};
+  for (int i = 1; i <= 21; ++i) {
+    if (i == 2) continue;
+    double p[2];
+    for (int l = 0; l < 2; ++l)
+      p[l] = (kPhi5[l][i] > 0 && r->gamma[l] > 0) ? 2.0 * kPhi5[l][i] / (double)r->gamma[l] : 0.0;
+    const double denom = K[0] * p[0] + K[1] * p[1];
+    if (denom == 0.0) continue;
+    const double pooled = ((double)r->hits[0][i] + (double)r->hits[1][i]) / denom;
+    double l1 = K[0] * p[0] / denom, l2 = K[1] * p[1] / denom;
+    const double v1 = p[0] > 0.0 ? nonneg(pooled / K[0] * (1.0 / p[0] - pooled)) : 0.0;
+    const double v2 = p[1] > 0.0 ? nonneg(pooled / K[1] * (1.0 / p[1] - pooled)) : 0.0;
+    double est = pooled, var;
+    if ((r->flags & MOSS_MIX_PAPER) && p[0] > 0.0 && p[1] > 0.0 && v1 + v2 > 0.0) {
+      l1 = v2 / (v1 + v2);
+      l2 = v1 / (v1 + v2);
+      est = l1 * ((double)r->hits[0][i] / (K[0] * p[0])) + l2 * ((double)r->hits[1][i] / (K[1] * p[1]));
+      var = v1 * v2 / (v1 + v2);
+    } else {
+      var = l1 * l1 * v1 + l2 * l2 * v2;
+    }
+    lam[0][i] = l1;
+    lam[1][i] = l2;
+    eta[i] = est;
+    r->estimate[i - 1] = est;
+    r->variance[i - 1] = nonneg(var);
+  }
+  double sub = 0.0;
+  for (int i = 1; i <= 21; ++i)
+    if (i != 2 && kPhi5[2][i] > 0) sub += kPhi5[2][i] * eta[i];
+  r->estimate[1] = (double)r->lambda - sub;
+  double v = 0.0;
+  for (int i = 1; i <= 21; ++i) {
+    if (i == 2 || kPhi5[2][i] == 0) continue;
+    for (int j = 1; j <= 21; ++j) {
+      if (j == 2 || kPhi5[2][j] == 0) continue;
+      const double c = i == j ? r->variance[i - 1]
+                              : -eta[i] * eta[j] * (lam[0][i] * lam[0][j] / K[0] + lam[1][i] * lam[1][j] / K[1]);
+      v += (double)kPhi5[2][i] * kPhi5[2][j] * c;
+    }
+  }
+  r->variance[1] = nonneg(v);
+}
+
+}  // namespace
+
+extern "C" moss_status moss_finals(moss_result* r) {
+  if (!r) return MOSS_E_ARG;
+  std::memset(r->estimate, 0, sizeof(r->estimate));
+  std::memset(r->variance, 0, sizeof(r->variance));
+  if (r->k == 4) {
+    if (r->K[0] == 0) return MOSS_E_ARG;
+    r->n_motifs = 6;
+    finals4(r);
+    return MOSS_OK;
+  }
+  if (r->k == 5) {
+    if (r->K[0] == 0 || r->K[1] == 0) return MOSS_E_ARG;
+    r->n_motifs = 21;
+    finals5(r);
+    return MOSS_OK;
+  }
+  return MOSS_E_ARG;
+}

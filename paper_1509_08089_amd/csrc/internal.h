@@ -1,0 +1,100 @@
+// Library-internal declarations shared by the host sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+
+#include "kernels.h"
+#include "moss.h"
+
+struct moss_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int32_t max_degree = 0;
+  const int32_t* rp = nullptr;
+  const int32_t* col = nullptr;
+  int32_t* owned_rp = nullptr;  // set when the CSR was copied from the host
+  int32_t* owned_col = nullptr;
+  uint32_t flags = 0;
+
+  // sampling tables
+  uint32_t* acc_sigma = nullptr;    // nnz
+  uint64_t* acc_tau = nullptr;      // nnz
+  uint64_t* acc_node[3] = {};       // n each: Gamma (MOSS-4), Gamma^(1) (T-5), Gamma^(2) (Path-5)
+  uint32_t* guide[3] = {};          // 2^gbits + 1 each
+  int gbits = 1;
+  uint64_t total[3] = {};
+  uint64_t lambda3 = 0, lambda4 = 0;
+  uint32_t built = 0;               // MOSS_TABLES_* bits
+
+  // per-graph scratch
+  unsigned long long* d_hits = nullptr;  // 2 x 22
+  uint32_t* d_err = nullptr;             // error bits + max degree
+  unsigned long long* d_lambda = nullptr;
+  uint64_t* h_stage = nullptr;           // pinned host staging, 64 words
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  std::atomic<int> busy{0};
+  uint64_t csr_bytes = 0;
+  uint64_t table_bytes = 0;
+};
+
+namespace moss {
+
+// index of a sampler's node distribution / tables
+inline int sampler_slot(int sampler) { return sampler == kMoss4 ? 0 : sampler == kT5 ? 1 : 2; }
+
+moss_status status_of(hipError_t e);
+
+// Sets the device for the scope of the object and restores the previous one.
+class DeviceScope {
+ public:
+  explicit DeviceScope(int device);
+  ~DeviceScope();
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = -1;
+  bool ok_ = false;
+};
+
+// Per-device one-time set-up (classification tables in constant memory).
+moss_status ensure_device(int device);
+int device_cus(int device);
+
+// Classification tables (sample probe bits -> motif id), computed on the host.
+void class_luts(uint8_t lut4[8], uint8_t lut5t[64], uint8_t lut5p[64]);
+
+SamplerView sampler_view(const moss_graph* g, int sampler);
+moss_status build_tables(moss_graph* g, uint32_t mask);
+// Frees the tables of `mask` (waits for the graph's stream first).
+void free_graph_tables(moss_graph* g, uint32_t mask);
+// Device bytes that building `mask` would add to the graph.
+uint64_t table_bytes_needed(const moss_graph* g, uint32_t mask);
+
+// Launch shape of the plain sampling kernel for `nsamples` samples.
+void plain_launch_shape(int device, int sampler, uint64_t nsamples, int* grid, int* block);
+
+struct Tuning {
+  uint32_t tile_samples = 0;
+  uint32_t blocks_per_cu = 0;
+  uint32_t threads_per_block = 0;
+};
+Tuning current_tuning();
+
+// RAII claim on a graph for the duration of a call (MOSS_E_BUSY when taken).
+class GraphClaim {
+ public:
+  explicit GraphClaim(moss_graph* g);
+  ~GraphClaim();
+  bool ok() const { return ok_; }
+
+ private:
+  moss_graph* g_;
+  bool ok_;
+};
+
+}  // namespace moss

@@ -1,0 +1,83 @@
+// Host-side declarations of the HIP kernels' launchers (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace moss {
+
+// Sampler ids double as Philox key tags.
+constexpr int kMoss4 = 0x4;
+constexpr int kT5 = 0x51;
+constexpr int kPath5 = 0x52;
+
+// Error bits raised by the device-side checks.
+constexpr uint32_t kErrArg = 1u << 0;
+constexpr uint32_t kErrUnsorted = 1u << 1;
+constexpr uint32_t kErrSelfLoop = 1u << 2;
+constexpr uint32_t kErrDuplicate = 1u << 3;
+constexpr uint32_t kErrAsymmetric = 1u << 4;
+constexpr uint32_t kErrOverflow = 1u << 5;    // a row sum S_v needs more than 32 bits (all tables)
+constexpr uint32_t kErrOverflowK4 = 1u << 6;  // Gamma prefix or Lambda_3 exceeds 64 bits
+constexpr uint32_t kErrOverflowK5 = 1u << 7;  // a Gamma^(1)/Gamma^(2) value or prefix, or Lambda_4
+
+// What one sampler needs of one graph.
+struct SamplerView {
+  const int32_t* rp;          // row_ptr[n+1]
+  const int32_t* col;         // col[nnz], rows ascending
+  const uint64_t* acc_node;   // inclusive prefix of the node weights of this sampler
+  const uint32_t* guide;      // guide[0..2^gbits]: node-draw search windows
+  const uint32_t* acc_sigma;  // row-local inclusive prefix of d_x - 1
+  const uint64_t* acc_tau;    // row-local inclusive prefix of the tau weights (Path-5)
+  uint64_t total;             // sum of the node weights
+  int32_t n;
+  int32_t gbits;
+};
+
+// One unit of batched work: samples [k0, k1) of one sampler on one graph.
+struct Tile {
+  uint32_t view;     // index into the SamplerView array
+  uint32_t sampler;  // kMoss4 / kT5 / kPath5
+  uint32_t out;      // histogram slot (22 counters each)
+  uint32_t pad;
+  uint64_t seed;
+  uint64_t k0, k1;
+};
+
+hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], const uint8_t lut5p[64]);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
+
+hipError_t launch_check_rowptr(int32_t n, int64_t nnz, const int32_t* rp, uint32_t* err, hipStream_t s);
+hipError_t launch_check_cols(int32_t n, const int32_t* rp, const int32_t* col, bool full, uint32_t* err,
+                             int grid, hipStream_t s);
+
+// Per-row tables and node weights; any of the weight outputs may be null.
+hipError_t launch_row_tables(int32_t n, const int32_t* rp, const int32_t* col, uint32_t* acc_sigma,
+                             uint64_t* acc_tau, uint64_t* w_gamma, uint64_t* w_gamma1, uint64_t* w_gamma2,
+                             unsigned long long* lambdas, uint32_t* err, int grid, hipStream_t s);
+
+// In-place inclusive scan of u64[n]; `tmp` must hold scan_tmp_elems(n) u64; a wrap
+// sets `err_bit` in *err.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scan_inplace(uint64_t* data, int64_t n, uint64_t* tmp, uint32_t* err, uint32_t err_bit,
+                               hipStream_t s);
+
+hipError_t launch_guide(const uint64_t* acc, int32_t n, uint64_t total, int gbits, uint32_t* guide,
+                        hipStream_t s);
+
+// Plain sampling launch: samples [k0, k1) of one sampler, hits[22] accumulated.
+hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
+                         unsigned long long* hits, uint8_t* class_out, int grid, int block, hipStream_t s);
+
+hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed, const uint64_t* index,
+                               int64_t count, int32_t* nodes_out, uint8_t* class_out, hipStream_t s);
+
+// Batched persistent launch over a tile list resident in device memory.
+hipError_t launch_batch(const SamplerView* views, const Tile* tiles, const uint32_t* n_tiles,
+                        uint32_t* tile_counter, unsigned long long* bins, int grid, int block, hipStream_t s);
+
+// Registers/VGPR usage probe for occupancy decisions (max active blocks per CU).
+int sample_kernel_blocks_per_cu(int sampler, int block);
+
+}  // namespace moss

@@ -1,0 +1,354 @@
+// Estimation server: continuous batching over resident graphs.
+//
+// A worker thread repeats one scheduling iteration:
+//   1. admission: while a slot is free, take the oldest waiting request; make sure
+//      its graph's tables for its k are resident, evicting the tables of idle graphs
+//      (least recently used first) to stay within the memory budget; a request
+//      whose tables can never fit fails with MOSS_E_ADMISSION, one that must wait for
+//      running requests to finish stays queued;
+//   2. one batched launch runs the next chunk of samples of every admitted request
+//      (requests that arrived during the previous launch are in it);
+//   3. finished requests get their finals and wake their waiters.
+// Each request's samples keep their global indices, so its result does not depend on
+// how its work was chunked or what ran beside it.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "batch.h"
+
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Req {
+  uint64_t ticket = 0;
+  int32_t graph_id = 0;
+  int32_t k = 4;
+  uint64_t n = 0, seed = 0;
+  uint32_t flags = 0;
+  uint64_t K[2] = {0, 0};
+  uint64_t next[2] = {0, 0};
+  uint64_t hits[2][22] = {};
+  bool done = false, cancelled = false;
+  moss_status status = MOSS_OK;
+  moss_result result{};
+  Clock::time_point t_submit, t_done;
+};
+
+struct GraphEntry {
+  moss_graph* g = nullptr;
+  uint64_t last_use = 0;
+  int active = 0;
+};
+
+}  // namespace
+
+struct moss_server {
+  moss_server_config cfg{};
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread worker;
+  bool stop = false;
+  std::deque<std::shared_ptr<Req>> pending;
+  std::vector<std::shared_ptr<Req>> active;
+  std::unordered_map<uint64_t, std::shared_ptr<Req>> by_ticket;
+  std::vector<GraphEntry> graphs;
+  uint64_t next_ticket = 1;
+  uint64_t iterations = 0, completed = 0, samples_done = 0, evictions = 0;
+  std::vector<double> latencies_ms;
+  bool have_first = false;
+  Clock::time_point t_first, t_last;
+  std::unique_ptr<moss::BatchRunner> runner;
+
+  void finish(const std::shared_ptr<Req>& r, moss_status st) {
+    r->status = st;
+    r->done = true;
+    r->t_done = Clock::now();
+    if (st == MOSS_OK) {
+      ++completed;
+      samples_done += r->n;
+      latencies_ms.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+      t_last = r->t_done;
+    }
+  }
+
+  uint64_t resident_bytes() const {
+    uint64_t b = 0;
+    for (const GraphEntry& e : graphs) b += e.g->table_bytes;
+    return b;
+  }
+
+  // Makes room for `need` bytes by evicting idle graphs other than `keep`; returns
+  // whether the budget now allows it.  Called with mu held.
+  bool make_room(uint64_t need, const moss_graph* keep) {
+    const uint64_t budget = cfg.mem_budget_bytes;
+    if (!budget) return true;
+    while (resident_bytes() + need > budget) {
+      GraphEntry* victim = nullptr;
+      for (GraphEntry& e : graphs)
+        if (e.g != keep && e.active == 0 && e.g->built && (!victim || e.last_use < victim->last_use)) victim = &e;
+      if (!victim) return false;
+      moss::GraphClaim claim(victim->g);
+      if (!claim.ok()) return false;
+      moss::free_graph_tables(victim->g, MOSS_TABLES_K4 | MOSS_TABLES_K5);
+      ++evictions;
+    }
+    return true;
+  }
+
+  void loop();
+};
+
+void moss_server::loop() {
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
+    if (stop) {
+      for (auto& r : pending) finish(r, MOSS_E_CANCELLED);
+      for (auto& r : active) finish(r, MOSS_E_CANCELLED);
+      pending.clear();
+      active.clear();
+      cv_done.notify_all();
+      return;
+    }
+    // 1. admission
+    while (active.size() < cfg.max_slots && !pending.empty()) {
+      std::shared_ptr<Req> r = pending.front();
+      if (r->cancelled) {
+        pending.pop_front();
+        finish(r, MOSS_E_CANCELLED);
+        continue;
+      }
+      GraphEntry& ge = graphs[(size_t)r->graph_id];
+      const uint32_t mask = r->k == 4 ? MOSS_TABLES_K4 : MOSS_TABLES_K5;
+      if ((ge.g->built & mask) != mask) {
+        const uint64_t need = moss::table_bytes_needed(ge.g, mask);
+        if (cfg.mem_budget_bytes && need > cfg.mem_budget_bytes) {
+          pending.pop_front();
+          finish(r, MOSS_E_ADMISSION);
+          continue;
+        }
+        if (!make_room(need, ge.g)) break;  // wait for running requests to release memory
+        moss_status st;
+        {
+          moss::GraphClaim claim(ge.g);
+          st = claim.ok() ? moss::build_tables(ge.g, mask) : MOSS_E_BUSY;
+        }
+        if (st != MOSS_OK) {
+          pending.pop_front();
+          finish(r, st);
+          continue;
+        }
+      }
+      pending.pop_front();
+      moss_result hdr;
+      moss::result_header(ge.g, r->k, r->n, r->flags, &hdr);
+      r->K[0] = hdr.K[0];
+      r->K[1] = hdr.K[1];
+      ge.active += 1;
+      active.push_back(r);
+    }
+    cv_done.notify_all();
+    if (active.empty()) {
+      // nothing admissible now: wait for a new arrival or a stop
+      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      continue;
+    }
+    // 2. next chunk of every admitted request
+    std::vector<moss::WorkItem> work;
+    std::vector<std::shared_ptr<Req>> batch = active;
+    std::vector<uint64_t> upto(batch.size() * 2);
+    const uint64_t chunk = cfg.chunk_samples;
+    for (size_t i = 0; i < batch.size(); ++i) {
+      Req& r = *batch[i];
+      moss_graph* g = graphs[(size_t)r.graph_id].g;
+      const int samplers[2] = {r.k == 4 ? moss::kMoss4 : moss::kT5, moss::kPath5};
+      for (int s = 0; s < (r.k == 4 ? 1 : 2); ++s) {
+        const uint64_t b = std::min(r.K[s], r.next[s] + chunk);
+        upto[2 * i + s] = b;
+        if (b > r.next[s]) work.push_back({g, samplers[s], r.seed, r.next[s], b, (uint32_t)(2 * i + s)});
+      }
+    }
+    lk.unlock();
+    std::vector<uint64_t> bins(batch.size() * 2 * 22, 0);
+    moss_status st = work.empty() ? MOSS_OK
+                                  : runner->run(work, (uint32_t)(batch.size() * 2), bins.data(), nullptr, nullptr);
+    lk.lock();
+    ++iterations;
+    // 3. account and complete
+    std::vector<std::shared_ptr<Req>> still;
+    for (size_t i = 0; i < batch.size(); ++i) {
+      std::shared_ptr<Req>& r = batch[i];
+      GraphEntry& ge = graphs[(size_t)r->graph_id];
+      ge.last_use = iterations;
+      bool finished = false;
+      if (st != MOSS_OK) {
+        finish(r, st);
+        finished = true;
+      } else {
+        for (int s = 0; s < 2; ++s) {
+          for (int c = 0; c < 22; ++c) r->hits[s][c] += bins[(2 * i + s) * 22 + c];
+          if (s == 0 || r->k == 5) r->next[s] = upto[2 * i + s];
+        }
+        if (r->cancelled) {
+          finish(r, MOSS_E_CANCELLED);
+          finished = true;
+        } else if (r->next[0] >= r->K[0] && r->next[1] >= r->K[1]) {
+          moss_result res;
+          moss::result_header(ge.g, r->k, r->n, r->flags, &res);
+          std::memcpy(res.hits, r->hits, sizeof(res.hits));
+          moss_status fs = moss_finals(&res);
+          r->result = res;
+          finish(r, fs);
+          finished = true;
+        }
+      }
+      if (finished) ge.active -= 1;
+      else still.push_back(r);
+    }
+    active.swap(still);
+    cv_done.notify_all();
+  }
+}
+
+using namespace moss;
+
+extern "C" {
+
+moss_status moss_server_create(const moss_server_config* cfg, void* hip_stream, moss_server** out) {
+  (void)hip_stream;
+  if (!out) return MOSS_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MOSS_E_DEVICE;
+  moss_status st = ensure_device(dev);
+  if (st != MOSS_OK) return st;
+  moss_server* s = new (std::nothrow) moss_server();
+  if (!s) return MOSS_E_NOMEM;
+  if (cfg) s->cfg = *cfg;
+  if (!s->cfg.max_slots) s->cfg.max_slots = 256;
+  if (!s->cfg.chunk_samples) s->cfg.chunk_samples = 1ull << 22;
+  s->device = dev;
+  s->runner = std::make_unique<BatchRunner>(dev);
+  s->worker = std::thread([s] {
+    DeviceScope scope(s->device);
+    s->loop();
+  });
+  *out = s;
+  return MOSS_OK;
+}
+
+moss_status moss_server_add_graph(moss_server* s, moss_graph* g, int32_t* graph_id) {
+  if (!s || !g || !graph_id) return MOSS_E_ARG;
+  if (g->device != s->device) return MOSS_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  GraphEntry e;
+  e.g = g;
+  s->graphs.push_back(e);
+  *graph_id = (int32_t)s->graphs.size() - 1;
+  return MOSS_OK;
+}
+
+moss_status moss_server_submit(moss_server* s, int32_t graph_id, int32_t k, uint64_t n_samples, uint64_t seed,
+                               uint32_t flags, uint64_t* ticket) {
+  if (!s || !ticket || (k != 4 && k != 5) || (flags & ~MOSS_MIX_PAPER)) return MOSS_E_ARG;
+  if ((k == 4 && n_samples < 1) || (k == 5 && n_samples < 2)) return MOSS_E_ARG;
+  auto r = std::make_shared<Req>();
+  r->graph_id = graph_id;
+  r->k = k;
+  r->n = n_samples;
+  r->seed = seed;
+  r->flags = flags;
+  r->t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return MOSS_E_CANCELLED;
+    if (graph_id < 0 || (size_t)graph_id >= s->graphs.size()) return MOSS_E_ARG;
+    r->ticket = s->next_ticket++;
+    if (!s->have_first) {
+      s->have_first = true;
+      s->t_first = r->t_submit;
+    }
+    s->pending.push_back(r);
+    s->by_ticket[r->ticket] = r;
+    *ticket = r->ticket;
+  }
+  s->cv_work.notify_one();
+  return MOSS_OK;
+}
+
+moss_status moss_server_wait(moss_server* s, uint64_t ticket, int64_t timeout_ms, moss_result* out) {
+  if (!s || !out) return MOSS_E_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->by_ticket.find(ticket);
+  if (it == s->by_ticket.end()) return MOSS_E_ARG;
+  std::shared_ptr<Req> r = it->second;
+  if (timeout_ms < 0) {
+    s->cv_done.wait(lk, [&] { return r->done; });
+  } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [&] { return r->done; })) {
+    return MOSS_E_TIMEOUT;
+  }
+  s->by_ticket.erase(ticket);
+  if (r->status == MOSS_OK) *out = r->result;
+  return r->status;
+}
+
+moss_status moss_server_cancel(moss_server* s, uint64_t ticket) {
+  if (!s) return MOSS_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->by_ticket.find(ticket);
+  if (it == s->by_ticket.end()) return MOSS_E_ARG;
+  it->second->cancelled = true;
+  s->cv_work.notify_one();
+  return MOSS_OK;
+}
+
+moss_status moss_server_stats_get(moss_server* s, moss_server_stats* out) {
+  if (!s || !out) return MOSS_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  moss_server_stats r{};
+  r.completed = s->completed;
+  r.samples = s->samples_done;
+  r.iterations = s->iterations;
+  r.queued = s->pending.size();
+  r.active = s->active.size();
+  r.evictions = s->evictions;
+  r.table_bytes = s->resident_bytes();
+  if (!s->latencies_ms.empty()) {
+    std::vector<double> v = s->latencies_ms;
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) {
+      size_t i = (size_t)std::min<double>((double)v.size() - 1, std::max(0.0, f * (double)v.size() - 1e-9));
+      return v[i];
+    };
+    r.p50_ms = q(0.50);
+    r.p99_ms = q(0.99);
+    const double secs = std::chrono::duration<double>(s->t_last - s->t_first).count();
+    r.samples_per_s = secs > 0 ? (double)s->samples_done / secs : 0.0;
+  }
+  *out = r;
+  return MOSS_OK;
+}
+
+moss_status moss_server_destroy(moss_server* s) {
+  if (!s) return MOSS_E_ARG;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  s->runner->release();
+  delete s;
+  return MOSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+"""Writes the stored reference values under tests/golden/ using only the oracle and
+the seeded input generators.
+
+  line_counts.json  mean number of distinct 64-byte lines one sample reads (binary
+                    searches as in Section 4.1.3, no reuse between samples), per
+                    workload and sampler, over the first `samples` indices of seed 1;
+                    64 B times this is the roofline's algorithmic bytes per sample
+  exact_c1.json     exact 4- and 5-node CIS counts of the C1 graph (enumeration)
+
+Usage: python tests/golden/make_golden.py [--skip-exact5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import graphgen as gg  # noqa: E402
+import oracle  # noqa: E402
+
+SAMPLERS = {"moss4": oracle.MOSS4, "t5": oracle.T5, "path5": oracle.PATH5}
+
+
+def line_counts(samples: int) -> dict:
+    out = {}
+    for name in ("C1", "C2", "C3"):
+        cfg = gg.CONFIGS[name]
+        g = cfg["graph"].build()
+        og = oracle.Graph(g)
+        entry = {"graph_sha256": g.sha256(), "n": g.n, "m": g.m, "seed": cfg["seed"], "samples": samples}
+        for sname, sid in SAMPLERS.items():
+            if (cfg["k"] == 4) != (sname == "moss4"):
+                continue
+            entry[sname] = og.line_count(sid, cfg["seed"], 0, samples)
+        out[name] = entry
+        print(name, entry, flush=True)
+    return out
+
+
+def exact_c1(with5: bool) -> dict:
+    g = gg.config_graph("C1")
+    og = oracle.Graph(g)
+    t = time.time()
+    c4 = [int(x) for x in og.count_cis(4)[1:7]]
+    res = {"graph_sha256": g.sha256(), "n4": c4, "seconds4": round(time.time() - t, 1)}
+    if with5:
+        t = time.time()
+        res["eta5"] = [int(x) for x in og.count_cis(5)[1:22]]
+        res["seconds5"] = round(time.time() - t, 1)
+    res.update(og.totals())
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--samples", type=int, default=200_000)
+    ap.add_argument("--skip-exact5", action="store_true")
+    a = ap.parse_args()
+    with open(os.path.join(HERE, "line_counts.json"), "w") as f:
+        json.dump(line_counts(a.samples), f, indent=1)
+    with open(os.path.join(HERE, "exact_c1.json"), "w") as f:
+        json.dump(exact_c1(not a.skip_exact5), f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

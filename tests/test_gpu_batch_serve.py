@@ -1,0 +1,152 @@
+"""Batched persistent launches and the serving loop: each request's result must be
+identical to the same request run alone (moss_estimate), whatever else shares the
+launch, the tile size, the occupancy, the chunking or the arrival order."""
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import assert_result_matches
+from paper_1509_08089_amd import moss
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    gs = [gg.chung_lu(300, 1500, 2.4, 40, 31), gg.chung_lu(4000, 30000, 2.2, 500, 32),
+          gg.gnp(25, 0.3, 33), gg.star(12), gg.cycle(12), gg.chung_lu(20000, 150000, 2.1, 2000, 34)]
+    return gs, [moss.Graph(g) for g in gs]
+
+
+def _requests(handles, n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        k = 4 if rng.random() < 0.5 else 5
+        budget = int(10 ** rng.uniform(1, 6))
+        out.append((handles[int(rng.integers(0, len(handles)))].h, k, max(budget, 2), i + 1,
+                    int(rng.integers(0, 2))))
+    return out
+
+
+def _alone(req):
+    g, k, ns, seed, flags = req
+    return moss.moss_estimate(g, k, ns, seed, flags)
+
+
+def test_batch_equals_single_requests(graphs):
+    gs, handles = graphs
+    reqs = _requests(handles, 60, 1)
+    alone = [_alone(q) for q in reqs]
+    for rep in range(3):  # replays of the captured graph, with other work in between
+        got = moss.moss_estimate_batch(reqs)
+        for a, b in zip(alone, got):
+            np.testing.assert_array_equal(a.hits_np, b.hits_np)
+            np.testing.assert_array_equal(a.estimate_np, b.estimate_np)
+        _alone(reqs[rep])
+
+
+def test_batch_matches_oracle(graphs):
+    gs, handles = graphs
+    reqs = [(handles[1].h, 4, 123_457, 5, 0), (handles[1].h, 5, 98_765, 6, 0), (handles[0].h, 5, 4_001, 7, 1)]
+    got = moss.moss_estimate_batch(reqs)
+    for (h, k, ns, seed, flags), r, g in zip(reqs, got, [gs[1], gs[1], gs[0]]):
+        og = oracle.Graph(g)
+        lam = og.totals()["lambda3" if k == 4 else "lambda4"]
+        assert_result_matches(r, og.estimate(k, ns, seed, flags, threads=8), float(lam))
+
+
+@pytest.mark.parametrize("tile,bpc", [(256, 1), (4096, 2), (65536, 8), (1 << 20, 4)])
+def test_tile_size_and_occupancy_do_not_change_results(graphs, tile, bpc):
+    gs, handles = graphs
+    reqs = _requests(handles, 24, 2)
+    ref = [_alone(q) for q in reqs]
+    moss.moss_set_tuning(tile, bpc, 0)
+    try:
+        got = moss.moss_estimate_batch(reqs)
+    finally:
+        moss.moss_set_tuning(0, 0, 0)
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a.hits_np, b.hits_np)
+
+
+def test_autotune_keeps_results(graphs):
+    gs, handles = graphs
+    reqs = _requests(handles, 16, 3)
+    best, ms = moss.moss_autotune(reqs)
+    assert best.tile_samples > 0 and ms > 0
+    got = moss.moss_estimate_batch(reqs)
+    for q, b in zip(reqs, got):
+        np.testing.assert_array_equal(_alone(q).hits_np, b.hits_np)
+    moss.moss_set_tuning(0, 0, 0)
+
+
+def test_server_alone_and_in_mix(graphs):
+    gs, handles = graphs
+    reqs = _requests(handles, 80, 4)
+    srv = moss.moss_server_create(0, 16, 50_000)
+    try:
+        ids = [moss.moss_server_add_graph(srv, h.h) for h in handles]
+        gid = {h.h.value: i for i, h in enumerate(handles)}
+        tickets = []
+        for j, (g, k, ns, seed, flags) in enumerate(reqs):
+            tickets.append(moss.moss_server_submit(srv, ids[gid[g.value]], k, ns, seed, flags))
+            if j % 10 == 0:
+                time.sleep(0.002)  # arrivals while earlier requests run
+        for q, t in zip(reqs, tickets):
+            r = moss.moss_server_wait(srv, t, 60_000)
+            a = _alone(q)
+            np.testing.assert_array_equal(a.hits_np, r.hits_np)
+            np.testing.assert_array_equal(a.estimate_np, r.estimate_np)
+        st = moss.moss_server_stats_get(srv)
+        assert st.completed == len(reqs) and st.iterations >= 1 and st.p99_ms >= st.p50_ms > 0
+    finally:
+        moss.moss_server_destroy(srv)
+
+
+def test_server_memory_budget_evicts_and_rejects():
+    gs = [gg.chung_lu(3000, 20000, 2.2, 300, 40 + i) for i in range(4)]
+    hs = [moss.Graph(g) for g in gs]
+    need = 3000 * 8 + 20000 * 2 * 4 + (1 << 13) * 4 + 4096  # k=4 tables of one graph, with slack
+    srv = moss.moss_server_create(int(need * 1.5), 4, 10_000)
+    try:
+        ids = [moss.moss_server_add_graph(srv, h.h) for h in hs]
+        ts = [moss.moss_server_submit(srv, ids[i % 4], 4, 30_000, i + 1) for i in range(8)]
+        for i, t in enumerate(ts):
+            r = moss.moss_server_wait(srv, t, 60_000)
+            np.testing.assert_array_equal(r.hits_np, hs[i % 4].estimate(4, 30_000, i + 1).hits_np)
+            hs[i % 4].h  # keep alive
+        st = moss.moss_server_stats_get(srv)
+        assert st.evictions >= 1
+        # a request whose tables can never fit the budget is refused, not queued forever
+        big = moss.Graph(gg.chung_lu(50000, 400000, 2.2, 2000, 49))
+        bid = moss.moss_server_add_graph(srv, big.h)
+        t = moss.moss_server_submit(srv, bid, 5, 1000, 1)
+        with pytest.raises(moss.MossError) as e:
+            moss.moss_server_wait(srv, t, 60_000)
+        assert e.value.status == moss.MOSS_E_ADMISSION
+    finally:
+        moss.moss_server_destroy(srv)
+
+
+def test_server_cancel_and_timeout(graphs):
+    gs, handles = graphs
+    srv = moss.moss_server_create(0, 2, 1 << 16)
+    try:
+        gid = moss.moss_server_add_graph(srv, handles[5].h)
+        t_long = moss.moss_server_submit(srv, gid, 5, 2_000_000_000, 1)
+        with pytest.raises(moss.MossError) as e:
+            moss.moss_server_wait(srv, t_long, 1)
+        assert e.value.status == moss.MOSS_E_TIMEOUT
+        moss.moss_server_cancel(srv, t_long)
+        with pytest.raises(moss.MossError) as e:
+            moss.moss_server_wait(srv, t_long, 60_000)
+        assert e.value.status == moss.MOSS_E_CANCELLED
+        t = moss.moss_server_submit(srv, gid, 4, 1000, 2)
+        r = moss.moss_server_wait(srv, t, 60_000)
+        np.testing.assert_array_equal(r.hits_np, handles[5].estimate(4, 1000, 2).hits_np)
+    finally:
+        moss.moss_server_destroy(srv)

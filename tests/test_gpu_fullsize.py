@@ -1,0 +1,70 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark times.
+
+C2 (4-node, n=1e5, m=1e6, 1e7 samples) and C3 (5-node, n=1e6, m=1e7, 1e8 samples):
+the whole-run hit counts against the oracle's (threaded over sample ranges, which
+gives identical counts), per-sample classes at sampled indices against the oracle's
+sample-by-sample draws, and properties that hold at any size."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+from gpu_util import ORACLE_SAMPLER, assert_result_matches
+from paper_1509_08089_amd import moss
+
+pytestmark = pytest.mark.gpu
+
+
+def threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return 8
+
+
+def _sampled_classes(G, og, sampler, seed, K, n_check, rng):
+    cls = torch.zeros(K, dtype=torch.uint8, device="cuda")
+    hits = G.sample_range(sampler, seed, 0, K, cls)
+    counts = torch.bincount(cls.to(torch.int64), minlength=22).cpu().numpy()[:22]
+    np.testing.assert_array_equal(counts, hits)
+    idx = np.unique(np.concatenate([np.arange(2000), K - 1 - np.arange(2000),
+                                    rng.integers(0, K, size=n_check)]))
+    got = cls[torch.from_numpy(idx).cuda()].cpu().numpy()
+    osid = ORACLE_SAMPLER[sampler]
+    want = np.array([og.sample(osid, seed, int(k))[0] for k in idx], dtype=np.uint8)
+    np.testing.assert_array_equal(got, want)
+    return hits
+
+
+@pytest.mark.timeout(600)
+def test_c2_full_size():
+    cfg = gg.CONFIGS["C2"]
+    g = cfg["graph"].build()
+    G, og = moss.Graph(g), oracle.Graph(g)
+    K, seed = cfg["samples"], cfg["seed"]
+    r = G.estimate(4, K, seed)
+    o = og.estimate(4, K, seed, threads=threads())
+    assert_result_matches(r, o, float(og.totals()["lambda3"]))
+    assert int(r.hits_np[0].sum()) == K
+    hits = _sampled_classes(G, og, moss.MOSS_SAMPLER_MOSS4, seed, K, 20_000, np.random.Generator(np.random.PCG64(2)))
+    np.testing.assert_array_equal(hits, r.hits_np[0])
+
+
+@pytest.mark.timeout(900)
+def test_c3_full_size():
+    cfg = gg.CONFIGS["C3"]
+    g = cfg["graph"].build()
+    G, og = moss.Graph(g), oracle.Graph(g)
+    K, seed = cfg["samples"], cfg["seed"]
+    r = G.estimate(5, K, seed)
+    assert int(r.hits_np[0].sum()) == K // 2 and int(r.hits_np[1].sum()) == K // 2
+    o = og.estimate(5, K, seed, threads=threads())
+    assert_result_matches(r, o, float(og.totals()["lambda4"]))
+    rng = np.random.Generator(np.random.PCG64(3))
+    h1 = _sampled_classes(G, og, moss.MOSS_SAMPLER_T5, seed, K // 2, 5_000, rng)
+    h2 = _sampled_classes(G, og, moss.MOSS_SAMPLER_PATH5, seed, K // 2, 5_000, rng)
+    np.testing.assert_array_equal(h1, r.hits_np[0])
+    np.testing.assert_array_equal(h2, r.hits_np[1])

@@ -1,0 +1,191 @@
+"""GPU path against the oracle on the same seeded inputs (calls go through the C ABI).
+
+Integer outputs (tables, hit counts, per-sample classes and nodes) must be identical;
+FP64 finals within 1e-12 relative.  Sizes span several tiles of every kernel and
+ragged tails; degenerate graphs and error paths are covered."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+from gpu_util import ORACLE_SAMPLER, SAMPLERS, assert_result_matches
+from paper_1509_08089_amd import moss
+from pins import choose
+
+pytestmark = pytest.mark.gpu
+
+GRAPHS = [
+    gg.gnp(11, 0.45, 2), gg.gnp(40, 0.2, 5), gg.wheel(9), gg.complete(7), gg.complete_bipartite(4, 6),
+    gg.chung_lu(600, 4000, 2.3, 80, 11), gg.chung_lu(5000, 40000, 2.1, 900, 12),
+]
+
+
+def ids(g):
+    return g.name[:40]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return gg.config_graph("C1")
+
+
+@pytest.mark.parametrize("g", GRAPHS, ids=ids)
+def test_tables_match_oracle(g):
+    G = moss.Graph(g)
+    G.build_tables()
+    og = oracle.Graph(g)
+    info, t = G.info(), og.totals()
+    assert (info.gamma, info.gamma1, info.gamma2, info.lambda3, info.lambda4) == \
+        (t["gamma"], t["gamma1"], t["gamma2"], t["lambda3"], t["lambda4"])
+    assert info.max_degree == int(g.degrees().max())
+    for which in (moss.MOSS_TAB_ACC_GAMMA, moss.MOSS_TAB_ACC_GAMMA1, moss.MOSS_TAB_ACC_GAMMA2,
+                  moss.MOSS_TAB_ACC_SIGMA, moss.MOSS_TAB_ACC_TAU):
+        np.testing.assert_array_equal(G.table(which), og.table(which), err_msg=str(which))
+
+
+@pytest.mark.parametrize("g", GRAPHS, ids=ids)
+@pytest.mark.parametrize("K,seed", [(1, 3), (777, 1), (100_003, 2)])
+def test_moss4_matches_oracle(g, K, seed):
+    G, og = moss.Graph(g), oracle.Graph(g)
+    r = G.estimate(4, K, seed)
+    assert_result_matches(r, og.estimate(4, K, seed, threads=8), float(og.totals()["lambda3"]))
+
+
+@pytest.mark.parametrize("g", GRAPHS, ids=ids)
+@pytest.mark.parametrize("K,seed,mix", [(2, 3, 0), (1001, 1, 0), (200_001, 2, 0), (50_000, 4, 1)])
+def test_moss5_matches_oracle(g, K, seed, mix):
+    G, og = moss.Graph(g), oracle.Graph(g)
+    r = G.estimate(5, K, seed, mix)
+    assert_result_matches(r, og.estimate(5, K, seed, mix, threads=8), float(og.totals()["lambda4"]))
+
+
+def test_c1_config(c1):
+    """The small benchmark configuration: 4-node, 1e5 samples, seed 1 (and its 5-node twin)."""
+    G, og = moss.Graph(c1), oracle.Graph(c1)
+    assert_result_matches(G.estimate(4, 100_000, 1), og.estimate(4, 100_000, 1, threads=8),
+                          float(og.totals()["lambda3"]))
+    assert_result_matches(G.estimate(5, 100_000, 1), og.estimate(5, 100_000, 1, threads=8),
+                          float(og.totals()["lambda4"]))
+
+
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_per_sample_classes_and_ranges(c1, sampler):
+    G, og = moss.Graph(c1), oracle.Graph(c1)
+    k0, k1 = 1234, 1234 + 70_001
+    cls = torch.zeros(k1 - k0, dtype=torch.uint8, device="cuda")
+    hits = G.sample_range(sampler, 7, k0, k1, cls)
+    c = cls.cpu().numpy()
+    np.testing.assert_array_equal(np.bincount(c, minlength=22)[:22], hits)
+    osid = ORACLE_SAMPLER[sampler]
+    want = np.array([og.sample(osid, 7, k)[0] for k in range(k0, k1)], dtype=np.uint8)
+    np.testing.assert_array_equal(c, want)
+    np.testing.assert_array_equal(hits, og.run(osid, 7, k0, k1, 8))
+    # additivity over split ranges
+    a = G.sample_range(sampler, 7, k0, k0 + 33_333) + G.sample_range(sampler, 7, k0 + 33_333, k1)
+    np.testing.assert_array_equal(a, hits)
+
+
+@pytest.mark.parametrize("sampler", SAMPLERS)
+def test_sampled_nodes_match_oracle(c1, sampler):
+    G, og = moss.Graph(c1), oracle.Graph(c1)
+    idx = np.concatenate([np.arange(0, 300), np.array([2**40 + 5, 2**63 - 1, 2**64 - 1], dtype=np.uint64),
+                          np.random.Generator(np.random.PCG64(1)).integers(0, 2**62, 500, dtype=np.uint64)])
+    idx = idx.astype(np.uint64)
+    nodes, cls = G.sample_nodes(sampler, 11, idx)
+    osid = ORACLE_SAMPLER[sampler]
+    for i, k in enumerate(idx):
+        c, nd = og.sample(osid, 11, int(k))
+        assert int(cls[i]) == c
+        want = nd[:4] + ([-1] if sampler == moss.MOSS_SAMPLER_MOSS4 else nd[4:5])
+        assert nodes[i].tolist() == want, (int(k), nodes[i].tolist(), want)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 99])
+def test_zero_variance_closed_forms_on_gpu(seed):
+    K = 300_000
+    cases4 = [(gg.path(9), {1: 6}), (gg.cycle(9), {1: 9}), (gg.cycle(4), {3: 1}),
+              (gg.complete_bipartite(3, 4), {3: 18, 2: 16}), (gg.star(6), {2: 20})]
+    for g, want in cases4:
+        r = moss.Graph(g).estimate(4, K, seed)
+        for i in range(6):
+            assert abs(r.estimate[i] - want.get(i + 1, 0)) <= 1e-9 * max(1, want.get(i + 1, 0)), (g.name, i)
+            assert r.variance[i] <= 1e-9
+    cases5 = [(gg.cycle(9), {1: 9}), (gg.path(10), {1: 6}), (gg.cycle(5), {6: 1}), (gg.star(7), {2: choose(7, 4)})]
+    for g, want in cases5:
+        r = moss.Graph(g).estimate(5, K, seed)
+        for i in range(21):
+            assert abs(r.estimate[i] - want.get(i + 1, 0)) <= 1e-9 * max(1, want.get(i + 1, 0)), (g.name, i)
+
+
+def test_degenerate_graphs():
+    # no 3-paths: every sampler is empty, estimates are exact
+    r = moss.Graph(gg.star(5)).estimate(4, 10, 1)
+    assert int(r.hits_np.sum()) == 0 and r.estimate[1] == choose(5, 3)
+    # a single edge, an edgeless graph, isolated nodes
+    for g in (gg.from_edges(2, [(0, 1)]), gg.from_edges(5, []), gg.from_edges(1, [])):
+        for k in (4, 5):
+            r = moss.Graph(g).estimate(k, 10, 1)
+            assert int(r.hits_np.sum()) == 0 and not np.any(r.estimate_np)
+    # graph with many isolated nodes next to a dense part
+    g = gg.from_edges(1000, [(i, j) for i in range(990, 1000) for j in range(i + 1, 1000)])
+    og = oracle.Graph(g)
+    assert_result_matches(moss.Graph(g).estimate(5, 12345, 3), og.estimate(5, 12345, 3), og.totals()["lambda4"])
+    # smallest budgets and bad budgets
+    G = moss.Graph(gg.gnp(20, 0.3, 1))
+    with pytest.raises(moss.MossError):
+        G.estimate(4, 0, 1)
+    with pytest.raises(moss.MossError):
+        G.estimate(5, 1, 1)
+    with pytest.raises(moss.MossError):
+        G.estimate(3, 10, 1)
+
+
+def test_empty_graph_object():
+    h = moss.moss_graph_create(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), 0, 0)
+    r = moss.moss_estimate(h, 4, 5, 1)
+    assert r.estimate[1] == 0.0
+    moss.moss_graph_destroy(h)
+
+
+def test_host_copy_path_matches_device_path():
+    g = gg.chung_lu(3000, 20000, 2.2, 300, 21)
+    a = moss.Graph(g, device_tensors=False).estimate(5, 100_000, 5)
+    b = moss.Graph(g, device_tensors=True).estimate(5, 100_000, 5)
+    np.testing.assert_array_equal(a.hits_np, b.hits_np)
+
+
+def test_validation_errors_on_gpu():
+    good = gg.gnp(30, 0.3, 4)
+    moss.Graph(good)
+    rp, col = good.row_ptr, good.col
+
+    def bad(rp_, col_, status, flags=0):
+        with pytest.raises(moss.MossError) as e:
+            moss.moss_graph_create(len(rp_) - 1, len(col_), rp_, col_, flags, 0)
+        assert e.value.status == status, (moss.STATUS[e.value.status], moss.STATUS[status])
+
+    c = col.copy()
+    c[rp[3]], c[rp[3] + 1] = c[rp[3] + 1], c[rp[3]]
+    bad(rp, c, moss.MOSS_E_UNSORTED)
+    bad(np.array([0, 1, 2], np.int32), np.array([0, 0], np.int32), moss.MOSS_E_SELF_LOOP)
+    bad(np.array([0, 2, 4], np.int32), np.array([1, 1, 0, 0], np.int32), moss.MOSS_E_DUPLICATE)
+    bad(np.array([0, 1, 1], np.int32), np.array([1], np.int32), moss.MOSS_E_ASYMMETRIC)
+    bad(np.array([0, 1, 1], np.int32), np.array([5], np.int32), moss.MOSS_E_ARG)
+    bad(np.array([0, 2, 1], np.int32), np.array([1, 0], np.int32), moss.MOSS_E_ARG)
+    bad(np.array([1, 2, 2], np.int32), np.array([1, 0], np.int32), moss.MOSS_E_ARG)
+    # column range is checked even when the caller vouches for the CSR
+    bad(np.array([0, 1, 1], np.int32), np.array([7], np.int32), moss.MOSS_E_ARG, moss.MOSS_TRUST_CSR)
+
+
+def test_overflow_reported_per_table_set():
+    """Lambda_4 of K_{1,150000} exceeds 64 bits; Lambda_3 does not: the 4-node tables
+    build, the 5-node tables report overflow."""
+    G = moss.Graph(gg.star(150_000))
+    G.build_tables(moss.MOSS_TABLES_K4)
+    assert G.info().lambda3 == choose(150_000, 3)
+    with pytest.raises(moss.MossError) as e:
+        G.build_tables(moss.MOSS_TABLES_K5)
+    assert e.value.status == moss.MOSS_E_OVERFLOW
+    r = G.estimate(4, 1000, 1)
+    assert r.estimate[1] == float(choose(150_000, 3))

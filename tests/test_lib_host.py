@@ -1,0 +1,115 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and its
+host-side logic (classification tables, estimator finals) agrees with the oracle.
+No call here touches a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1509_08089_amd import moss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "moss.h")).read()
+    return sorted(set(re.findall(r"^(?:moss_status|const char \*)\s*(moss_\w+)\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = moss.lib()
+    decl = declared_symbols()
+    assert len(decl) >= 20
+    assert set(decl) == set(moss.EXPORTED)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    for code in moss.STATUS:
+        assert moss.moss_status_string(code)
+
+
+# node order v, u, w, r, t; pairs fixed by each sampler, then the probed pairs in bit order
+STRUCTURE = {
+    moss.MOSS_SAMPLER_MOSS4: (4, [(0, 1), (0, 2), (1, 3)], [(1, 2), (0, 3), (2, 3)]),
+    moss.MOSS_SAMPLER_T5: (5, [(0, 1), (0, 2), (0, 3), (1, 4)], [(1, 2), (1, 3), (2, 3), (0, 4), (2, 4), (3, 4)]),
+    moss.MOSS_SAMPLER_PATH5: (5, [(0, 1), (0, 2), (1, 3), (2, 4)], [(0, 3), (0, 4), (1, 2), (1, 4), (2, 3), (3, 4)]),
+}
+
+
+@pytest.mark.parametrize("sampler", list(STRUCTURE))
+def test_class_tables_match_oracle_classifier(sampler):
+    k, known, probes = STRUCTURE[sampler]
+    lut = moss.moss_class_lut(sampler)
+    assert len(lut) == 1 << len(probes)
+    for mask in range(1 << len(probes)):
+        adj = np.zeros((k, k), np.uint8)
+        for a, b in known:
+            adj[a, b] = adj[b, a] = 1
+        for i, (a, b) in enumerate(probes):
+            if mask >> i & 1:
+                adj[a, b] = adj[b, a] = 1
+        assert int(lut[mask]) == oracle.classify(k, adj), (sampler, mask)
+
+
+def _rel_close(a, b, scale, tol=1e-12):
+    return abs(a - b) <= tol * max(abs(a), abs(b), scale, 1e-300)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_finals4_match_oracle(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K = int(rng.integers(1, 10**9))
+    hits = rng.multinomial(K, rng.dirichlet(np.ones(7))).astype(np.uint64)
+    hits[2] = 0  # class 2 is never sampled by MOSS-4
+    K = int(hits.sum()) or 1
+    gamma = int(rng.integers(0, 2**62)) if seed % 4 else 0
+    lam = int(rng.integers(0, 2**60))
+    r = moss.moss_result()
+    r.k, r.K[0], r.gamma[0], r.lambda_ = 4, K, gamma, lam
+    for i in range(7):
+        r.hits[0][i] = int(hits[i])
+    moss.moss_finals(r)
+    est, var = oracle.finals4(K, hits, gamma, lam)
+    for i in range(6):
+        scale = float(lam) if i == 1 else 0.0
+        assert _rel_close(r.estimate[i], est[i], scale), (i, r.estimate[i], est[i])
+        assert _rel_close(r.variance[i], var[i], scale * scale / K if i == 1 else 0.0), (i, r.variance[i], var[i])
+
+
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("mix", [moss.MOSS_MIX_POOLED, moss.MOSS_MIX_PAPER])
+def test_finals5_match_oracle(seed, mix):
+    rng = np.random.Generator(np.random.PCG64(100 + seed))
+    K1 = int(rng.integers(1, 10**8))
+    K2 = K1 - int(rng.integers(0, 2)) or 1
+    h1 = rng.multinomial(K1, rng.dirichlet(np.ones(22) * 0.5)).astype(np.uint64)
+    h2 = rng.multinomial(K2, rng.dirichlet(np.ones(22) * 0.5)).astype(np.uint64)
+    g1 = int(rng.integers(0, 2**60)) if seed % 5 else 0
+    g2 = int(rng.integers(0, 2**60)) if seed % 7 else 0
+    lam = int(rng.integers(0, 2**62))
+    r = moss.moss_result()
+    r.k, r.flags, r.K[0], r.K[1], r.lambda_ = 5, mix, K1, K2, lam
+    r.gamma[0], r.gamma[1] = g1, g2
+    for i in range(22):
+        r.hits[0][i] = int(h1[i])
+        r.hits[1][i] = int(h2[i])
+    moss.moss_finals(r)
+    est, var, _ = oracle.finals5(K1, K2, h1, h2, g1, g2, lam, mix)
+    for i in range(21):
+        scale = float(lam) if i == 1 else 0.0
+        assert _rel_close(r.estimate[i], est[i], scale), (i, r.estimate[i], est[i])
+        assert _rel_close(r.variance[i], var[i], 0.0, 1e-11), (i, r.variance[i], var[i])
+
+
+def test_finals_reject_bad_arguments():
+    r = moss.moss_result()
+    r.k = 3
+    with pytest.raises(moss.MossError):
+        moss.moss_finals(r)
+    r.k, r.K[0] = 4, 0
+    with pytest.raises(moss.MossError):
+        moss.moss_finals(r)
