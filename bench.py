@@ -57,7 +57,20 @@ def parse():
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (3 times), to scale HBM counters")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes: int) -> int:
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reads_per_dispatch": nbytes, "writes_per_dispatch": nbytes}))
+    return 0
 
 
 def host_cores() -> int:
@@ -123,6 +136,9 @@ def main():
                                    "ranges with one histogram all-reduce, which is not built here",
                           "n_gpus": args.gpus}))
         return 2
+
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
 
     import numpy as np
     import torch

@@ -137,7 +137,10 @@ void free_tables(moss_graph* g, uint32_t mask) {
     g->total[1] = g->total[2] = 0;
   }
   g->built &= ~mask;
-  if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5))) dev_free(g->acc_sigma);
+  if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5))) {
+    dev_free(g->acc_sigma);
+    g->sigma_ready = false;
+  }
   g->table_bytes = moss::table_bytes_needed(g, 0);
 }
 
@@ -149,6 +152,10 @@ void destroy_graph(moss_graph* g) {
   free_tables(g, MOSS_TABLES_K4 | MOSS_TABLES_K5);
   dev_free(g->owned_rp);
   dev_free(g->owned_col);
+  dev_free(g->items);
+  dev_free(g->item_sum);
+  dev_free(g->scan_tmp);
+  dev_free(g->partials);
   dev_free(g->d_hits);
   dev_free(g->d_err);
   dev_free(g->d_lambda);
@@ -166,12 +173,6 @@ int validate_error_status(uint32_t bits) {
   if (bits & kErrAsymmetric) return MOSS_E_ASYMMETRIC;
   if (bits & kErrOverflow) return MOSS_E_OVERFLOW;
   return MOSS_OK;
-}
-
-int node_grid(int64_t n) {
-  // one wave per node, 4 waves per block
-  int64_t g = (n + 3) / 4;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 16));
 }
 
 // Scratch, events and the CSR checks shared by both creation paths.
@@ -194,7 +195,25 @@ moss_status finish_create(moss_graph* g) {
   uint32_t bits = ((uint32_t*)g->h_stage)[0];
   g->max_degree = (int32_t)((uint32_t*)g->h_stage)[1];
   if (bits) return (moss_status)validate_error_status(bits);
-  e = launch_check_cols(g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->d_err, node_grid(g->n), s);
+  // work items: every row cut into pieces of at most 256 entries
+  const int64_t items_ub = (int64_t)g->n + g->nnz / 256 + 1;
+  const int64_t tmp_elems = std::max(scan_tmp_elems(g->n), scan_tmp_elems(items_ub));
+  uint64_t* item_end = nullptr;
+  if ((st = dev_alloc(&g->items, (size_t)items_ub)) != MOSS_OK) return st;
+  if ((st = dev_alloc(&g->item_sum, (size_t)items_ub)) != MOSS_OK) return st;
+  if ((st = dev_alloc(&g->scan_tmp, (size_t)tmp_elems)) != MOSS_OK) return st;
+  if ((st = dev_alloc(&g->partials, 2 * (size_t)node_weight_blocks(g->n))) != MOSS_OK) return st;
+  if ((st = dev_alloc(&item_end, (size_t)g->n)) != MOSS_OK) return st;
+  e = launch_items(g->n, g->rp, item_end, g->items, g->scan_tmp, g->d_err, s);
+  g->h_stage[1] = 0;
+  if (e == hipSuccess && g->n > 0)
+    e = hipMemcpyAsync(g->h_stage + 1, item_end + (g->n - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dev_free(item_end);
+  if (e != hipSuccess) return status_of(e);
+  g->n_items = (int64_t)g->h_stage[1];
+  if (g->n_items > items_ub) return MOSS_E_ARG;
+  e = launch_check_items(g->n_items, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->d_err, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return status_of(e);
@@ -394,25 +413,28 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     if (st == MOSS_OK) st = dev_alloc(&g->guide[2], G);
     bytes += nnz * 8 + 2 * n * 8 + 2 * G * 4;
   }
-  uint64_t* tmp = nullptr;
-  if (st == MOSS_OK) st = dev_alloc(&tmp, (size_t)scan_tmp_elems((int64_t)n));
   if (st != MOSS_OK) {
-    dev_free(tmp);
     free_tables(g, need);
     return st;
   }
   hipStream_t s = g->stream;
   hipError_t e = launch_fill_u32(g->d_err, 0, 4, s);
   if (e == hipSuccess) e = launch_fill_u64((uint64_t*)g->d_lambda, 0, 2, s);
+  if (e == hipSuccess && !g->sigma_ready)
+    e = launch_row_prefix(false, g->n_items, g->items, g->rp, g->col, g->acc_sigma, nullptr, g->item_sum, g->scan_tmp,
+                          g->d_err, s);
+  if (e == hipSuccess && want5)
+    e = launch_row_prefix(true, g->n_items, g->items, g->rp, g->col, g->acc_sigma, g->acc_tau, g->item_sum,
+                          g->scan_tmp, g->d_err, s);
   if (e == hipSuccess)
-    e = launch_row_tables(g->n, g->rp, g->col, g->acc_sigma, want5 ? g->acc_tau : nullptr,
-                          want4 ? g->acc_node[0] : nullptr, want5 ? g->acc_node[1] : nullptr,
-                          want5 ? g->acc_node[2] : nullptr, g->d_lambda, g->d_err, node_grid(g->n), s);
+    e = launch_node_weights(g->n, g->rp, g->acc_sigma, want5 ? g->acc_tau : nullptr, want4 ? g->acc_node[0] : nullptr,
+                            want5 ? g->acc_node[1] : nullptr, want5 ? g->acc_node[2] : nullptr, g->partials,
+                            g->d_lambda, g->d_err, s);
   for (int slot = 0; slot < 3 && e == hipSuccess; ++slot) {
     const bool want = slot == 0 ? want4 : want5;
     if (want)
-      e = launch_scan_inplace(g->acc_node[slot], (int64_t)n, tmp, g->d_err, slot == 0 ? kErrOverflowK4 : kErrOverflowK5,
-                              s);
+      e = launch_scan_inplace(g->acc_node[slot], (int64_t)n, g->scan_tmp, g->d_err,
+                              slot == 0 ? kErrOverflowK4 : kErrOverflowK5, s);
   }
   // stage: [0] error bits, [1..3] totals, [4..5] Lambdas
   uint64_t* h = g->h_stage;
@@ -426,16 +448,15 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   if (e == hipSuccess) e = hipMemcpyAsync(h + 4, g->d_lambda, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
-    dev_free(tmp);
     free_tables(g, need);
     return status_of(e);
   }
   const uint32_t bits = (uint32_t)(h[0] & 0xFFFFFFFFu);
   if ((bits & kErrOverflow) || (want4 && (bits & kErrOverflowK4)) || (want5 && (bits & kErrOverflowK5))) {
-    dev_free(tmp);
     free_tables(g, need);
     return MOSS_E_OVERFLOW;
   }
+  g->sigma_ready = true;
   for (int slot = 0; slot < 3 && e == hipSuccess; ++slot) {
     const bool want = slot == 0 ? want4 : want5;
     if (!want) continue;
@@ -443,7 +464,6 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     if (g->total[slot] > 0) e = launch_guide(g->acc_node[slot], g->n, g->total[slot], g->gbits, g->guide[slot], s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(tmp);
   if (e != hipSuccess) {
     free_tables(g, need);
     return status_of(e);

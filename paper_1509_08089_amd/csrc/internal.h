@@ -30,6 +30,14 @@ struct moss_graph {
   uint64_t lambda3 = 0, lambda4 = 0;
   uint32_t built = 0;               // MOSS_TABLES_* bits
 
+  // work items of the O(|E|) kernels: rows cut into pieces of <= 256 entries
+  uint64_t* items = nullptr;             // n_items packed (row, piece)
+  uint64_t* item_sum = nullptr;          // n_items, per-piece totals / their scan
+  int64_t n_items = 0;
+  uint64_t* scan_tmp = nullptr;          // block sums of the scans
+  uint64_t* partials = nullptr;          // per-block Lambda partial sums
+  bool sigma_ready = false;
+
   // per-graph scratch
   unsigned long long* d_hits = nullptr;  // 2 x 22
   uint32_t* d_err = nullptr;             // error bits + max degree

@@ -49,13 +49,26 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 hipError_t launch_fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
 
 hipError_t launch_check_rowptr(int32_t n, int64_t nnz, const int32_t* rp, uint32_t* err, hipStream_t s);
-hipError_t launch_check_cols(int32_t n, const int32_t* rp, const int32_t* col, bool full, uint32_t* err,
-                             int grid, hipStream_t s);
+// Work items: rows cut into pieces of at most 256 entries.  item_end (n u64) receives
+// the inclusive prefix of the piece counts; items (at most n + nnz/256 + 1 u64) the
+// packed (row, piece) pairs; the item count is item_end[n-1].
+hipError_t launch_items(int32_t n, const int32_t* rp, uint64_t* item_end, uint64_t* items, uint64_t* tmp,
+                        uint32_t* err, hipStream_t s);
+hipError_t launch_check_items(int64_t n_items, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
+                              bool full, uint32_t* err, hipStream_t s);
 
-// Per-row tables and node weights; any of the weight outputs may be null.
-hipError_t launch_row_tables(int32_t n, const int32_t* rp, const int32_t* col, uint32_t* acc_sigma,
-                             uint64_t* acc_tau, uint64_t* w_gamma, uint64_t* w_gamma1, uint64_t* w_gamma2,
-                             unsigned long long* lambdas, uint32_t* err, int grid, hipStream_t s);
+// Row prefixes ACC_sigma (tau = false) or ACC_tau (tau = true, needs ACC_sigma);
+// item_sum holds n_items u64, tmp scan_tmp_elems(n_items) u64.
+hipError_t launch_row_prefix(bool tau, int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
+                             uint32_t* acc_sigma, uint64_t* acc_tau, uint64_t* item_sum, uint64_t* tmp, uint32_t* err,
+                             hipStream_t s);
+
+// Node weights (any output may be null) and Lambda_3, Lambda_4 into lambdas[0..1];
+// partials must hold 2 * node_weight_blocks(n) u64.
+int node_weight_blocks(int32_t n);
+hipError_t launch_node_weights(int32_t n, const int32_t* rp, const uint32_t* acc_sigma, const uint64_t* acc_tau,
+                               uint64_t* w_gamma, uint64_t* w_gamma1, uint64_t* w_gamma2, uint64_t* partials,
+                               unsigned long long* lambdas, uint32_t* err, hipStream_t s);
 
 // In-place inclusive scan of u64[n]; `tmp` must hold scan_tmp_elems(n) u64; a wrap
 // sets `err_bit` in *err.

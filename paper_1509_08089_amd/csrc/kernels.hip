@@ -15,6 +15,8 @@
 //
 // All counting is integer; a sample's outcome depends only on (graph, seed, sampler,
 // sample index), never on which lane, block or launch draws it.
+#include <algorithm>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -56,6 +58,15 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream
   return hipGetLastError();
 }
 
+__device__ __forceinline__ uint64_t add_wrap(uint64_t a, uint64_t b, bool& wrapped) {
+  const uint64_t z = a + b;
+  wrapped |= z < a;
+  return z;
+}
+
+hipError_t launch_scan_inplace(uint64_t* data, int64_t n, uint64_t* tmp, uint32_t* err, uint32_t err_bit,
+                               hipStream_t s);
+
 hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], const uint8_t lut5p[64]) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lut4), lut4, 8);
   if (e != hipSuccess) return e;
@@ -91,131 +102,301 @@ hipError_t launch_check_rowptr(int32_t n, int64_t nnz, const int32_t* rp, uint32
   return hipGetLastError();
 }
 
-// One wave per node: column range, self-loops, strict ascent (sorted, no repeats)
-// and symmetry (v must appear in the row of each of its neighbours).
-__global__ __launch_bounds__(256) void k_check_cols(int32_t n, const int32_t* __restrict__ rp,
-                                                    const int32_t* __restrict__ col, int full, uint32_t* err) {
+// ---------------------------------------------------------------------------------
+// Work items.  Every CSR row is cut into items of at most kItem consecutive entries
+// and each item is handled by one wave, so no wave walks a long row alone: the
+// costliest row (a hub with tens of thousands of neighbours) becomes many items
+// that run concurrently.  items[i] packs (row << 32 | piece index within the row).
+// Per-row quantities that span pieces are stitched with a scan over item totals.
+// ---------------------------------------------------------------------------------
+constexpr int32_t kItem = 256;
+
+__global__ void k_item_count(int32_t n, const int32_t* __restrict__ rp, uint64_t* __restrict__ cnt) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    cnt[v] = (uint64_t)((rp[v + 1] - rp[v] + kItem - 1) / kItem);
+}
+
+// item_end[v] = inclusive prefix of the piece counts
+__global__ void k_item_fill(int32_t n, const int32_t* __restrict__ rp, const uint64_t* __restrict__ item_end,
+                            uint64_t* __restrict__ items) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = (uint64_t)((rp[v + 1] - rp[v] + kItem - 1) / kItem);
+    const uint64_t first = item_end[v] - c;
+    for (uint64_t j = 0; j < c; ++j) items[first + j] = (uint64_t)v << 32 | j;
+  }
+}
+
+hipError_t launch_items(int32_t n, const int32_t* rp, uint64_t* item_end, uint64_t* items, uint64_t* tmp,
+                        uint32_t* err, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_item_count, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, item_end);
+  hipError_t e = launch_scan_inplace(item_end, n, tmp, err, kErrArg, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_item_fill, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, item_end, items);
+  return hipGetLastError();
+}
+
+static int item_grid(int64_t n_items) {
+  int64_t g = (n_items + 3) / 4;  // one wave per item, 4 waves per block
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+struct ItemRange {
+  int32_t v, r0, r1, e0, e1, piece;
+};
+
+__device__ __forceinline__ ItemRange item_range(const uint64_t* __restrict__ items, const int32_t* __restrict__ rp,
+                                                int64_t i) {
+  const uint64_t it = items[i];
+  ItemRange r;
+  r.v = (int32_t)(it >> 32);
+  r.piece = (int32_t)(it & 0xFFFFFFFFu);
+  r.r0 = rp[r.v];
+  r.r1 = rp[r.v + 1];
+  r.e0 = r.r0 + r.piece * kItem;
+  r.e1 = min(r.r1, r.e0 + kItem);
+  return r;
+}
+
+// Column range, self-loops, strict ascent (sorted, no repeats) and symmetry (v must
+// appear in the row of each of its neighbours).
+__global__ __launch_bounds__(256) void k_check_items(int64_t n_items, const uint64_t* __restrict__ items, int32_t n,
+                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                     int full, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   uint32_t bad = 0;
-  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nwaves) {
-    const int32_t r0 = rp[v], r1 = rp[v + 1];
-    for (int32_t e = r0 + lane; e < r1; e += 64) {
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
       const int32_t c = col[e];
       if (c < 0 || c >= n) {
         bad |= kErrArg;
         continue;
       }
       if (!full) continue;
-      if (c == (int32_t)v) bad |= kErrSelfLoop;
-      if (e > r0) {
+      if (c == it.v) bad |= kErrSelfLoop;
+      if (e > it.r0) {
         const int32_t p = col[e - 1];
         if (p == c) bad |= kErrDuplicate;
         else if (p > c) bad |= kErrUnsorted;
       }
       const int32_t rc = rp[c];
-      if (!row_has(col, rc, rp[c + 1] - rc, (int32_t)v)) bad |= kErrAsymmetric;
+      if (!row_has(col, rc, rp[c + 1] - rc, it.v)) bad |= kErrAsymmetric;
     }
   }
   bad = wave_or(bad);
   if (lane == 0 && bad) atomicOr(err, bad);
 }
 
-hipError_t launch_check_cols(int32_t n, const int32_t* rp, const int32_t* col, bool full, uint32_t* err, int grid,
-                             hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_check_cols, dim3(grid), dim3(256), 0, s, n, rp, col, full ? 1 : 0, err);
+hipError_t launch_check_items(int64_t n_items, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
+                              bool full, uint32_t* err, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_items, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, n, rp, col,
+                     full ? 1 : 0, err);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
-// Per-row tables and node weights, one wave per node.
-//   ACC_sigma[e] = sum of (d_x - 1) over the row up to e          (Section 4.1.3)
-//   ACC_tau[e]   = sum of (d_x - 1)(S_v - (d_x - 1)) up to e      (Section 5.1.2, tau)
-//   Gamma_v = (d_v - 1) S_v,  Gamma^(1)_v = (d_v - 1)(d_v - 2) S_v,
-//   Gamma^(2)_v = S_v^2 - Q_v  with S_v = sum (d_x - 1), Q_v = sum (d_x - 1)^2
-//   Lambda_3 += C(d_v, 3), Lambda_4 += C(d_v, 4)                  (Table 1)
-// S_v must fit 32 bits (ACC_sigma is u32); then Gamma_v, Gamma^(2)_v and every
-// ACC_tau entry fit 64 bits and only Gamma^(1)_v and the Lambdas need checks.
+// Row prefixes (Section 4.1.3 ACC_sigma = ACC_mu of Section 5.1.5; the tau prefix of
+// Section 5.1.2), in three steps per table:
+//   local  each item scans its own entries and writes its total to item_sum
+//   scan   inclusive scan of item_sum (in place)
+//   fix    every later piece of a row adds the totals of the row's earlier pieces
+// ACC_sigma entries are (d_x - 1) of the neighbours; ACC_tau entries are
+// (d_x - 1)(S_v - (d_x - 1)) with S_v the row total of ACC_sigma.
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_row_tables(int32_t n, const int32_t* __restrict__ rp,
-                                                    const int32_t* __restrict__ col, uint32_t* __restrict__ acc_sigma,
-                                                    uint64_t* __restrict__ acc_tau, uint64_t* __restrict__ w_gamma,
-                                                    uint64_t* __restrict__ w_gamma1, uint64_t* __restrict__ w_gamma2,
-                                                    unsigned long long* __restrict__ lambdas, uint32_t* err) {
+template <bool TAU>
+__global__ __launch_bounds__(256) void k_prefix_local(int64_t n_items, const uint64_t* __restrict__ items,
+                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                      uint32_t* __restrict__ acc_sigma, uint64_t* __restrict__ acc_tau,
+                                                      uint64_t* __restrict__ item_sum) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  bool over = false, over4 = false, over5 = false;
-  uint64_t l3 = 0, l4 = 0;
-  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nwaves) {
-    const int32_t r0 = rp[v], r1 = rp[v + 1];
-    uint64_t S = 0, q = 0;
-    for (int32_t e0 = r0; e0 < r1; e0 += 64) {
+  bool wrapped = false;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    uint64_t S = 0;
+    if (TAU) S = acc_sigma[it.r1 - 1];
+    uint64_t carry = 0;
+    for (int32_t e0 = it.e0; e0 < it.e1; e0 += 64) {
       const int32_t e = e0 + lane;
       uint64_t x = 0;
-      if (e < r1) {
-        const int32_t c = col[e];
-        x = (uint64_t)(rp[c + 1] - rp[c] - 1);
-      }
-      q += x * x;
-      const uint64_t s = wave_inclusive_scan(x, over) + S;
-      if (e < r1) acc_sigma[e] = (uint32_t)s;
-      S = __shfl(s, 63, 64);
-    }
-    over |= S > 0xFFFFFFFFull;
-    const uint64_t Q = wave_sum(q);
-    if (acc_tau) {
-      uint64_t T = 0;
-      for (int32_t e0 = r0; e0 < r1; e0 += 64) {
-        const int32_t e = e0 + lane;
-        uint64_t t = 0;
-        if (e < r1) {
+      if (e < it.e1) {
+        if (TAU) {
+          const uint64_t dx = (uint64_t)acc_sigma[e] - (e > it.r0 ? (uint64_t)acc_sigma[e - 1] : 0ull);
+          x = dx * (S - dx);
+        } else {
           const int32_t c = col[e];
-          const uint64_t x = (uint64_t)(rp[c + 1] - rp[c] - 1);
-          t = x * (S - x);
+          x = (uint64_t)(rp[c + 1] - rp[c] - 1);
         }
-        const uint64_t s = wave_inclusive_scan(t, over) + T;
-        if (e < r1) acc_tau[e] = s;
-        T = __shfl(s, 63, 64);
       }
+      const uint64_t s = wave_inclusive_scan(x, wrapped) + carry;
+      if (e < it.e1) {
+        if (TAU) acc_tau[e] = s;
+        else acc_sigma[e] = (uint32_t)s;
+      }
+      carry = __shfl(s, 63, 64);
     }
-    const uint64_t d = (uint64_t)(r1 - r0);
-    const uint64_t dd = d >= 2 ? (d - 1) * (d - 2) : 0;
-    over5 |= __umul64hi(dd, S) != 0;
-    if (lane == 0) {
-      if (w_gamma) w_gamma[v] = d >= 1 ? (d - 1) * S : 0;
-      if (w_gamma1) w_gamma1[v] = dd * S;
-      if (w_gamma2) w_gamma2[v] = S * S - Q;
-      const uint64_t c3 = choose3(d, over4), c4 = choose4(d, over5);
-      uint64_t z = l3 + c3;
-      over4 |= z < l3;
-      l3 = z;
-      z = l4 + c4;
-      over5 |= z < l4;
-      l4 = z;
-    }
+    if (lane == 0) item_sum[i] = carry;
   }
-  if (lane == 0 && lambdas) {
-    if (l3) {
-      const unsigned long long old = atomicAdd(&lambdas[0], (unsigned long long)l3);
-      over4 |= old + l3 < old;
-    }
-    if (l4) {
-      const unsigned long long old = atomicAdd(&lambdas[1], (unsigned long long)l4);
-      over5 |= old + l4 < old;
-    }
-  }
-  const uint32_t bits = (__ballot(over) != 0 ? kErrOverflow : 0u) | (__ballot(over4) != 0 ? kErrOverflowK4 : 0u) |
-                        (__ballot(over5) != 0 ? kErrOverflowK5 : 0u);
-  if (bits && lane == 0) atomicOr(err, bits);
+  (void)wrapped;  // row totals are checked in the fix step
 }
 
-hipError_t launch_row_tables(int32_t n, const int32_t* rp, const int32_t* col, uint32_t* acc_sigma, uint64_t* acc_tau,
-                             uint64_t* w_gamma, uint64_t* w_gamma1, uint64_t* w_gamma2, unsigned long long* lambdas,
-                             uint32_t* err, int grid, hipStream_t s) {
+template <bool TAU>
+__global__ __launch_bounds__(256) void k_prefix_fix(int64_t n_items, const uint64_t* __restrict__ items,
+                                                    const int32_t* __restrict__ rp,
+                                                    const uint64_t* __restrict__ item_incl, uint32_t* __restrict__ acc_sigma,
+                                                    uint64_t* __restrict__ acc_tau, uint32_t* err) {
+  const int lane = lane_id();
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  bool over = false;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    const int64_t first = i - it.piece;  // the row's first item
+    const uint64_t before_row = first > 0 ? item_incl[first - 1] : 0;
+    if (it.e1 == it.r1 && !TAU) {
+      // last piece: the row total S_v must fit the 32-bit ACC_sigma
+      over |= item_incl[i] - before_row > 0xFFFFFFFFull;
+    }
+    if (it.piece == 0) continue;
+    const uint64_t off = item_incl[i - 1] - before_row;
+    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
+      if (TAU) acc_tau[e] += off;
+      else acc_sigma[e] += (uint32_t)off;
+    }
+  }
+  if (__ballot(over) != 0 && lane == 0) atomicOr(err, kErrOverflow);
+}
+
+hipError_t launch_row_prefix(bool tau, int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
+                             uint32_t* acc_sigma, uint64_t* acc_tau, uint64_t* item_sum, uint64_t* tmp, uint32_t* err,
+                             hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const dim3 grid(item_grid(n_items)), block(256);
+  if (tau) hipLaunchKernelGGL(k_prefix_local<true>, grid, block, 0, s, n_items, items, rp, col, acc_sigma, acc_tau, item_sum);
+  else hipLaunchKernelGGL(k_prefix_local<false>, grid, block, 0, s, n_items, items, rp, col, acc_sigma, acc_tau, item_sum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the sum of every row's tau total is Gamma^(2): a wrap there is a 5-node overflow
+  e = launch_scan_inplace(item_sum, n_items, tmp, err, tau ? kErrOverflowK5 : kErrOverflow, s);
+  if (e != hipSuccess) return e;
+  if (tau) hipLaunchKernelGGL(k_prefix_fix<true>, grid, block, 0, s, n_items, items, rp, item_sum, acc_sigma, acc_tau, err);
+  else hipLaunchKernelGGL(k_prefix_fix<false>, grid, block, 0, s, n_items, items, rp, item_sum, acc_sigma, acc_tau, err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Node weights, one thread per node, from the finished row prefixes:
+//   S_v = ACC_sigma at the row end;  Gamma_v = (d_v - 1) S_v  (Section 4.1.1)
+//   Gamma^(1)_v = (d_v - 1)(d_v - 2) S_v                      (Section 5.1.1)
+//   Gamma^(2)_v = ACC_tau at the row end = S_v^2 - sum (d_x - 1)^2 (Section 5.1.2)
+//   Lambda_3 = sum C(d_v, 3), Lambda_4 = sum C(d_v, 4)        (Table 1)
+// The Lambdas are reduced per block into `partials` (2 per block) and finished by
+// k_lambda_final, so no two blocks update the same word.
+// ---------------------------------------------------------------------------------
+constexpr int kWeightThreads = 256;
+
+__global__ __launch_bounds__(256) void k_node_weights(int32_t n, const int32_t* __restrict__ rp,
+                                                      const uint32_t* __restrict__ acc_sigma,
+                                                      const uint64_t* __restrict__ acc_tau, uint64_t* __restrict__ w_gamma,
+                                                      uint64_t* __restrict__ w_gamma1, uint64_t* __restrict__ w_gamma2,
+                                                      uint64_t* __restrict__ partials, uint32_t* err) {
+  __shared__ uint64_t red[2][kWeightThreads / 64];
+  __shared__ uint32_t red_bits;
+  bool over4 = false, over5 = false;
+  uint64_t l3 = 0, l4 = 0;
+  if (threadIdx.x == 0) red_bits = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r0 = rp[v], r1 = rp[v + 1];
+    const uint64_t d = (uint64_t)(r1 - r0);
+    const uint64_t S = d > 0 ? (uint64_t)acc_sigma[r1 - 1] : 0;
+    if (w_gamma) w_gamma[v] = d >= 1 ? (d - 1) * S : 0;
+    if (w_gamma1) {
+      const uint64_t dd = d >= 2 ? (d - 1) * (d - 2) : 0;
+      over5 |= __umul64hi(dd, S) != 0;
+      w_gamma1[v] = dd * S;
+    }
+    if (w_gamma2) w_gamma2[v] = d > 0 ? acc_tau[r1 - 1] : 0;
+    l3 = add_wrap(l3, choose3(d, over4), over4);
+    l4 = add_wrap(l4, choose4(d, over5), over5);
+  }
+  // block reduction of (l3, l4)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    l3 = add_wrap(l3, __shfl_xor(l3, off, 64), over4);
+    l4 = add_wrap(l4, __shfl_xor(l4, off, 64), over5);
+  }
+  // (every lane of a wave now holds the wave total)
+  const int wave = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    red[0][wave] = l3;
+    red[1][wave] = l4;
+  }
+  __syncthreads();
+  const uint32_t bits = (__ballot(over4) != 0 ? kErrOverflowK4 : 0u) | (__ballot(over5) != 0 ? kErrOverflowK5 : 0u);
+  if (bits && lane_id() == 0) atomicOr(&red_bits, bits);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool o4 = false, o5 = false;
+    uint64_t a = 0, b = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a = add_wrap(a, red[0][w], o4);
+      b = add_wrap(b, red[1][w], o5);
+    }
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = b;
+    const uint32_t all = red_bits | (o4 ? kErrOverflowK4 : 0u) | (o5 ? kErrOverflowK5 : 0u);
+    if (all) atomicOr(err, all);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lambda_final(const uint64_t* __restrict__ partials, int nblocks,
+                                                      unsigned long long* __restrict__ lambdas, uint32_t* err) {
+  __shared__ uint64_t red[2][4];
+  bool o4 = false, o5 = false;
+  uint64_t a = 0, b = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) {
+    a = add_wrap(a, partials[2 * i], o4);
+    b = add_wrap(b, partials[2 * i + 1], o5);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a = add_wrap(a, __shfl_xor(a, off, 64), o4);
+    b = add_wrap(b, __shfl_xor(b, off, 64), o5);
+  }
+  if (lane_id() == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  const uint32_t bits = (__ballot(o4) != 0 ? kErrOverflowK4 : 0u) | (__ballot(o5) != 0 ? kErrOverflowK5 : 0u);
+  if (bits && lane_id() == 0) atomicOr(err, bits);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool p4 = false, p5 = false;
+    uint64_t x = 0, y = 0;
+    for (int w = 0; w < 4; ++w) {
+      x = add_wrap(x, red[0][w], p4);
+      y = add_wrap(y, red[1][w], p5);
+    }
+    lambdas[0] = x;
+    lambdas[1] = y;
+    if (p4 || p5) atomicOr(err, (p4 ? kErrOverflowK4 : 0u) | (p5 ? kErrOverflowK5 : 0u));
+  }
+}
+
+int node_weight_blocks(int32_t n) { return std::max(1, std::min(2048, (int)((n + 255) / 256))); }
+
+hipError_t launch_node_weights(int32_t n, const int32_t* rp, const uint32_t* acc_sigma, const uint64_t* acc_tau,
+                               uint64_t* w_gamma, uint64_t* w_gamma1, uint64_t* w_gamma2, uint64_t* partials,
+                               unsigned long long* lambdas, uint32_t* err, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_tables, dim3(grid), dim3(256), 0, s, n, rp, col, acc_sigma, acc_tau, w_gamma, w_gamma1,
-                     w_gamma2, lambdas, err);
+  const int nb = node_weight_blocks(n);
+  hipLaunchKernelGGL(k_node_weights, dim3(nb), dim3(kWeightThreads), 0, s, n, rp, acc_sigma, acc_tau, w_gamma,
+                     w_gamma1, w_gamma2, partials, err);
+  hipLaunchKernelGGL(k_lambda_final, dim3(1), dim3(256), 0, s, partials, nb, lambdas, err);
   return hipGetLastError();
 }
 
@@ -227,11 +408,6 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int64_t kScanTile = kScanThreads * kScanItems;
 
-__device__ __forceinline__ uint64_t add_wrap(uint64_t a, uint64_t b, bool& wrapped) {
-  const uint64_t z = a + b;
-  wrapped |= z < a;
-  return z;
-}
 
 // Scans one tile in place (inclusive or exclusive), starting from `offset`; returns
 // the tile total.  Must be called by all 256 threads.
