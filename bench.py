@@ -100,6 +100,17 @@ def measured_traffic(kernel: str, workload: str):
     return float(b.group(1))
 
 
+def exact_counts(workload: str, sha: str, k: int):
+    """Stored exact motif counts of the workload's graph (tests/golden), if any."""
+    p = os.path.join(ROOT, "tests", "golden", f"exact_{workload.lower()}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("graph_sha256") != sha:
+        return None
+    return d.get("n4") if k == 4 else d.get("eta5")
+
+
 def cpu_baseline(csr, cfg, seconds: float):
     import oracle
     cores = host_cores()
@@ -210,6 +221,10 @@ def main():
         "estimates": [float(x) for x in r0.estimate_np],
         "stderr_rel": [float(math.sqrt(v) / e) if e > 0 else None for v, e in zip(r0.variance_np, r0.estimate_np)],
     }
+    exact = exact_counts(args.workload, csr.sha256(), k)
+    if exact is not None:
+        line["exact"] = exact
+        line["rel_error"] = [abs(e - x) / x if x else None for e, x in zip(line["estimates"], exact)]
     if args.batched:
         line["batched"] = run_batched(moss, gg)
     if args.serve:
@@ -226,8 +241,8 @@ def run_batched(moss, gg):
     import numpy as np
     import torch
     specs, reqs = gg.batch_workload()
-    log(f"[bench] batched: generating {len(specs)} graphs")
-    graphs = [moss.Graph(s.build()) for s in specs]
+    log(f"[bench] batched: generating {len(specs)} graphs on the device")
+    graphs = [moss.Graph.from_device(*s.build_device()) for s in specs]
     torch.cuda.synchronize()
     q = [(graphs[r.graph].h, r.k, r.samples, r.seed, 0) for r in reqs]
     total = sum(r.samples for r in reqs)
@@ -257,8 +272,8 @@ def run_batched(moss, gg):
 def run_serving(moss, gg, n_requests):
     import torch
     specs, reqs = gg.serving_workload(n_requests=n_requests)
-    log(f"[bench] serving: generating {len(specs)} graphs")
-    graphs = [moss.Graph(s.build()) for s in specs]
+    log(f"[bench] serving: generating {len(specs)} graphs on the device")
+    graphs = [moss.Graph.from_device(*s.build_device()) for s in specs]
     torch.cuda.synchronize()
     srv = moss.moss_server_create(0, 256, 1 << 22)
     try:

@@ -35,6 +35,11 @@ class GraphSpec:
         return chung_lu(self.n, self.m, self.beta, self.dmax, self.seed,
                         name=f"CL(n={self.n},m={self.m},beta={self.beta},dmax={self.dmax},seed={self.seed})")
 
+    def build_device(self, device="cuda"):
+        """(row_ptr, col) int32 tensors generated on the device (see chung_lu_device)."""
+        from .chung_lu_device import chung_lu_device
+        return chung_lu_device(self.n, self.m, self.beta, self.dmax, self.seed, device)
+
 
 CONFIGS = {
     "C1": dict(graph=GraphSpec(2_000, 10_000, 2.5, 200, 1), k=4, samples=100_000, seed=1),

@@ -75,6 +75,7 @@ def lib():
             L.orc_estimate.argtypes = [P, ctypes.c_int, u64, u64, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(_Result)]
             L.orc_count_cis.argtypes = [P, ctypes.c_int, P]
+            L.orc_count4_exact.argtypes = [P, P]
             L.orc_line_count.argtypes = [P, ctypes.c_int, u64, u64, u64, ctypes.POINTER(ctypes.c_double)]
             _lib = L
         return _lib
@@ -138,8 +139,11 @@ class Graph:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().orc_free(h)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.orc_free(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     def totals(self) -> dict:
@@ -185,6 +189,13 @@ class Graph:
         st = lib().orc_count_cis(self._h, k, _ptr(out))
         if st != OK:
             raise OracleError(st, "orc_count_cis")
+        return out
+
+    def count4_exact(self) -> np.ndarray:
+        out = np.zeros(7, np.uint64)
+        st = lib().orc_count4_exact(self._h, _ptr(out))
+        if st != OK:
+            raise OracleError(st, "orc_count4_exact")
         return out
 
     def line_count(self, sampler: int, seed: int, k0: int, k1: int) -> float:

@@ -775,6 +775,107 @@ int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]) {
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Exact 4-node counts through non-induced patterns.  With N_P4, N_star, N_C4, */
+/* N_paw, N_diamond, N_K4 the numbers of (not necessarily induced) copies, and */
+/* c[j][i] the number of copies of pattern j inside motif M_i^(4):             */
+/*   N_P4 = n1 + 4n3 + 2n4 + 6n5 + 12n6   (the phi^(1) row of Section 4.1.2)   */
+/*   N_star = n2 + n4 + 2n5 + 4n6         (the phi^(2) row, Eq. n2)            */
+/*   N_C4 = n3 + n5 + 3n6,  N_paw = n4 + 4n5 + 12n6,  N_diamond = n5 + 6n6,     */
+/*   N_K4 = n6;                                                                */
+/* the system is triangular and solved from n6 up.  The pattern counts use    */
+/* t_e (triangles on edge e): T = sum t_e / 3, N_P4 = Gamma/2 - 3T,           */
+/* N_paw = sum_v T_v (d_v - 2), N_diamond = sum_e C(t_e, 2), N_C4 = half of    */
+/* sum over node pairs of C(common neighbours, 2), N_K4 by listing the common */
+/* neighbours of each edge.                                                   */
+/* ------------------------------------------------------------------------ */
+static int64_t row_find(const orc_graph *g, int32_t a, int32_t b) {
+  int64_t lo = g->rp[a], hi = g->rp[a + 1];
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (g->col[mid] == b) return mid;
+    if (g->col[mid] < b) lo = mid + 1; else hi = mid;
+  }
+  return -1;
+}
+
+int orc_count4_exact(const orc_graph *g, uint64_t counts[7]) {
+  if (!g || !counts) return ORC_E_ARG;
+  memset(counts, 0, 7 * sizeof(uint64_t));
+  int32_t n = g->n;
+  uint64_t *te = (uint64_t *)calloc((size_t)g->nnz + 1, sizeof(uint64_t)); /* per CSR entry */
+  uint32_t *cnt = (uint32_t *)calloc((size_t)n + 1, sizeof(uint32_t));
+  int32_t *touched = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  int32_t *common = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  if (!te || !cnt || !touched || !common) { free(te); free(cnt); free(touched); free(common); return ORC_E_NOMEM; }
+  u128 tri3 = 0, diamonds = 0, paws = 0, c4 = 0, k4 = 0;
+  /* triangles per edge: common neighbours of v and u (v < u) by merging the sorted rows */
+  for (int32_t v = 0; v < n; ++v) {
+    for (int64_t e = g->rp[v]; e < g->rp[v + 1]; ++e) {
+      int32_t u = g->col[e];
+      if (u <= v) continue;
+      int64_t i = g->rp[v], j = g->rp[u];
+      int nc = 0;
+      while (i < g->rp[v + 1] && j < g->rp[u + 1]) {
+        if (g->col[i] == g->col[j]) { common[nc++] = g->col[i]; ++i; ++j; }
+        else if (g->col[i] < g->col[j]) ++i; else ++j;
+      }
+      te[e] = (uint64_t)nc;
+      te[row_find(g, u, v)] = (uint64_t)nc;
+      tri3 += (u128)nc;
+      diamonds += (u128)nc * (u128)(nc > 0 ? nc - 1 : 0) / 2;
+      /* 4-cliques {v, u, x, y} with u < x < y counted once at their two smallest members */
+      for (int a = 0; a < nc; ++a) {
+        if (common[a] <= u) continue;
+        for (int b = a + 1; b < nc; ++b)
+          if (row_find(g, common[a], common[b]) >= 0) ++k4;
+      }
+    }
+  }
+  /* paws: triangles at v times the d_v - 2 other neighbours */
+  for (int32_t v = 0; v < n; ++v) {
+    u128 tv2 = 0; /* 2 T_v = sum over v's edges of t_e */
+    for (int64_t e = g->rp[v]; e < g->rp[v + 1]; ++e) tv2 += te[e];
+    int64_t dv = g->rp[v + 1] - g->rp[v];
+    if (dv >= 2) paws += (tv2 / 2) * (u128)(dv - 2);
+  }
+  /* 4-cycles: for each a, count 2-paths a - x - b to every b > a */
+  for (int32_t a = 0; a < n; ++a) {
+    int nt = 0;
+    for (int64_t e = g->rp[a]; e < g->rp[a + 1]; ++e) {
+      int32_t x = g->col[e];
+      for (int64_t f = g->rp[x]; f < g->rp[x + 1]; ++f) {
+        int32_t b = g->col[f];
+        if (b <= a) continue;
+        if (cnt[b]++ == 0) touched[nt++] = b;
+      }
+    }
+    for (int i = 0; i < nt; ++i) {
+      uint64_t c = cnt[touched[i]];
+      c4 += (u128)c * (c - 1) / 2;
+      cnt[touched[i]] = 0;
+    }
+  }
+  c4 /= 2; /* each 4-cycle has two diagonals */
+  free(te); free(cnt); free(touched); free(common);
+  u128 T = tri3 / 3;
+  u128 p4 = (u128)g->tot.gamma / 2 - 3 * T;
+  u128 star = g->tot.lambda3;
+  /* triangular solve; every count is non-negative in exact arithmetic */
+  u128 n6 = k4;
+  u128 n5 = diamonds - 6 * n6;
+  u128 n4 = paws - 4 * n5 - 12 * n6;
+  u128 n3 = c4 - n5 - 3 * n6;
+  u128 n2 = star - n4 - 2 * n5 - 4 * n6;
+  u128 n1 = p4 - 4 * n3 - 2 * n4 - 6 * n5 - 12 * n6;
+  u128 res[7] = {0, n1, n2, n3, n4, n5, n6};
+  for (int i = 1; i <= 6; ++i) {
+    if (!fits(res[i])) return ORC_E_OVERFLOW;
+    counts[i] = (uint64_t)res[i];
+  }
+  return ORC_OK;
+}
+
 int orc_line_count(const orc_graph *g, int sampler, uint64_t seed, uint64_t k0, uint64_t k1,
                    double *mean_lines) {
   if (!g || !mean_lines || k1 <= k0) return ORC_E_ARG;

@@ -101,6 +101,12 @@ int orc_estimate(const orc_graph *g, int k, uint64_t n_samples, uint64_t seed, i
 /* exact counts of k-node connected induced subgraphs per class (ESU enumeration) */
 int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]);
 
+/* exact counts n_1..n_6 (counts[1..6]) from non-induced pattern counts: 3-paths, 3-stars,
+   4-cycles, triangles with a pendant, diamonds and 4-cliques, converted with the matrix of
+   how many copies of each pattern every motif contains.  Same result as orc_count_cis(4)
+   but feasible on graphs with millions of edges. */
+int orc_count4_exact(const orc_graph *g, uint64_t counts[7]);
+
 /* mean number of distinct 64-byte lines one sample reads when every search is a
    plain binary search and nothing is reused between samples; arrays are taken to
    start on 64-byte boundaries with the widths of the sampling tables */

@@ -6,6 +6,8 @@ the seeded input generators.
                     workload and sampler, over the first `samples` indices of seed 1;
                     64 B times this is the roofline's algorithmic bytes per sample
   exact_c1.json     exact 4- and 5-node CIS counts of the C1 graph (enumeration)
+  exact_c2.json     exact 4-node counts of the C2 graph (non-induced patterns converted
+                    through the containment matrix; enumeration is infeasible there)
 
 Usage: python tests/golden/make_golden.py [--skip-exact5]
 """
@@ -57,15 +59,29 @@ def exact_c1(with5: bool) -> dict:
     return res
 
 
+def exact_c2() -> dict:
+    g = gg.config_graph("C2")
+    og = oracle.Graph(g)
+    t = time.time()
+    n4 = [int(x) for x in og.count4_exact()[1:7]]
+    return {"graph_sha256": g.sha256(), "n4": n4, "seconds": round(time.time() - t, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=200_000)
     ap.add_argument("--skip-exact5", action="store_true")
+    ap.add_argument("--only", choices=["lines", "c1", "c2"], default=None)
     a = ap.parse_args()
-    with open(os.path.join(HERE, "line_counts.json"), "w") as f:
-        json.dump(line_counts(a.samples), f, indent=1)
-    with open(os.path.join(HERE, "exact_c1.json"), "w") as f:
-        json.dump(exact_c1(not a.skip_exact5), f, indent=1)
+    if a.only in (None, "lines"):
+        with open(os.path.join(HERE, "line_counts.json"), "w") as f:
+            json.dump(line_counts(a.samples), f, indent=1)
+    if a.only in (None, "c1"):
+        with open(os.path.join(HERE, "exact_c1.json"), "w") as f:
+            json.dump(exact_c1(not a.skip_exact5), f, indent=1)
+    if a.only in (None, "c2"):
+        with open(os.path.join(HERE, "exact_c2.json"), "w") as f:
+            json.dump(exact_c2(), f, indent=1)
 
 
 if __name__ == "__main__":

@@ -163,3 +163,20 @@ def test_overflow_is_reported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.Graph(gg.star(150_000))
     assert e.value.status == oracle.E_OVERFLOW
+
+
+@pytest.mark.parametrize("g", TINY + [gg.chung_lu(300, 2000, 2.2, 60, 7), gg.complete(9), gg.wheel(12)],
+                         ids=lambda g: g.name)
+def test_pattern_conversion_counts_match_enumeration(g):
+    """The non-induced-pattern route to n_1..n_6 agrees with ESU enumeration."""
+    og = oracle.Graph(g)
+    np.testing.assert_array_equal(og.count4_exact()[1:7], og.count_cis(4)[1:7])
+
+
+def test_pattern_conversion_on_c1():
+    g = gg.config_graph("C1")
+    og = oracle.Graph(g)
+    import json, os
+    want = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_c1.json")))
+    assert want["graph_sha256"] == g.sha256()
+    assert og.count4_exact()[1:7].tolist() == want["n4"]
