@@ -58,6 +58,11 @@ moss_status ensure_device(int device) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
     return MOSS_E_DEVICE;
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess && pool) {
+    uint64_t keep = ~0ull;  // keep freed blocks for reuse instead of returning them at each sync
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   g_dev_cus[device] = cus;
   g_dev_ready[device] = 1;
   return MOSS_OK;
@@ -77,6 +82,11 @@ SamplerView sampler_view(const moss_graph* g, int sampler) {
   v.guide = g->guide[s];
   v.acc_sigma = g->acc_sigma;
   v.acc_tau = g->acc_tau;
+  v.rec = g->rec;
+  v.sig_guide = g->sig_guide;
+  v.tau_guide = g->tau_guide;
+  v.edge_slots = g->edge_slots;
+  v.edge_bits = g->edge_bits;
   v.total = g->total[s];
   v.n = g->n;
   v.gbits = g->gbits;
@@ -103,11 +113,14 @@ using namespace moss;
 
 namespace {
 
+// Device memory is stream-ordered (hipMallocAsync on the graph's stream from the
+// device's default pool, which keeps freed blocks for reuse), so building and
+// dropping tables costs no device-wide synchronisation.
 template <typename T>
-moss_status dev_alloc(T** p, size_t count) {
+moss_status dev_alloc(hipStream_t s, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  hipError_t e = hipMallocAsync((void**)p, count * sizeof(T), s);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
@@ -117,28 +130,55 @@ moss_status dev_alloc(T** p, size_t count) {
 }
 
 template <typename T>
-void dev_free(T*& p) {
-  if (p) (void)hipFree((void*)p);
+void dev_free(hipStream_t s, T*& p) {
+  if (p) (void)hipFreeAsync((void*)p, s);
   p = nullptr;
+}
+
+// Small pinned host buffers for results and flags, reused across graphs.
+std::mutex g_pin_mu;
+std::vector<uint64_t*> g_pin_free;
+constexpr size_t kPinWords = 64;
+
+uint64_t* pinned_chunk() {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  if (g_pin_free.empty()) {
+    uint64_t* slab = nullptr;
+    if (hipHostMalloc((void**)&slab, 64 * kPinWords * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    for (int i = 0; i < 64; ++i) g_pin_free.push_back(slab + i * kPinWords);
+  }
+  uint64_t* p = g_pin_free.back();
+  g_pin_free.pop_back();
+  return p;
+}
+
+void pinned_release(uint64_t* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(p);
 }
 
 void free_tables(moss_graph* g, uint32_t mask) {
   if (mask & MOSS_TABLES_K4) {
-    dev_free(g->acc_node[0]);
-    dev_free(g->guide[0]);
+    dev_free(g->stream, g->acc_node[0]);
+    dev_free(g->stream, g->guide[0]);
     g->total[0] = 0;
   }
   if (mask & MOSS_TABLES_K5) {
-    dev_free(g->acc_node[1]);
-    dev_free(g->acc_node[2]);
-    dev_free(g->guide[1]);
-    dev_free(g->guide[2]);
-    dev_free(g->acc_tau);
+    dev_free(g->stream, g->acc_node[1]);
+    dev_free(g->stream, g->acc_node[2]);
+    dev_free(g->stream, g->guide[1]);
+    dev_free(g->stream, g->guide[2]);
+    dev_free(g->stream, g->acc_tau);
+    dev_free(g->stream, g->tau_guide);
     g->total[1] = g->total[2] = 0;
   }
   g->built &= ~mask;
   if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5))) {
-    dev_free(g->acc_sigma);
+    dev_free(g->stream, g->acc_sigma);
+    dev_free(g->stream, g->sig_guide);
+    dev_free(g->stream, g->edge_slots);
     g->sigma_ready = false;
   }
   g->table_bytes = moss::table_bytes_needed(g, 0);
@@ -147,19 +187,21 @@ void free_tables(moss_graph* g, uint32_t mask) {
 void destroy_graph(moss_graph* g) {
   if (!g) return;
   DeviceScope scope(g->device);
-  if (g->stream) (void)hipStreamSynchronize(g->stream);
-  else (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(g->stream);
   free_tables(g, MOSS_TABLES_K4 | MOSS_TABLES_K5);
-  dev_free(g->owned_rp);
-  dev_free(g->owned_col);
-  dev_free(g->items);
-  dev_free(g->item_sum);
-  dev_free(g->scan_tmp);
-  dev_free(g->partials);
-  dev_free(g->d_hits);
-  dev_free(g->d_err);
-  dev_free(g->d_lambda);
-  if (g->h_stage) (void)hipHostFree(g->h_stage);
+  dev_free(g->stream, g->owned_rp);
+  dev_free(g->stream, g->owned_col);
+  dev_free(g->stream, g->items);
+  dev_free(g->stream, g->item_sum);
+  dev_free(g->stream, g->scan_tmp);
+  dev_free(g->stream, g->partials);
+  dev_free(g->stream, g->rec);
+  dev_free(g->stream, g->d_hits);
+  dev_free(g->stream, g->d_err);
+  dev_free(g->stream, g->d_lambda);
+  dev_free(g->stream, g->d_meta);
+  pinned_release(g->h_stage);
+  g->h_stage = nullptr;
   if (g->ev0) (void)hipEventDestroy(g->ev0);
   if (g->ev1) (void)hipEventDestroy(g->ev1);
   delete g;
@@ -178,13 +220,11 @@ int validate_error_status(uint32_t bits) {
 // Scratch, events and the CSR checks shared by both creation paths.
 moss_status finish_create(moss_graph* g) {
   moss_status st;
-  if ((st = dev_alloc(&g->d_hits, 2 * 22)) != MOSS_OK) return st;
-  if ((st = dev_alloc(&g->d_err, 4)) != MOSS_OK) return st;
-  if ((st = dev_alloc(&g->d_lambda, 2)) != MOSS_OK) return st;
-  if (hipHostMalloc((void**)&g->h_stage, 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
-    g->h_stage = nullptr;
-    return MOSS_E_NOMEM;
-  }
+  if ((st = dev_alloc(g->stream, &g->d_hits, 2 * 22)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->d_err, 4)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->d_lambda, 2)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->d_meta, 2)) != MOSS_OK) return st;
+  if (!(g->h_stage = pinned_chunk())) return MOSS_E_NOMEM;
   if (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess) return MOSS_E_DEVICE;
   hipStream_t s = g->stream;
   hipError_t e = launch_fill_u32(g->d_err, 0, 4, s);
@@ -199,24 +239,33 @@ moss_status finish_create(moss_graph* g) {
   const int64_t items_ub = (int64_t)g->n + g->nnz / 256 + 1;
   const int64_t tmp_elems = std::max(scan_tmp_elems(g->n), scan_tmp_elems(items_ub));
   uint64_t* item_end = nullptr;
-  if ((st = dev_alloc(&g->items, (size_t)items_ub)) != MOSS_OK) return st;
-  if ((st = dev_alloc(&g->item_sum, (size_t)items_ub)) != MOSS_OK) return st;
-  if ((st = dev_alloc(&g->scan_tmp, (size_t)tmp_elems)) != MOSS_OK) return st;
-  if ((st = dev_alloc(&g->partials, 2 * (size_t)node_weight_blocks(g->n))) != MOSS_OK) return st;
-  if ((st = dev_alloc(&item_end, (size_t)g->n)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->items, (size_t)items_ub)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->item_sum, (size_t)items_ub)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->scan_tmp, (size_t)tmp_elems)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->partials, 2 * (size_t)node_weight_blocks(g->n))) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &g->rec, (size_t)g->n)) != MOSS_OK) return st;
+  if ((st = dev_alloc(g->stream, &item_end, (size_t)g->n)) != MOSS_OK) return st;
   e = launch_items(g->n, g->rp, item_end, g->items, g->scan_tmp, g->d_err, s);
-  g->h_stage[1] = 0;
+  if (e == hipSuccess) e = launch_fill_u64(g->d_meta, 0, 2, s);
   if (e == hipSuccess && g->n > 0)
-    e = hipMemcpyAsync(g->h_stage + 1, item_end + (g->n - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(g->d_meta, item_end + (g->n - 1), sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+  // row-guide layout (depends on degrees only), then the records' row start, degree, offset
+  if (e == hipSuccess) e = launch_row_guide_sizes(g->n, g->rp, item_end, s);
+  if (e == hipSuccess) e = launch_scan_inplace(item_end, g->n, g->scan_tmp, g->d_err, kErrArg, s);
+  if (e == hipSuccess) e = launch_records(g->n, g->rp, nullptr, item_end, g->rec, s);
+  if (e == hipSuccess && g->n > 0)
+    e = hipMemcpyAsync(g->d_meta + 1, item_end + (g->n - 1), sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = launch_check_items(items_ub, g->d_meta, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR),
+                           g->d_err, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage + 1, g->d_meta, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  dev_free(g->stream, item_end);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  dev_free(item_end);
   if (e != hipSuccess) return status_of(e);
   g->n_items = (int64_t)g->h_stage[1];
+  g->row_guide_len = (int64_t)g->h_stage[2];
   if (g->n_items > items_ub) return MOSS_E_ARG;
-  e = launch_check_items(g->n_items, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->d_err, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return status_of(e);
   bits = ((uint32_t*)g->h_stage)[0];
   return (moss_status)validate_error_status(bits);
 }
@@ -274,8 +323,8 @@ moss_status moss_graph_create(int32_t n, int64_t nnz, const int32_t* row_ptr, co
   moss_status st = create_common(n, nnz, flags, hip_stream, out, &g);
   if (st != MOSS_OK) return st;
   DeviceScope scope(g->device);
-  st = dev_alloc(&g->owned_rp, (size_t)n + 1);
-  if (st == MOSS_OK) st = dev_alloc(&g->owned_col, (size_t)nnz);
+  st = dev_alloc(g->stream, &g->owned_rp, (size_t)n + 1);
+  if (st == MOSS_OK) st = dev_alloc(g->stream, &g->owned_col, (size_t)nnz);
   if (st == MOSS_OK) {
     hipError_t e = hipMemcpyAsync(g->owned_rp, row_ptr, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
                                   g->stream);
@@ -397,20 +446,24 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   moss_status st = MOSS_OK;
   uint64_t bytes = 0;
   if (!g->acc_sigma) {
-    st = dev_alloc(&g->acc_sigma, nnz);
+    st = dev_alloc(g->stream, &g->acc_sigma, nnz);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->sig_guide, (size_t)g->row_guide_len);
+    g->edge_bits = edge_hash_bits(g->nnz / 2);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->edge_slots, (size_t)1 << g->edge_bits);
     bytes += nnz * 4;
   }
   if (st == MOSS_OK && want4) {
-    st = dev_alloc(&g->acc_node[0], n);
-    if (st == MOSS_OK) st = dev_alloc(&g->guide[0], G);
+    st = dev_alloc(g->stream, &g->acc_node[0], n);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->guide[0], G);
     bytes += n * 8 + G * 4;
   }
   if (st == MOSS_OK && want5) {
-    st = dev_alloc(&g->acc_tau, nnz);
-    if (st == MOSS_OK) st = dev_alloc(&g->acc_node[1], n);
-    if (st == MOSS_OK) st = dev_alloc(&g->acc_node[2], n);
-    if (st == MOSS_OK) st = dev_alloc(&g->guide[1], G);
-    if (st == MOSS_OK) st = dev_alloc(&g->guide[2], G);
+    st = dev_alloc(g->stream, &g->acc_tau, nnz);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->tau_guide, (size_t)g->row_guide_len);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->acc_node[1], n);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->acc_node[2], n);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->guide[1], G);
+    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->guide[2], G);
     bytes += nnz * 8 + 2 * n * 8 + 2 * G * 4;
   }
   if (st != MOSS_OK) {
@@ -420,12 +473,21 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   hipStream_t s = g->stream;
   hipError_t e = launch_fill_u32(g->d_err, 0, 4, s);
   if (e == hipSuccess) e = launch_fill_u64((uint64_t*)g->d_lambda, 0, 2, s);
-  if (e == hipSuccess && !g->sigma_ready)
+  if (e == hipSuccess && !g->sigma_ready) {
     e = launch_row_prefix(false, g->n_items, g->items, g->rp, g->col, g->acc_sigma, nullptr, g->item_sum, g->scan_tmp,
                           g->d_err, s);
-  if (e == hipSuccess && want5)
+    if (e == hipSuccess) e = launch_records(g->n, g->rp, g->acc_sigma, nullptr, g->rec, s);
+    if (e == hipSuccess)
+      e = launch_row_guides(false, g->n_items, g->items, g->rp, g->rec, g->acc_sigma, nullptr, g->sig_guide, s);
+    if (e == hipSuccess)
+      e = launch_edge_hash(g->n_items, g->items, g->rp, g->col, g->edge_slots, g->edge_bits, g->d_err, s);
+  }
+  if (e == hipSuccess && want5) {
     e = launch_row_prefix(true, g->n_items, g->items, g->rp, g->col, g->acc_sigma, g->acc_tau, g->item_sum,
                           g->scan_tmp, g->d_err, s);
+    if (e == hipSuccess)
+      e = launch_row_guides(true, g->n_items, g->items, g->rp, g->rec, nullptr, g->acc_tau, g->tau_guide, s);
+  }
   if (e == hipSuccess)
     e = launch_node_weights(g->n, g->rp, g->acc_sigma, want5 ? g->acc_tau : nullptr, want4 ? g->acc_node[0] : nullptr,
                             want5 ? g->acc_node[1] : nullptr, want5 ? g->acc_node[2] : nullptr, g->partials,
@@ -435,6 +497,10 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     if (want)
       e = launch_scan_inplace(g->acc_node[slot], (int64_t)n, g->scan_tmp, g->d_err,
                               slot == 0 ? kErrOverflowK4 : kErrOverflowK5, s);
+  }
+  for (int slot = 0; slot < 3 && e == hipSuccess; ++slot) {
+    const bool want = slot == 0 ? want4 : want5;
+    if (want) e = launch_guide(g->acc_node[slot], g->n, g->gbits, g->guide[slot], s);
   }
   // stage: [0] error bits, [1..3] totals, [4..5] Lambdas
   uint64_t* h = g->h_stage;
@@ -457,16 +523,9 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     return MOSS_E_OVERFLOW;
   }
   g->sigma_ready = true;
-  for (int slot = 0; slot < 3 && e == hipSuccess; ++slot) {
+  for (int slot = 0; slot < 3; ++slot) {
     const bool want = slot == 0 ? want4 : want5;
-    if (!want) continue;
-    g->total[slot] = h[1 + slot];
-    if (g->total[slot] > 0) e = launch_guide(g->acc_node[slot], g->n, g->total[slot], g->gbits, g->guide[slot], s);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    free_tables(g, need);
-    return status_of(e);
+    if (want) g->total[slot] = h[1 + slot];
   }
   g->lambda3 = h[4];
   g->lambda4 = h[5];
@@ -485,7 +544,9 @@ void moss::free_graph_tables(moss_graph* g, uint32_t mask) {
 // With mask = 0: the bytes held now.  Otherwise the bytes that building `mask` adds.
 uint64_t moss::table_bytes_needed(const moss_graph* g, uint32_t mask) {
   const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz, G = (1ull << g->gbits) + 1;
-  const uint64_t k4 = n * 8 + G * 4, k5 = nnz * 8 + 2 * n * 8 + 2 * G * 4, sig = nnz * 4;
+  const uint64_t rg = (uint64_t)g->row_guide_len * 4;
+  const uint64_t hash = 8ull << edge_hash_bits(g->nnz / 2);
+  const uint64_t k4 = n * 8 + G * 4, k5 = nnz * 8 + 2 * n * 8 + 2 * G * 4 + rg, sig = nnz * 4 + rg + hash;
   if (mask == 0) {
     uint64_t b = 0;
     if (g->built) b += sig;

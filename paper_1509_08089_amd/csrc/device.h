@@ -77,6 +77,31 @@ __device__ __forceinline__ bool adjacent(const int32_t* __restrict__ col, int32_
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// ---- edge hash set: open addressing with linear probing over 2^bits u64 slots ----
+constexpr uint64_t kEmptySlot = ~0ull;
+
+__device__ __forceinline__ uint64_t edge_key(int32_t a, int32_t b) {
+  const uint32_t lo = (uint32_t)min(a, b), hi = (uint32_t)max(a, b);
+  return (uint64_t)lo << 32 | hi;
+}
+
+// Fibonacci hashing: the top bits of key * 2^64 / phi.
+__device__ __forceinline__ uint64_t edge_slot(uint64_t key, int bits) {
+  return (key * 0x9E3779B97F4A7C15ull) >> (64 - bits);
+}
+
+__device__ __forceinline__ bool edge_hash_has(const uint64_t* __restrict__ slots, int bits, int32_t a, int32_t b) {
+  const uint64_t key = edge_key(a, b), mask = (1ull << bits) - 1;
+  uint64_t h = edge_slot(key, bits);
+  for (uint64_t i = 0; i <= mask; ++i) {
+    const uint64_t x = slots[h];
+    if (x == key) return true;
+    if (x == kEmptySlot) return false;
+    h = (h + 1) & mask;
+  }
+  return false;
+}
+
 // Inclusive scan over the 64 lanes of a wave; `wrapped` is set on any 64-bit wrap.
 __device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t x, bool& wrapped) {
   const int lane = lane_id();

@@ -35,12 +35,19 @@ struct moss_graph {
   uint64_t* item_sum = nullptr;          // n_items, per-piece totals / their scan
   int64_t n_items = 0;
   uint64_t* scan_tmp = nullptr;          // block sums of the scans
+  uint4* rec = nullptr;                  // per node: row start, degree, S_v, row-guide offset
+  int64_t row_guide_len = 0;             // entries of one row-guide array
+  uint32_t* sig_guide = nullptr;         // row guides over ACC_sigma
+  uint32_t* tau_guide = nullptr;         // row guides over ACC_tau
+  uint64_t* edge_slots = nullptr;        // edge hash set for the induced-edge probes
+  int edge_bits = 4;
   uint64_t* partials = nullptr;          // per-block Lambda partial sums
   bool sigma_ready = false;
 
   // per-graph scratch
   unsigned long long* d_hits = nullptr;  // 2 x 22
   uint32_t* d_err = nullptr;             // error bits + max degree
+  uint64_t* d_meta = nullptr;            // [0] item count, [1] row-guide length
   unsigned long long* d_lambda = nullptr;
   uint64_t* h_stage = nullptr;           // pinned host staging, 64 words
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

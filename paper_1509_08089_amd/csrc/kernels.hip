@@ -162,11 +162,13 @@ __device__ __forceinline__ ItemRange item_range(const uint64_t* __restrict__ ite
 
 // Column range, self-loops, strict ascent (sorted, no repeats) and symmetry (v must
 // appear in the row of each of its neighbours).
-__global__ __launch_bounds__(256) void k_check_items(int64_t n_items, const uint64_t* __restrict__ items, int32_t n,
+__global__ __launch_bounds__(256) void k_check_items(const uint64_t* __restrict__ n_items_p,
+                                                     const uint64_t* __restrict__ items, int32_t n,
                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                      int full, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t n_items = (int64_t)*n_items_p;
   uint32_t bad = 0;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
     const ItemRange it = item_range(items, rp, i);
@@ -191,10 +193,10 @@ __global__ __launch_bounds__(256) void k_check_items(int64_t n_items, const uint
   if (lane == 0 && bad) atomicOr(err, bad);
 }
 
-hipError_t launch_check_items(int64_t n_items, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
-                              bool full, uint32_t* err, hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_check_items, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, n, rp, col,
+hipError_t launch_check_items(int64_t max_items, const uint64_t* n_items, const uint64_t* items, int32_t n,
+                              const int32_t* rp, const int32_t* col, bool full, uint32_t* err, hipStream_t s) {
+  if (max_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_items, dim3(item_grid(max_items)), dim3(256), 0, s, n_items, items, n, rp, col,
                      full ? 1 : 0, err);
   return hipGetLastError();
 }
@@ -285,6 +287,56 @@ hipError_t launch_row_prefix(bool tau, int64_t n_items, const uint64_t* items, c
   if (e != hipSuccess) return e;
   if (tau) hipLaunchKernelGGL(k_prefix_fix<true>, grid, block, 0, s, n_items, items, rp, item_sum, acc_sigma, acc_tau, err);
   else hipLaunchKernelGGL(k_prefix_fix<false>, grid, block, 0, s, n_items, items, rp, item_sum, acc_sigma, acc_tau, err);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Edge hash set for the induced-edge probes (the CIS() of Algorithms 1, 3, 4): each
+// undirected edge is inserted once (from its smaller endpoint's row) with a 64-bit
+// compare-and-swap, linear probing.  The table has at least 2.5 slots per edge, so a
+// lookup reads about 1.2-1.4 slots.  Every loop is bounded by the table size.
+// ---------------------------------------------------------------------------------
+int edge_hash_bits(int64_t m) {
+  int bits = 4;
+  while (bits < 40 && (double)(1ll << bits) < 2.5 * (double)m) ++bits;
+  return bits;
+}
+
+__global__ __launch_bounds__(256) void k_edge_hash(int64_t n_items, const uint64_t* __restrict__ items,
+                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   unsigned long long* __restrict__ slots, int bits, uint32_t* err) {
+  const int lane = lane_id();
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t mask = (1ull << bits) - 1;
+  bool full = false;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
+      const int32_t c = col[e];
+      if (c <= it.v) continue;  // each edge once, from its smaller endpoint
+      const uint64_t key = edge_key(it.v, c);
+      uint64_t h = edge_slot(key, bits);
+      uint64_t probes = 0;
+      for (;;) {
+        const unsigned long long old = atomicCAS(&slots[h], (unsigned long long)kEmptySlot, (unsigned long long)key);
+        if (old == kEmptySlot || old == key) break;
+        h = (h + 1) & mask;
+        if (++probes > mask) {
+          full = true;
+          break;
+        }
+      }
+    }
+  }
+  if (__ballot(full) != 0 && lane == 0) atomicOr(err, kErrOverflow);
+}
+
+hipError_t launch_edge_hash(int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
+                            uint64_t* slots, int bits, uint32_t* err, hipStream_t s) {
+  hipError_t e = launch_fill_u64(slots, kEmptySlot, 1ll << bits, s);
+  if (e != hipSuccess || n_items <= 0) return e;
+  hipLaunchKernelGGL(k_edge_hash, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, rp, col,
+                     (unsigned long long*)slots, bits, err);
   return hipGetLastError();
 }
 
@@ -498,9 +550,10 @@ hipError_t launch_scan_inplace(uint64_t* data, int64_t n, uint64_t* tmp, uint32_
 // monotone in the word, so every word of bucket b picks a node in
 // [guide[b], guide[b+1]], and the search runs over that window only.
 // ---------------------------------------------------------------------------------
-__global__ void k_guide(const uint64_t* __restrict__ acc, int32_t n, uint64_t total, int gbits,
-                        uint32_t* __restrict__ guide) {
+__global__ void k_guide(const uint64_t* __restrict__ acc, int32_t n, int gbits, uint32_t* __restrict__ guide) {
   const int64_t G = 1ll << gbits;
+  const uint64_t total = acc[n - 1];
+  if (total == 0) return;  // nothing can be drawn; the guide is never read
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= G; b += (int64_t)gridDim.x * blockDim.x) {
     if (b == G) {
       guide[b] = (uint32_t)(n - 1);
@@ -511,10 +564,114 @@ __global__ void k_guide(const uint64_t* __restrict__ acc, int32_t n, uint64_t to
   }
 }
 
-hipError_t launch_guide(const uint64_t* acc, int32_t n, uint64_t total, int gbits, uint32_t* guide, hipStream_t s) {
+hipError_t launch_guide(const uint64_t* acc, int32_t n, int gbits, uint32_t* guide, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
   const int64_t G = (1ll << gbits) + 1;
-  hipLaunchKernelGGL(k_guide, dim3(fill_grid(G)), dim3(256), 0, s, acc, n, total, gbits, guide);
+  hipLaunchKernelGGL(k_guide, dim3(fill_grid(G)), dim3(256), 0, s, acc, n, gbits, guide);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Node records and row guides.  A weighted pick inside a row (sigma, mu, tau) is a
+// search for the first entry of the row's prefix above a value x < total.  For rows
+// with d >= kRowGuideMin the value range is cut into 2^g buckets of width 2^s
+// (g = floor(log2 d) - 1, s = max(0, bitlen(total) - g)); guide[b] is the first
+// entry above b * 2^s, and guide[2^g] = d - 1.  A value x in bucket b = x >> s has
+// its answer in [guide[b], guide[b+1]], a window of about two entries.  The pick is
+// the same entry as the plain binary search; only the number of reads changes.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ int row_guide_bits(int32_t d) { return 31 - __clz(d) - 1; }
+
+__device__ __forceinline__ int row_guide_shift(uint64_t total, int g) {
+  const int bl = total ? 64 - __clzll((long long)total) : 0;
+  return bl > g ? bl - g : 0;
+}
+
+__global__ void k_row_guide_sizes(int32_t n, const int32_t* __restrict__ rp, uint64_t* __restrict__ sizes) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t d = rp[v + 1] - rp[v];
+    sizes[v] = d >= kRowGuideMin ? (1ull << row_guide_bits(d)) + 1 : 0ull;
+  }
+}
+
+hipError_t launch_row_guide_sizes(int32_t n, const int32_t* rp, uint64_t* sizes, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_guide_sizes, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, sizes);
+  return hipGetLastError();
+}
+
+// With goff_end: writes whole records (S_v = 0 when acc_sigma is null).  Without:
+// only refreshes S_v of existing records.
+__global__ void k_records(int32_t n, const int32_t* __restrict__ rp, const uint32_t* __restrict__ acc_sigma,
+                          const uint64_t* __restrict__ goff_end, uint4* __restrict__ rec) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r0 = rp[v], r1 = rp[v + 1], d = r1 - r0;
+    const uint32_t S = (acc_sigma && d > 0) ? acc_sigma[r1 - 1] : 0u;
+    if (goff_end) {
+      const uint64_t size = d >= kRowGuideMin ? (1ull << row_guide_bits(d)) + 1 : 0ull;
+      rec[v] = make_uint4((uint32_t)r0, (uint32_t)d, S, (uint32_t)(goff_end[v] - size));
+    } else {
+      rec[v].z = S;
+    }
+  }
+}
+
+hipError_t launch_records(int32_t n, const int32_t* rp, const uint32_t* acc_sigma, const uint64_t* goff_end, uint4* rec,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_records, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, acc_sigma, goff_end, rec);
+  return hipGetLastError();
+}
+
+// One wave per work item: entry i of the row covers the buckets whose lower bound
+// lies in [ACC[i-1], ACC[i]); the last entry also covers the buckets at or above the
+// total.
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_guides(int64_t n_items, const uint64_t* __restrict__ items,
+                                                    const int32_t* __restrict__ rp, const uint4* __restrict__ rec,
+                                                    const T* __restrict__ acc, uint32_t* __restrict__ guide) {
+  const int lane = lane_id();
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    const int32_t d = it.r1 - it.r0;
+    if (d < kRowGuideMin) continue;
+    const int g = row_guide_bits(d);
+    const uint64_t total = acc[it.r1 - 1];
+    const int s = row_guide_shift(total, g);
+    const uint64_t last_bucket = 1ull << g;
+    uint32_t* gd = guide + rec[it.v].w;
+    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
+      const uint64_t lo = e > it.r0 ? (uint64_t)acc[e - 1] : 0ull, hi = (uint64_t)acc[e];
+      const uint64_t b0 = lo ? ((lo - 1) >> s) + 1 : 0ull;
+      uint64_t b1 = hi ? ((hi - 1) >> s) + 1 : 0ull;
+      if (e == it.r1 - 1) b1 = last_bucket + 1;
+      for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - it.r0);
+    }
+  }
+}
+
+hipError_t launch_row_guides(bool tau, int64_t n_items, const uint64_t* items, const int32_t* rp, const uint4* rec,
+                             const uint32_t* acc_sigma, const uint64_t* acc_tau, uint32_t* guide, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (tau)
+    hipLaunchKernelGGL(k_row_guides<uint64_t>, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, rp, rec,
+                       acc_tau, guide);
+  else
+    hipLaunchKernelGGL(k_row_guides<uint32_t>, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, rp, rec,
+                       acc_sigma, guide);
+  return hipGetLastError();
+}
+
+// Weighted pick in a row: the first entry of acc[0..d) above x (x < total = acc[d-1]).
+template <typename T>
+__device__ __forceinline__ int32_t row_pick(const T* __restrict__ acc, int32_t d, uint64_t total, uint64_t x,
+                                            const uint32_t* __restrict__ guide, uint32_t goff) {
+  if (d < kRowGuideMin) return first_above(acc, 0, d - 1, x);
+  const int g = row_guide_bits(d);
+  const uint64_t b = x >> row_guide_shift(total, g);
+  const uint32_t* gd = guide + goff;
+  return first_above(acc, (int32_t)gd[b], (int32_t)gd[b + 1], x);
 }
 
 // ---------------------------------------------------------------------------------
@@ -536,6 +693,11 @@ __device__ __forceinline__ int32_t neighbour_except(const int32_t* __restrict__ 
   return x >= skip ? col[ra + j + 1] : x;
 }
 
+// row start and degree of a node (the first half of its record)
+__device__ __forceinline__ uint2 row_of(const uint4* __restrict__ rec, int32_t x) {
+  return *reinterpret_cast<const uint2*>(rec + x);
+}
+
 // MOSS-4 (Algorithm 1): v ~ Gamma_v, u ~ d_u - 1 over N_v, w uniform in N_v - {u},
 // r uniform in N_u - {v}; rejected when r = w.  Known edges vu, vw, ur; probe bits
 // b0 = u~w, b1 = v~r, b2 = w~r.
@@ -545,23 +707,24 @@ __device__ __forceinline__ int draw_moss4(const SamplerView& a, const uint8_t* l
   philox_block(k, 0, seed, kMoss4, W);
   const int32_t* __restrict__ col = a.col;
   const int32_t v = pick_node(a, W[0]);
-  const int32_t rv = a.rp[v], dv = a.rp[v + 1] - rv;
-  const uint32_t Sv = a.acc_sigma[rv + dv - 1];
-  const int32_t iu = first_above(a.acc_sigma + rv, 0, dv - 1, bounded(W[1], Sv));
+  const uint4 R = a.rec[v];
+  const int32_t rv = (int32_t)R.x, dv = (int32_t)R.y;
+  const int32_t iu = row_pick(a.acc_sigma + rv, dv, R.z, bounded(W[1], R.z), a.sig_guide, R.w);
   const int32_t u = col[rv + iu];
   int32_t iw = (int32_t)bounded(W[2], (uint64_t)(dv - 1));
   iw += iw >= iu;
   const int32_t w = col[rv + iw];
-  const int32_t ru = a.rp[u], du = a.rp[u + 1] - ru;
+  const uint2 U = row_of(a.rec, u);
+  const int32_t ru = (int32_t)U.x, du = (int32_t)U.y;
   const int32_t r = neighbour_except(col, ru, du, v, W[3]);
   if (nodes) {
     nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = -1;
   }
   if (r == w) return 0;
-  const int32_t rw = a.rp[w], dw = a.rp[w + 1] - rw;
-  const int32_t rr = a.rp[r], dr = a.rp[r + 1] - rr;
-  const int m = (int)adjacent(col, ru, du, u, rw, dw, w) | (int)adjacent(col, rv, dv, v, rr, dr, r) << 1 |
-                (int)adjacent(col, rw, dw, w, rr, dr, r) << 2;
+  const uint64_t* __restrict__ hs = a.edge_slots;
+  const int hb = a.edge_bits;
+  const int m = (int)edge_hash_has(hs, hb, u, w) | (int)edge_hash_has(hs, hb, v, r) << 1 |
+                (int)edge_hash_has(hs, hb, w, r) << 2;
   return lut[m];
 }
 
@@ -576,9 +739,9 @@ __device__ __forceinline__ int draw_t5(const SamplerView& a, const uint8_t* lut,
   philox_block(k, 1, seed, kT5, X);
   const int32_t* __restrict__ col = a.col;
   const int32_t v = pick_node(a, W[0]);
-  const int32_t rv = a.rp[v], dv = a.rp[v + 1] - rv;
-  const uint32_t Sv = a.acc_sigma[rv + dv - 1];
-  const int32_t iu = first_above(a.acc_sigma + rv, 0, dv - 1, bounded(W[1], Sv));
+  const uint4 R = a.rec[v];
+  const int32_t rv = (int32_t)R.x, dv = (int32_t)R.y;
+  const int32_t iu = row_pick(a.acc_sigma + rv, dv, R.z, bounded(W[1], R.z), a.sig_guide, R.w);
   const int32_t u = col[rv + iu];
   int32_t iw = (int32_t)bounded(W[2], (uint64_t)(dv - 1));
   iw += iw >= iu;
@@ -588,18 +751,18 @@ __device__ __forceinline__ int draw_t5(const SamplerView& a, const uint8_t* lut,
   ir += ir >= lo;
   ir += ir >= hi;
   const int32_t r = col[rv + ir];
-  const int32_t ru = a.rp[u], du = a.rp[u + 1] - ru;
+  const uint2 U = row_of(a.rec, u);
+  const int32_t ru = (int32_t)U.x, du = (int32_t)U.y;
   const int32_t t = neighbour_except(col, ru, du, v, X[0]);
   if (nodes) {
     nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = t;
   }
   if (t == w || t == r) return 0;
-  const int32_t rw = a.rp[w], dw = a.rp[w + 1] - rw;
-  const int32_t rr = a.rp[r], dr = a.rp[r + 1] - rr;
-  const int32_t rt = a.rp[t], dt = a.rp[t + 1] - rt;
-  const int m = (int)adjacent(col, ru, du, u, rw, dw, w) | (int)adjacent(col, ru, du, u, rr, dr, r) << 1 |
-                (int)adjacent(col, rw, dw, w, rr, dr, r) << 2 | (int)adjacent(col, rv, dv, v, rt, dt, t) << 3 |
-                (int)adjacent(col, rw, dw, w, rt, dt, t) << 4 | (int)adjacent(col, rr, dr, r, rt, dt, t) << 5;
+  const uint64_t* __restrict__ hs = a.edge_slots;
+  const int hb = a.edge_bits;
+  const int m = (int)edge_hash_has(hs, hb, u, w) | (int)edge_hash_has(hs, hb, u, r) << 1 |
+                (int)edge_hash_has(hs, hb, w, r) << 2 | (int)edge_hash_has(hs, hb, v, t) << 3 |
+                (int)edge_hash_has(hs, hb, w, t) << 4 | (int)edge_hash_has(hs, hb, r, t) << 5;
   return lut[m];
 }
 
@@ -615,31 +778,33 @@ __device__ __forceinline__ int draw_path5(const SamplerView& a, const uint8_t* l
   philox_block(k, 1, seed, kPath5, X);
   const int32_t* __restrict__ col = a.col;
   const int32_t v = pick_node(a, W[0]);
-  const int32_t rv = a.rp[v], dv = a.rp[v + 1] - rv;
+  const uint4 R = a.rec[v];
+  const int32_t rv = (int32_t)R.x, dv = (int32_t)R.y;
   const uint64_t* __restrict__ tau = a.acc_tau + rv;
-  const int32_t iu = first_above(tau, 0, dv - 1, bounded(W[1], tau[dv - 1]));
+  const uint64_t T = tau[dv - 1];
+  const int32_t iu = row_pick(tau, dv, T, bounded(W[1], T), a.tau_guide, R.w);
   const int32_t u = col[rv + iu];
   const uint32_t* __restrict__ sig = a.acc_sigma + rv;
-  const uint64_t Sv = sig[dv - 1];
+  const uint64_t Sv = R.z;
   const uint64_t blk_lo = iu > 0 ? sig[iu - 1] : 0;
   const uint64_t du1 = (uint64_t)sig[iu] - blk_lo;
   uint64_t x = bounded(W[2], Sv - du1);
   x += x >= blk_lo ? du1 : 0;
-  const int32_t iw = first_above(sig, 0, dv - 1, x);
+  const int32_t iw = row_pick(sig, dv, Sv, x, a.sig_guide, R.w);
   const int32_t w = col[rv + iw];
-  const int32_t ru = a.rp[u], du = a.rp[u + 1] - ru;
+  const uint2 U = row_of(a.rec, u), Wr = row_of(a.rec, w);
+  const int32_t ru = (int32_t)U.x, du = (int32_t)U.y, rw = (int32_t)Wr.x, dw = (int32_t)Wr.y;
   const int32_t r = neighbour_except(col, ru, du, v, W[3]);
-  const int32_t rw = a.rp[w], dw = a.rp[w + 1] - rw;
   const int32_t t = neighbour_except(col, rw, dw, v, X[0]);
   if (nodes) {
     nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = t;
   }
   if (t == u || r == w || t == r) return 0;
-  const int32_t rr = a.rp[r], dr = a.rp[r + 1] - rr;
-  const int32_t rt = a.rp[t], dt = a.rp[t + 1] - rt;
-  const int m = (int)adjacent(col, rv, dv, v, rr, dr, r) | (int)adjacent(col, rv, dv, v, rt, dt, t) << 1 |
-                (int)adjacent(col, ru, du, u, rw, dw, w) << 2 | (int)adjacent(col, ru, du, u, rt, dt, t) << 3 |
-                (int)adjacent(col, rw, dw, w, rr, dr, r) << 4 | (int)adjacent(col, rr, dr, r, rt, dt, t) << 5;
+  const uint64_t* __restrict__ hs = a.edge_slots;
+  const int hb = a.edge_bits;
+  const int m = (int)edge_hash_has(hs, hb, v, r) | (int)edge_hash_has(hs, hb, v, t) << 1 |
+                (int)edge_hash_has(hs, hb, u, w) << 2 | (int)edge_hash_has(hs, hb, u, t) << 3 |
+                (int)edge_hash_has(hs, hb, w, r) << 4 | (int)edge_hash_has(hs, hb, r, t) << 5;
   return lut[m];
 }
 
@@ -665,7 +830,7 @@ constexpr int kMaxWaves = 16;  // 1024 threads per block at most
 constexpr int kBins = 22;
 
 template <int S>
-__global__ __launch_bounds__(256) void k_sample(SamplerView a, uint64_t seed, uint64_t k0, uint64_t k1,
+__global__ __launch_bounds__(256, 8) void k_sample(SamplerView a, uint64_t seed, uint64_t k0, uint64_t k1,
                                                 unsigned long long* __restrict__ hits, uint8_t* __restrict__ class_out) {
   __shared__ uint32_t bins[kMaxWaves][kBins + 2];
   __shared__ uint8_t lut[64];
@@ -740,7 +905,7 @@ hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed,
 // samples are spread over the block's lanes; its histogram is flushed to the tile's
 // output slot.  The sampler is uniform within a tile, so the branch is uniform.
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_batch(const SamplerView* __restrict__ views, const Tile* __restrict__ tiles,
+__global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict__ views, const Tile* __restrict__ tiles,
                                                const uint32_t* __restrict__ n_tiles_p, uint32_t* tile_counter,
                                                unsigned long long* __restrict__ bins) {
   __shared__ uint32_t lb[kMaxWaves][kBins + 2];

@@ -337,6 +337,15 @@ class Graph:
             self._rp = self._col = None
             self.h = moss_graph_create(self.n, self.nnz, csr.row_ptr, csr.col, flags, stream)
 
+    @classmethod
+    def from_device(cls, d_row_ptr, d_col, flags: int = 0, stream=None):
+        """Borrows int32 device tensors row_ptr[n+1], col[nnz] (kept alive by the object)."""
+        self = cls.__new__(cls)
+        self.n, self.nnz = int(d_row_ptr.numel()) - 1, int(d_col.numel())
+        self._rp, self._col = d_row_ptr, d_col
+        self.h = moss_graph_create_device(self.n, self.nnz, d_row_ptr, d_col, flags, stream)
+        return self
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             moss_graph_destroy(self.h)

@@ -110,7 +110,10 @@ def test_server_alone_and_in_mix(graphs):
 def test_server_memory_budget_evicts_and_rejects():
     gs = [gg.chung_lu(3000, 20000, 2.2, 300, 40 + i) for i in range(4)]
     hs = [moss.Graph(g) for g in gs]
-    need = 3000 * 8 + 20000 * 2 * 4 + (1 << 13) * 4 + 4096  # k=4 tables of one graph, with slack
+    probe = moss.Graph(gs[0])
+    probe.build_tables(moss.MOSS_TABLES_K4)
+    need = max(probe.info().device_bytes for _ in range(1))  # 4-node tables of one such graph
+    probe.close()
     srv = moss.moss_server_create(int(need * 1.5), 4, 10_000)
     try:
         ids = [moss.moss_server_add_graph(srv, h.h) for h in hs]

@@ -15,9 +15,18 @@ from pins import choose
 
 pytestmark = pytest.mark.gpu
 
+def _broom():
+    # a hub of degree 300 whose neighbours mostly have degree 1 (zero sigma weight),
+    # with a few heavier neighbours spread over the row
+    edges = [(0, i) for i in range(1, 301)]
+    edges += [(i, 300 + i) for i in range(1, 301, 37)] + [(5, 6), (100, 101), (299, 300)]
+    return gg.from_edges(700, edges, "broom")
+
+
 GRAPHS = [
     gg.gnp(11, 0.45, 2), gg.gnp(40, 0.2, 5), gg.wheel(9), gg.complete(7), gg.complete_bipartite(4, 6),
     gg.chung_lu(600, 4000, 2.3, 80, 11), gg.chung_lu(5000, 40000, 2.1, 900, 12),
+    gg.wheel(300), _broom(), gg.complete_bipartite(3, 200), gg.complete(70),
 ]
 
 
