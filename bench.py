@@ -204,6 +204,7 @@ def main():
     kern_ms = sum(r.device_ms for r in results) / len(results)
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9
     traffic = measured_traffic(kernel, args.workload)
+    traffic_gbs = traffic / (kern_ms / 1e3) / 1e9 if traffic else None
     line = {
         "metric": "graphlet samples/sec (4-,5-node) batched vs plain; serving p50/p99 latency",
         "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -215,6 +216,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": kernel, "kernel_ms": kern_ms,
+                     "traffic_gbs": traffic_gbs, "traffic_frac": traffic_gbs / PEAK_HBM_GBS if traffic_gbs else None,
                      "alg_bytes_per_launch": alg_bytes,
                      "lines_per_sample": {kk: lc[kk] for kk in ("moss4", "t5", "path5") if kk in lc},
                      "kernel_samples_per_s": K / (kern_ms / 1e3)},
