@@ -82,8 +82,12 @@ def host_cores() -> int:
 
 
 def kernel_source_sha() -> str:
-    p = os.path.join(ROOT, "paper_1509_08089_amd", "csrc", "kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the device sources (kernels and the device helpers they include)."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1509_08089_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -250,18 +254,20 @@ def run_batched(moss, gg):
     total = sum(r.samples for r in reqs)
     for g in graphs:
         g.build_tables()
-    moss.moss_estimate_batch(q)  # warm-up
-    t = time.perf_counter()
-    got = moss.moss_estimate_batch(q)
-    t_batch = time.perf_counter() - t
-    t = time.perf_counter()
-    alone = [moss.moss_estimate(*x) for x in q]
-    t_plain = time.perf_counter() - t
+    def timed(fn, reps=3):  # median wall time of `reps` calls after one warm-up call
+        out = fn()
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            out = fn()
+            ts.append(time.perf_counter() - t)
+        return sorted(ts)[len(ts) // 2], out
+
+    t_batch, got = timed(lambda: moss.moss_estimate_batch(q))
+    t_plain, alone = timed(lambda: [moss.moss_estimate(*x) for x in q])
     same = all(np.array_equal(a.hits_np, b.hits_np) for a, b in zip(alone, got))
     best, ms = moss.moss_autotune(q)
-    t = time.perf_counter()
-    got2 = moss.moss_estimate_batch(q)
-    t_tuned = time.perf_counter() - t
+    t_tuned, got2 = timed(lambda: moss.moss_estimate_batch(q))
     same = same and all(np.array_equal(a.hits_np, b.hits_np) for a, b in zip(alone, got2))
     moss.moss_set_tuning(0, 0, 0)
     return {"requests": len(q), "graphs": len(graphs), "samples": total,

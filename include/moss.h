@@ -224,9 +224,10 @@ typedef struct {
 moss_status moss_set_tuning(const moss_tuning *t);
 moss_status moss_get_tuning(moss_tuning *t);
 
-/* Autotuner: times the batched kernel over the given requests for each candidate tile
-   size and occupancy (results are identical for every candidate) and keeps the fastest
-   as the process-wide tuning; best_ms receives its time. */
+/* Autotuner: times moss_estimate_batch over the given requests (host tile list and
+   staging included) for each candidate tile size and occupancy (results are identical
+   for every candidate) and keeps the fastest as the process-wide tuning; best_ms
+   receives its wall time. */
 moss_status moss_autotune(const moss_request *reqs, int32_t n, moss_tuning *best, double *best_ms);
 
 /* ---- serving: continuous batching over resident graphs --------------------------------

@@ -87,23 +87,41 @@ SamplerView sampler_view(const moss_graph* g, int sampler) {
   v.tau_guide = g->tau_guide;
   v.edge_slots = g->edge_slots;
   v.edge_bits = g->edge_bits;
+  v.filter = g->filter;
+  v.filter_bits = g->filter_bits;
   v.total = g->total[s];
   v.n = g->n;
   v.gbits = g->gbits;
   return v;
 }
 
-void plain_launch_shape(int device, int sampler, uint64_t nsamples, int* grid, int* block) {
+// Resident waves per CU for the sampling kernels, by the bytes a graph's samples read
+// at random (CSR and tables).  Measured on MI355X: a graph whose tables fit the 256 MB
+// MALL samples fastest with about 20 waves per CU; one far larger than the MALL with
+// 8 (more waves in flight then only add queueing and translation misses).
+int sampling_waves_per_cu(uint64_t footprint_bytes) {
+  const uint64_t MB = 1ull << 20;
+  if (footprint_bytes <= 128 * MB) return 20;
+  if (footprint_bytes <= 256 * MB) return 16;
+  if (footprint_bytes <= 384 * MB) return 12;
+  return 8;
+}
+
+uint64_t sampling_footprint(const moss_graph* g) {
+  return g->table_bytes + ((uint64_t)g->n + 1 + (uint64_t)g->nnz) * sizeof(int32_t);
+}
+
+void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int* grid, int* block) {
   const Tuning t = current_tuning();
   int b = t.threads_per_block ? (int)t.threads_per_block : 256;
   int per_cu = t.blocks_per_cu ? (int)t.blocks_per_cu : 0;
   if (per_cu == 0) {
-    per_cu = sample_kernel_blocks_per_cu(sampler, b);
-    per_cu = std::max(1, std::min(per_cu, 8));
+    const int cap = std::max(1, std::min(sample_kernel_blocks_per_cu(sampler, b), 8));
+    per_cu = std::max(1, std::min(cap, sampling_waves_per_cu(sampling_footprint(g)) / (b / 64)));
   }
   const uint64_t want = (nsamples + (uint64_t)b - 1) / (uint64_t)b;
-  const uint64_t cap = (uint64_t)device_cus(device) * (uint64_t)per_cu;
-  *grid = (int)std::max<uint64_t>(1, std::min(want, cap));
+  const uint64_t most = (uint64_t)device_cus(g->device) * (uint64_t)per_cu;
+  *grid = (int)std::max<uint64_t>(1, std::min(want, most));
   *block = b;
 }
 
@@ -115,12 +133,12 @@ namespace {
 
 // Device memory is stream-ordered (hipMallocAsync on the graph's stream from the
 // device's default pool, which keeps freed blocks for reuse), so building and
-// dropping tables costs no device-wide synchronisation.
-template <typename T>
-moss_status dev_alloc(hipStream_t s, T** p, size_t count) {
+// dropping tables costs no device-wide synchronisation.  Each graph holds a few
+// blocks, every array carved out of one of them at a 256-byte boundary.
+moss_status dev_alloc_bytes(hipStream_t s, void** p, size_t bytes) {
   *p = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMallocAsync((void**)p, count * sizeof(T), s);
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMallocAsync(p, bytes, s);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
@@ -129,16 +147,85 @@ moss_status dev_alloc(hipStream_t s, T** p, size_t count) {
   return MOSS_OK;
 }
 
-template <typename T>
-void dev_free(hipStream_t s, T*& p) {
-  if (p) (void)hipFreeAsync((void*)p, s);
+void dev_free(hipStream_t s, void*& p) {
+  if (p) (void)hipFreeAsync(p, s);
   p = nullptr;
+}
+
+struct Carve {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t count) {
+    const size_t o = off;
+    off += (count * sizeof(T) + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// per graph: word block, items, item sums, row-guide lengths, scan scratch, partials, records
+struct GraphLayout {
+  size_t small, items, item_sum, guide_len, tmp[3], partials, rec, bytes;
+};
+
+GraphLayout graph_layout(int32_t n, int64_t nnz) {
+  const int64_t cap = items_cap(n, nnz);
+  GraphLayout L;
+  Carve c;
+  L.small = c.take<uint64_t>(kWords);
+  L.items = c.take<uint64_t>((size_t)cap);
+  L.item_sum = c.take<uint64_t>((size_t)std::max<int64_t>(cap, (int64_t)n));
+  L.guide_len = c.take<uint64_t>((size_t)n);
+  for (int j = 0; j < 3; ++j) L.tmp[j] = c.take<uint64_t>((size_t)scan_tmp_elems(n));
+  L.partials = c.take<uint64_t>(2 * (size_t)node_weight_blocks(n));
+  L.rec = c.take<uint4>((size_t)n);
+  L.bytes = c.off;
+  return L;
+}
+
+struct SigLayout {
+  size_t acc_sigma, guide, slots, filter, bytes;
+};
+
+SigLayout sig_layout(const moss_graph* g) {
+  SigLayout L;
+  Carve c;
+  L.acc_sigma = c.take<uint32_t>((size_t)g->nnz);
+  L.guide = c.take<uint32_t>((size_t)g->row_guide_len);
+  L.slots = c.take<uint64_t>((size_t)1 << edge_hash_bits(g->nnz / 2));
+  L.filter = c.take<uint64_t>((size_t)1 << edge_filter_bits(g->nnz / 2));
+  L.bytes = c.off;
+  return L;
+}
+
+struct NodeLayout {
+  size_t acc_tau, tau_guide, acc[2], guide[2], bytes;
+};
+
+// k5 = false: ACC_Gamma and its guide; true: ACC_tau, its row guides, ACC_Gamma1/2, guides
+NodeLayout node_layout(const moss_graph* g, bool k5) {
+  const size_t n = (size_t)g->n, G = ((size_t)1 << g->gbits) + 1;
+  NodeLayout L{};
+  Carve c;
+  if (k5) {
+    L.acc_tau = c.take<uint64_t>((size_t)g->nnz);
+    L.tau_guide = c.take<uint32_t>((size_t)g->row_guide_len);
+  }
+  const int sets = k5 ? 2 : 1;
+  for (int j = 0; j < sets; ++j) L.acc[j] = c.take<uint64_t>(n);
+  for (int j = 0; j < sets; ++j) L.guide[j] = c.take<uint32_t>(G);
+  L.bytes = c.off;
+  return L;
 }
 
 // Small pinned host buffers for results and flags, reused across graphs.
 std::mutex g_pin_mu;
 std::vector<uint64_t*> g_pin_free;
-constexpr size_t kPinWords = 64;
+constexpr size_t kPinWords = kWords;
 
 uint64_t* pinned_chunk() {
   std::lock_guard<std::mutex> lk(g_pin_mu);
@@ -159,27 +246,52 @@ void pinned_release(uint64_t* p) {
   g_pin_free.push_back(p);
 }
 
+// Timing events, kept per device for reuse (creating and destroying them costs more
+// than the small calls they time).
+std::vector<std::vector<hipEvent_t>> g_events;  // guarded by g_pin_mu
+
+hipEvent_t pooled_event(int device) {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if ((int)g_events.size() > device && !g_events[device].empty()) {
+      hipEvent_t e = g_events[device].back();
+      g_events[device].pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void event_release(int device, hipEvent_t e) {
+  if (!e) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  if ((int)g_events.size() <= device) g_events.resize(device + 1);
+  g_events[device].push_back(e);
+}
+
 void free_tables(moss_graph* g, uint32_t mask) {
   if (mask & MOSS_TABLES_K4) {
-    dev_free(g->stream, g->acc_node[0]);
-    dev_free(g->stream, g->guide[0]);
+    dev_free(g->stream, g->mem_k4);
+    g->acc_node[0] = nullptr;
+    g->guide[0] = nullptr;
     g->total[0] = 0;
   }
   if (mask & MOSS_TABLES_K5) {
-    dev_free(g->stream, g->acc_node[1]);
-    dev_free(g->stream, g->acc_node[2]);
-    dev_free(g->stream, g->guide[1]);
-    dev_free(g->stream, g->guide[2]);
-    dev_free(g->stream, g->acc_tau);
-    dev_free(g->stream, g->tau_guide);
+    dev_free(g->stream, g->mem_k5);
+    g->acc_tau = nullptr;
+    g->tau_guide = nullptr;
+    g->acc_node[1] = g->acc_node[2] = nullptr;
+    g->guide[1] = g->guide[2] = nullptr;
     g->total[1] = g->total[2] = 0;
   }
   g->built &= ~mask;
   if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5))) {
-    dev_free(g->stream, g->acc_sigma);
-    dev_free(g->stream, g->sig_guide);
-    dev_free(g->stream, g->edge_slots);
-    g->sigma_ready = false;
+    dev_free(g->stream, g->mem_sig);
+    g->acc_sigma = nullptr;
+    g->sig_guide = nullptr;
+    g->edge_slots = nullptr;
+    g->filter = nullptr;
   }
   g->table_bytes = moss::table_bytes_needed(g, 0);
 }
@@ -189,21 +301,13 @@ void destroy_graph(moss_graph* g) {
   DeviceScope scope(g->device);
   (void)hipStreamSynchronize(g->stream);
   free_tables(g, MOSS_TABLES_K4 | MOSS_TABLES_K5);
-  dev_free(g->stream, g->owned_rp);
-  dev_free(g->stream, g->owned_col);
-  dev_free(g->stream, g->items);
-  dev_free(g->stream, g->item_sum);
-  dev_free(g->stream, g->scan_tmp);
-  dev_free(g->stream, g->partials);
-  dev_free(g->stream, g->rec);
-  dev_free(g->stream, g->d_hits);
-  dev_free(g->stream, g->d_err);
-  dev_free(g->stream, g->d_lambda);
-  dev_free(g->stream, g->d_meta);
+  void* csr = g->owned_rp;
+  dev_free(g->stream, csr);
+  dev_free(g->stream, g->mem_graph);
   pinned_release(g->h_stage);
   g->h_stage = nullptr;
-  if (g->ev0) (void)hipEventDestroy(g->ev0);
-  if (g->ev1) (void)hipEventDestroy(g->ev1);
+  event_release(g->device, g->ev0);
+  event_release(g->device, g->ev1);
   delete g;
 }
 
@@ -217,57 +321,57 @@ int validate_error_status(uint32_t bits) {
   return MOSS_OK;
 }
 
-// Scratch, events and the CSR checks shared by both creation paths.
+// Per-graph memory, events and the CSR checks shared by both creation paths: one
+// pass over the nodes, one scan pair (piece counts and row-guide lengths), items and
+// records, the column checks, one copy back and one synchronisation.
 moss_status finish_create(moss_graph* g) {
-  moss_status st;
-  if ((st = dev_alloc(g->stream, &g->d_hits, 2 * 22)) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &g->d_err, 4)) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &g->d_lambda, 2)) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &g->d_meta, 2)) != MOSS_OK) return st;
+  const GraphLayout L = graph_layout(g->n, g->nnz);
+  moss_status st = dev_alloc_bytes(g->stream, &g->mem_graph, L.bytes);
+  if (st != MOSS_OK) return st;
+  void* m = g->mem_graph;
+  g->small = at<uint64_t>(m, L.small);
+  g->items = at<uint64_t>(m, L.items);
+  g->item_sum = at<uint64_t>(m, L.item_sum);
+  g->guide_len = at<uint64_t>(m, L.guide_len);
+  for (int j = 0; j < 3; ++j) g->scan_tmp[j] = at<uint64_t>(m, L.tmp[j]);
+  g->partials = at<uint64_t>(m, L.partials);
+  g->rec = at<uint4>(m, L.rec);
   if (!(g->h_stage = pinned_chunk())) return MOSS_E_NOMEM;
-  if (hipEventCreate(&g->ev0) != hipSuccess || hipEventCreate(&g->ev1) != hipSuccess) return MOSS_E_DEVICE;
+  if (!(g->ev0 = pooled_event(g->device)) || !(g->ev1 = pooled_event(g->device))) return MOSS_E_DEVICE;
   hipStream_t s = g->stream;
-  hipError_t e = launch_fill_u32(g->d_err, 0, 4, s);
-  if (e == hipSuccess) e = launch_check_rowptr(g->n, g->nnz, g->rp, g->d_err, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->d_err, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return status_of(e);
-  uint32_t bits = ((uint32_t*)g->h_stage)[0];
-  g->max_degree = (int32_t)((uint32_t*)g->h_stage)[1];
-  if (bits) return (moss_status)validate_error_status(bits);
-  // work items: every row cut into pieces of at most 256 entries
-  const int64_t items_ub = (int64_t)g->n + g->nnz / 256 + 1;
-  const int64_t tmp_elems = std::max(scan_tmp_elems(g->n), scan_tmp_elems(items_ub));
-  uint64_t* item_end = nullptr;
-  if ((st = dev_alloc(g->stream, &g->items, (size_t)items_ub)) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &g->item_sum, (size_t)items_ub)) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &g->scan_tmp, (size_t)tmp_elems)) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &g->partials, 2 * (size_t)node_weight_blocks(g->n))) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &g->rec, (size_t)g->n)) != MOSS_OK) return st;
-  if ((st = dev_alloc(g->stream, &item_end, (size_t)g->n)) != MOSS_OK) return st;
-  e = launch_items(g->n, g->rp, item_end, g->items, g->scan_tmp, g->d_err, s);
-  if (e == hipSuccess) e = launch_fill_u64(g->d_meta, 0, 2, s);
-  if (e == hipSuccess && g->n > 0)
-    e = hipMemcpyAsync(g->d_meta, item_end + (g->n - 1), sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
-  // row-guide layout (depends on degrees only), then the records' row start, degree, offset
-  if (e == hipSuccess) e = launch_row_guide_sizes(g->n, g->rp, item_end, s);
-  if (e == hipSuccess) e = launch_scan_inplace(item_end, g->n, g->scan_tmp, g->d_err, kErrArg, s);
-  if (e == hipSuccess) e = launch_records(g->n, g->rp, nullptr, item_end, g->rec, s);
-  if (e == hipSuccess && g->n > 0)
-    e = hipMemcpyAsync(g->d_meta + 1, item_end + (g->n - 1), sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+  const int64_t cap = items_cap(g->n, g->nnz);
+  uint32_t* err = (uint32_t*)(g->small + kWErr);
+  hipError_t e = launch_fill_u64(g->small, 0, kWords, s);
+  // item_sum holds the piece counts here, scanned into each row's item end
+  if (e == hipSuccess) e = launch_node_prep(g->n, g->nnz, g->rp, g->item_sum, g->guide_len, g->small, s);
+  if (e == hipSuccess) {
+    ScanSet set{};
+    set.data[0] = g->item_sum;
+    set.data[1] = g->guide_len;
+    set.tmp[0] = g->scan_tmp[0];
+    set.tmp[1] = g->scan_tmp[1];
+    set.total[0] = g->small + kWItems;
+    set.total[1] = g->small + kWGuideLen;
+    set.err_bit[0] = set.err_bit[1] = kErrArg;
+    set.count = 2;
+    e = launch_scans(set, g->n, err, s);
+  }
   if (e == hipSuccess)
-    e = launch_check_items(items_ub, g->d_meta, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR),
-                           g->d_err, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage + 1, g->d_meta, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-  dev_free(g->stream, item_end);
+    e = launch_items_records(g->n, g->rp, g->item_sum, g->guide_len, cap, g->items, g->rec, g->small, s);
+  if (e == hipSuccess)
+    e = launch_check_items(cap, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->small, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->small, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return status_of(e);
-  g->n_items = (int64_t)g->h_stage[1];
-  g->row_guide_len = (int64_t)g->h_stage[2];
-  if (g->n_items > items_ub) return MOSS_E_ARG;
-  bits = ((uint32_t*)g->h_stage)[0];
-  return (moss_status)validate_error_status(bits);
+  const uint64_t* h = g->h_stage;
+  uint32_t bits = (uint32_t)(h[kWErr] & 0xFFFFFFFFu);
+  if (bits) return (moss_status)validate_error_status(bits);
+  g->max_degree = (int32_t)h[kWMaxDeg];
+  g->n_items = (int64_t)h[kWItems];
+  g->row_guide_len = (int64_t)h[kWGuideLen];
+  if (g->n_items > cap) return MOSS_E_ARG;
+  if (!(g->flags & MOSS_TRUST_CSR) && 2 * h[kWUpper] != (uint64_t)g->nnz) return MOSS_E_ASYMMETRIC;
+  return MOSS_OK;
 }
 
 moss_status create_common(int32_t n, int64_t nnz, uint32_t flags, void* hip_stream, moss_graph** out,
@@ -323,15 +427,17 @@ moss_status moss_graph_create(int32_t n, int64_t nnz, const int32_t* row_ptr, co
   moss_status st = create_common(n, nnz, flags, hip_stream, out, &g);
   if (st != MOSS_OK) return st;
   DeviceScope scope(g->device);
-  st = dev_alloc(g->stream, &g->owned_rp, (size_t)n + 1);
-  if (st == MOSS_OK) st = dev_alloc(g->stream, &g->owned_col, (size_t)nnz);
+  const size_t rp_bytes = (((size_t)n + 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+  void* csr = nullptr;
+  st = dev_alloc_bytes(g->stream, &csr, rp_bytes + (size_t)nnz * sizeof(int32_t));
   if (st == MOSS_OK) {
+    g->owned_rp = at<int32_t>(csr, 0);
+    g->owned_col = at<int32_t>(csr, rp_bytes);
     hipError_t e = hipMemcpyAsync(g->owned_rp, row_ptr, ((size_t)n + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
                                   g->stream);
     if (e == hipSuccess && nnz > 0)
       e = hipMemcpyAsync(g->owned_col, col, (size_t)nnz * sizeof(int32_t), hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
-    st = status_of(e);
+    st = status_of(e);  // the checks below end in a synchronisation before the call returns
   }
   if (st == MOSS_OK) {
     g->rp = g->owned_rp;
@@ -442,96 +548,121 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   DeviceScope scope(g->device);
   if (!scope.ok()) return MOSS_E_DEVICE;
   const bool want4 = need & MOSS_TABLES_K4, want5 = need & MOSS_TABLES_K5;
-  const size_t n = (size_t)g->n, nnz = (size_t)g->nnz, G = ((size_t)1 << g->gbits) + 1;
+  const bool sig_ready = g->built != 0;  // ACC_sigma and its companions come with the first set
   moss_status st = MOSS_OK;
-  uint64_t bytes = 0;
-  if (!g->acc_sigma) {
-    st = dev_alloc(g->stream, &g->acc_sigma, nnz);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->sig_guide, (size_t)g->row_guide_len);
-    g->edge_bits = edge_hash_bits(g->nnz / 2);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->edge_slots, (size_t)1 << g->edge_bits);
-    bytes += nnz * 4;
+  if (!sig_ready) {
+    const SigLayout L = sig_layout(g);
+    st = dev_alloc_bytes(g->stream, &g->mem_sig, L.bytes);
+    if (st == MOSS_OK) {
+      g->acc_sigma = at<uint32_t>(g->mem_sig, L.acc_sigma);
+      g->sig_guide = at<uint32_t>(g->mem_sig, L.guide);
+      g->edge_slots = at<uint64_t>(g->mem_sig, L.slots);
+      g->filter = at<uint64_t>(g->mem_sig, L.filter);
+      g->edge_bits = edge_hash_bits(g->nnz / 2);
+      g->filter_bits = edge_filter_bits(g->nnz / 2);
+    }
   }
   if (st == MOSS_OK && want4) {
-    st = dev_alloc(g->stream, &g->acc_node[0], n);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->guide[0], G);
-    bytes += n * 8 + G * 4;
+    const NodeLayout L = node_layout(g, false);
+    st = dev_alloc_bytes(g->stream, &g->mem_k4, L.bytes);
+    if (st == MOSS_OK) {
+      g->acc_node[0] = at<uint64_t>(g->mem_k4, L.acc[0]);
+      g->guide[0] = at<uint32_t>(g->mem_k4, L.guide[0]);
+    }
   }
   if (st == MOSS_OK && want5) {
-    st = dev_alloc(g->stream, &g->acc_tau, nnz);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->tau_guide, (size_t)g->row_guide_len);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->acc_node[1], n);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->acc_node[2], n);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->guide[1], G);
-    if (st == MOSS_OK) st = dev_alloc(g->stream, &g->guide[2], G);
-    bytes += nnz * 8 + 2 * n * 8 + 2 * G * 4;
+    const NodeLayout L = node_layout(g, true);
+    st = dev_alloc_bytes(g->stream, &g->mem_k5, L.bytes);
+    if (st == MOSS_OK) {
+      g->acc_tau = at<uint64_t>(g->mem_k5, L.acc_tau);
+      g->tau_guide = at<uint32_t>(g->mem_k5, L.tau_guide);
+      for (int j = 0; j < 2; ++j) {
+        g->acc_node[1 + j] = at<uint64_t>(g->mem_k5, L.acc[j]);
+        g->guide[1 + j] = at<uint32_t>(g->mem_k5, L.guide[j]);
+      }
+    }
   }
   if (st != MOSS_OK) {
     free_tables(g, need);
     return st;
   }
   hipStream_t s = g->stream;
-  hipError_t e = launch_fill_u32(g->d_err, 0, 4, s);
-  if (e == hipSuccess) e = launch_fill_u64((uint64_t*)g->d_lambda, 0, 2, s);
-  if (e == hipSuccess && !g->sigma_ready) {
-    e = launch_row_prefix(false, g->n_items, g->items, g->rp, g->col, g->acc_sigma, nullptr, g->item_sum, g->scan_tmp,
-                          g->d_err, s);
-    if (e == hipSuccess) e = launch_records(g->n, g->rp, g->acc_sigma, nullptr, g->rec, s);
-    if (e == hipSuccess)
-      e = launch_row_guides(false, g->n_items, g->items, g->rp, g->rec, g->acc_sigma, nullptr, g->sig_guide, s);
-    if (e == hipSuccess)
-      e = launch_edge_hash(g->n_items, g->items, g->rp, g->col, g->edge_slots, g->edge_bits, g->d_err, s);
+  uint32_t* err = (uint32_t*)(g->small + kWErr);
+  // error bits, Lambdas and totals to zero; with the first set the hash set to empty
+  // keys and the filter to zero
+  FillSet f{};
+  f.p[0] = g->small + kWErr;
+  f.count[0] = kWLambda + 2;
+  f.p[1] = g->small + kWTotal;
+  f.count[1] = 3;
+  if (!sig_ready) {
+    f.p[2] = g->edge_slots;
+    f.count[2] = (int64_t)1 << g->edge_bits;
+    f.value[2] = ~0ull;
+    f.p[3] = g->filter;
+    f.count[3] = (int64_t)1 << g->filter_bits;
+  }
+  hipError_t e = launch_fill_set(f, s);
+  RowTables t{};
+  t.items = g->items;
+  t.rp = g->rp;
+  t.col = g->col;
+  t.acc_sigma = g->acc_sigma;
+  t.item_sum = g->item_sum;
+  t.rec = g->rec;
+  t.n_items = g->n_items;
+  t.hash_bits = g->edge_bits;
+  t.filter_bits = g->filter_bits;
+  if (e == hipSuccess && !sig_ready) {
+    t.guide = g->sig_guide;
+    t.slots = g->edge_slots;
+    t.filter = g->filter;
+    e = launch_row_tables(false, t, err, s);
   }
   if (e == hipSuccess && want5) {
-    e = launch_row_prefix(true, g->n_items, g->items, g->rp, g->col, g->acc_sigma, g->acc_tau, g->item_sum,
-                          g->scan_tmp, g->d_err, s);
-    if (e == hipSuccess)
-      e = launch_row_guides(true, g->n_items, g->items, g->rp, g->rec, nullptr, g->acc_tau, g->tau_guide, s);
+    t.acc_tau = g->acc_tau;
+    t.guide = g->tau_guide;
+    t.slots = nullptr;
+    t.filter = nullptr;
+    e = launch_row_tables(true, t, err, s);
   }
   if (e == hipSuccess)
-    e = launch_node_weights(g->n, g->rp, g->acc_sigma, want5 ? g->acc_tau : nullptr, want4 ? g->acc_node[0] : nullptr,
+    e = launch_node_weights(g->n, g->rp, g->rec, want5 ? g->acc_tau : nullptr, want4 ? g->acc_node[0] : nullptr,
                             want5 ? g->acc_node[1] : nullptr, want5 ? g->acc_node[2] : nullptr, g->partials,
-                            g->d_lambda, g->d_err, s);
-  for (int slot = 0; slot < 3 && e == hipSuccess; ++slot) {
-    const bool want = slot == 0 ? want4 : want5;
-    if (want)
-      e = launch_scan_inplace(g->acc_node[slot], (int64_t)n, g->scan_tmp, g->d_err,
-                              slot == 0 ? kErrOverflowK4 : kErrOverflowK5, s);
+                            (unsigned long long*)(g->small + kWLambda), err, s);
+  ScanSet scans{};
+  GuideSet guides{};
+  for (int slot = 0; slot < 3; ++slot) {
+    if (!(slot == 0 ? want4 : want5)) continue;
+    const int j = scans.count++;
+    scans.data[j] = g->acc_node[slot];
+    scans.tmp[j] = g->scan_tmp[j];
+    scans.err_bit[j] = slot == 0 ? kErrOverflowK4 : kErrOverflowK5;
+    guides.acc[j] = g->acc_node[slot];
+    guides.guide[j] = g->guide[slot];
+    guides.total[j] = g->small + kWTotal + slot;
+    guides.count = scans.count;
   }
-  for (int slot = 0; slot < 3 && e == hipSuccess; ++slot) {
-    const bool want = slot == 0 ? want4 : want5;
-    if (want) e = launch_guide(g->acc_node[slot], g->n, g->gbits, g->guide[slot], s);
-  }
-  // stage: [0] error bits, [1..3] totals, [4..5] Lambdas
+  if (e == hipSuccess) e = launch_scans(scans, g->n, err, s);
+  if (e == hipSuccess) e = launch_guides(guides, g->n, g->gbits, s);
   uint64_t* h = g->h_stage;
-  if (e == hipSuccess) e = hipMemcpyAsync(h, g->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-  for (int slot = 0; slot < 3 && e == hipSuccess; ++slot) {
-    const bool want = slot == 0 ? want4 : want5;
-    h[1 + slot] = 0;
-    if (want && n > 0)
-      e = hipMemcpyAsync(h + 1 + slot, g->acc_node[slot] + (n - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, s);
-  }
-  if (e == hipSuccess) e = hipMemcpyAsync(h + 4, g->d_lambda, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h, g->small, kWHits * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     free_tables(g, need);
     return status_of(e);
   }
-  const uint32_t bits = (uint32_t)(h[0] & 0xFFFFFFFFu);
+  const uint32_t bits = (uint32_t)(h[kWErr] & 0xFFFFFFFFu);
   if ((bits & kErrOverflow) || (want4 && (bits & kErrOverflowK4)) || (want5 && (bits & kErrOverflowK5))) {
     free_tables(g, need);
     return MOSS_E_OVERFLOW;
   }
-  g->sigma_ready = true;
-  for (int slot = 0; slot < 3; ++slot) {
-    const bool want = slot == 0 ? want4 : want5;
-    if (want) g->total[slot] = h[1 + slot];
-  }
-  g->lambda3 = h[4];
-  g->lambda4 = h[5];
+  for (int slot = 0; slot < 3; ++slot)
+    if (slot == 0 ? want4 : want5) g->total[slot] = g->n > 0 ? h[kWTotal + slot] : 0;
+  if (want4) g->lambda3 = h[kWLambda];
+  if (want5) g->lambda4 = h[kWLambda + 1];
   g->built |= need;
   g->table_bytes = table_bytes_needed(g, 0);
-  (void)bytes;
   return MOSS_OK;
 }
 
@@ -543,22 +674,12 @@ void moss::free_graph_tables(moss_graph* g, uint32_t mask) {
 
 // With mask = 0: the bytes held now.  Otherwise the bytes that building `mask` adds.
 uint64_t moss::table_bytes_needed(const moss_graph* g, uint32_t mask) {
-  const uint64_t n = (uint64_t)g->n, nnz = (uint64_t)g->nnz, G = (1ull << g->gbits) + 1;
-  const uint64_t rg = (uint64_t)g->row_guide_len * 4;
-  const uint64_t hash = 8ull << edge_hash_bits(g->nnz / 2);
-  const uint64_t k4 = n * 8 + G * 4, k5 = nnz * 8 + 2 * n * 8 + 2 * G * 4 + rg, sig = nnz * 4 + rg + hash;
-  if (mask == 0) {
-    uint64_t b = 0;
-    if (g->built) b += sig;
-    if (g->built & MOSS_TABLES_K4) b += k4;
-    if (g->built & MOSS_TABLES_K5) b += k5;
-    return b;
-  }
-  const uint32_t need = mask & ~g->built;
+  const uint64_t sig = sig_layout(g).bytes, k4 = node_layout(g, false).bytes, k5 = node_layout(g, true).bytes;
+  const uint32_t have = g->built, add = mask == 0 ? have : (mask & ~have);
   uint64_t b = 0;
-  if (need && !g->built) b += sig;
-  if (need & MOSS_TABLES_K4) b += k4;
-  if (need & MOSS_TABLES_K5) b += k5;
+  if (add && (mask == 0 || !have)) b += sig;
+  if (add & MOSS_TABLES_K4) b += k4;
+  if (add & MOSS_TABLES_K5) b += k5;
   return b;
 }
 
@@ -568,19 +689,20 @@ namespace {
 moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0, const uint64_t* k1, int count,
                          uint64_t seed, uint8_t* class_out, uint64_t hits[][22], double* device_ms) {
   hipStream_t s = g->stream;
-  hipError_t e = launch_fill_u64((uint64_t*)g->d_hits, 0, 2 * 22, s);
+  unsigned long long* d_hits = (unsigned long long*)(g->small + kWHits);
+  hipError_t e = launch_fill_u64(g->small + kWHits, 0, 2 * 22, s);
   if (e == hipSuccess) e = hipEventRecord(g->ev0, s);
   for (int i = 0; i < count && e == hipSuccess; ++i) {
     const int slot = sampler_slot(samplers[i]);
     if (g->total[slot] == 0 || k1[i] <= k0[i]) continue;
     int grid, block;
-    plain_launch_shape(g->device, samplers[i], k1[i] - k0[i], &grid, &block);
-    e = launch_sample(samplers[i], sampler_view(g, samplers[i]), seed, k0[i], k1[i], g->d_hits + 22 * i, class_out,
+    plain_launch_shape(g, samplers[i], k1[i] - k0[i], &grid, &block);
+    e = launch_sample(samplers[i], sampler_view(g, samplers[i]), seed, k0[i], k1[i], d_hits + 22 * i, class_out,
                       grid, block, s);
   }
   if (e == hipSuccess) e = hipEventRecord(g->ev1, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(g->h_stage, g->d_hits, 2 * 22 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(g->h_stage, d_hits, 2 * 22 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return status_of(e);
   for (int i = 0; i < count; ++i) std::memcpy(hits[i], g->h_stage + 22 * i, 22 * sizeof(uint64_t));

@@ -18,7 +18,7 @@ Tuning g_tuning;
 std::mutex g_runner_mu;
 std::map<int, std::unique_ptr<BatchRunner>> g_runners;
 
-constexpr uint32_t kDefaultTile = 16384;
+constexpr uint32_t kDefaultTile = 4096;
 }  // namespace
 
 Tuning current_tuning() {
@@ -199,7 +199,12 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   uint32_t T = tile_samples ? tile_samples : (tune.tile_samples ? tune.tile_samples : kDefaultTile);
   const int block = tune.threads_per_block ? (int)tune.threads_per_block : 256;
   int bpc = blocks_per_cu ? (int)blocks_per_cu : (int)tune.blocks_per_cu;
-  if (bpc == 0) bpc = std::max(1, std::min(8, sample_kernel_blocks_per_cu(0, block)));
+  if (bpc == 0) {  // by the largest graph of the batch (its tiles run together)
+    uint64_t most = 0;
+    for (const WorkItem& w : work) most = std::max(most, sampling_footprint(w.g));
+    const int cap = std::max(1, std::min(8, sample_kernel_blocks_per_cu(0, block)));
+    bpc = std::max(1, std::min(cap, sampling_waves_per_cu(most) / (block / 64)));
+  }
   const int grid = device_cus(device_) * bpc;
 
   // views: one per distinct (graph, sampler)
@@ -235,9 +240,19 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
       tiles.push_back({t, (b - a) * weight});
     }
   }
-  // costliest tiles first so the last tiles drawn from the counter are the short ones
-  std::stable_sort(tiles.begin(), tiles.end(),
-                   [](const PendingTile& x, const PendingTile& y) { return x.cost > y.cost; });
+  // Graph-major order: the tiles of one (graph, sampler) view run together, so at any
+  // moment the chip works on one graph's tables and they stay in L2 and the MALL
+  // (interleaving the graphs of a batch measured about 15% slower per sample).  The
+  // views with the most work go first; every view's partial tile comes last in it.
+  std::vector<uint64_t> view_cost(views.size(), 0);
+  for (const PendingTile& t : tiles) view_cost[t.t.view] += t.cost;
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const PendingTile& x, const PendingTile& y) {
+    if (x.t.view != y.t.view) {
+      const uint64_t cx = view_cost[x.t.view], cy = view_cost[y.t.view];
+      return cx != cy ? cx > cy : x.t.view < y.t.view;
+    }
+    return x.cost > y.cost;
+  });
   if (tiles.size() >= 0xFFFFFFFFull) return MOSS_E_ARG;
   moss_status st = reserve(views.size(), tiles.size(), n_slots);
   if (st != MOSS_OK) return st;
@@ -365,8 +380,8 @@ moss_status moss_get_tuning(moss_tuning* t) {
 
 moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best, double* best_ms) {
   if (!reqs || n <= 0 || !best) return MOSS_E_ARG;
-  static const uint32_t kTiles[] = {4096, 16384, 65536, 262144};
-  static const uint32_t kBpc[] = {2, 4, 8};
+  static const uint32_t kTiles[] = {2048, 4096, 16384, 65536};
+  static const uint32_t kBpc[] = {2, 3, 4, 5, 6, 8};
   std::vector<moss_result> ref((size_t)n), cur((size_t)n);
   moss_status st = batch_impl(reqs, n, ref.data(), nullptr, kDefaultTile, 4, nullptr);  // warm-up, reference
   if (st != MOSS_OK) return st;
@@ -374,8 +389,10 @@ moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best
   moss_tuning b{};
   for (uint32_t T : kTiles) {
     for (uint32_t bpc : kBpc) {
-      double ms = 0.0;
-      st = batch_impl(reqs, n, cur.data(), nullptr, T, bpc, &ms);
+      // the whole call: smaller tiles cost host time (tile list, staging) as well
+      const auto t0 = std::chrono::steady_clock::now();
+      st = batch_impl(reqs, n, cur.data(), nullptr, T, bpc, nullptr);
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       if (st != MOSS_OK) return st;
       for (int32_t i = 0; i < n; ++i)
         if (std::memcmp(cur[i].hits, ref[i].hits, sizeof(ref[i].hits)) != 0) return MOSS_E_DEVICE;

@@ -41,14 +41,14 @@ __device__ __forceinline__ void philox_block(uint64_t k, uint64_t blk, uint64_t 
 // floor(x * n / 2^64): a uniform index in [0, n) from one 64-bit word.
 __device__ __forceinline__ uint64_t bounded(uint64_t x, uint64_t n) { return __umul64hi(x, n); }
 
-// Smallest i in [lo, hi] with acc[i] > r, given acc[hi] > r (inverse CDF over an
+// Smallest i in [lo, hi] with value(i) > r, given value(hi) > r (inverse CDF over an
 // inclusive prefix; Section 4.1.3 "WeightRandomVertex", step 2).
-template <typename T>
-__device__ __forceinline__ int32_t first_above(const T* __restrict__ acc, int32_t lo, int32_t hi, uint64_t r) {
+template <typename F>
+__device__ __forceinline__ int32_t first_above_by(F value, int32_t lo, int32_t hi, uint64_t r) {
   int32_t n = hi - lo;
   while (n > 0) {
     const int32_t half = n >> 1;
-    if (static_cast<uint64_t>(acc[lo + half]) <= r) {
+    if (value(lo + half) <= r) {
       lo += half + 1;
       n -= half + 1;
     } else {
@@ -56,6 +56,11 @@ __device__ __forceinline__ int32_t first_above(const T* __restrict__ acc, int32_
     }
   }
   return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t first_above(const T* __restrict__ acc, int32_t lo, int32_t hi, uint64_t r) {
+  return first_above_by([acc](int32_t i) { return static_cast<uint64_t>(acc[i]); }, lo, hi, r);
 }
 
 // Is key in the sorted row col[base .. base+len)?
@@ -67,12 +72,6 @@ __device__ __forceinline__ bool row_has(const int32_t* __restrict__ col, int32_t
     n -= half;
   }
   return n == 1 && col[lo] == key;
-}
-
-// Edge test between a (row ra, length da) and b: search the shorter row.
-__device__ __forceinline__ bool adjacent(const int32_t* __restrict__ col, int32_t ra, int32_t da, int32_t a,
-                                         int32_t rb, int32_t db, int32_t b) {
-  return da <= db ? row_has(col, ra, da, b) : row_has(col, rb, db, a);
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -90,16 +89,40 @@ __device__ __forceinline__ uint64_t edge_slot(uint64_t key, int bits) {
   return (key * 0x9E3779B97F4A7C15ull) >> (64 - bits);
 }
 
-__device__ __forceinline__ bool edge_hash_has(const uint64_t* __restrict__ slots, int bits, int32_t a, int32_t b) {
-  const uint64_t key = edge_key(a, b), mask = (1ull << bits) - 1;
-  uint64_t h = edge_slot(key, bits);
-  for (uint64_t i = 0; i <= mask; ++i) {
+// Settles a lookup of `key` whose home slot h held `first`: found, absent (an empty
+// slot ends the probe sequence) or, rarely, more slots to walk.
+__device__ __forceinline__ bool edge_hash_rest(const uint64_t* __restrict__ slots, int bits, uint64_t key, uint64_t h,
+                                               uint64_t first) {
+  if (first == key) return true;
+  if (first == kEmptySlot) return false;
+  const uint64_t mask = (1ull << bits) - 1;
+  for (uint64_t i = 1; i <= mask; ++i) {
+    h = (h + 1) & mask;
     const uint64_t x = slots[h];
     if (x == key) return true;
     if (x == kEmptySlot) return false;
-    h = (h + 1) & mask;
   }
   return false;
+}
+
+// ---- edge filter: a blocked Bloom filter in front of the hash set ----
+// Every edge sets 4 bits of one 64-bit word.  A pair whose 4 bits are not all set
+// is certainly not an edge, so most non-edges are settled by one read of a table
+// of 1-2 bytes per edge, small enough to stay in L2 or the MALL; the others and
+// every edge go on to the hash set.  Word and bit positions come from the
+// splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) of the edge key.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t filter_word(uint64_t z, int fbits) { return z >> (64 - fbits); }
+
+__device__ __forceinline__ uint64_t filter_mask(uint64_t z) {
+  return (1ull << (z & 63)) | (1ull << ((z >> 6) & 63)) | (1ull << ((z >> 12) & 63)) | (1ull << ((z >> 18) & 63));
 }
 
 // Inclusive scan over the 64 lanes of a wave; `wrapped` is set on any 64-bit wrap.
@@ -120,6 +143,16 @@ __device__ __forceinline__ uint64_t wave_inclusive_scan(uint64_t x, bool& wrappe
 __device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_wrap(uint64_t x, bool& wrapped) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t z = x + __shfl_xor(x, off, 64);
+    wrapped |= z < x;
+    x = z;
+  }
   return x;
 }
 

@@ -20,9 +20,34 @@ struct moss_graph {
   int32_t* owned_col = nullptr;
   uint32_t flags = 0;
 
+  // Device memory comes in four stream-ordered blocks: per graph (word block, work
+  // items, node records, scan scratch), and per table set (ACC_sigma with its row
+  // guides, the edge hash set and filter; the MOSS-4 node table; the 5-node tables).
+  void* mem_graph = nullptr;
+  void* mem_sig = nullptr;
+  void* mem_k4 = nullptr;
+  void* mem_k5 = nullptr;
+
+  // per graph (mem_graph)
+  uint64_t* small = nullptr;             // kWords words shared with the kernels
+  uint64_t* items = nullptr;             // work items: rows cut into pieces of <= 256 entries
+  uint64_t* item_sum = nullptr;          // per-piece totals (at creation: piece counts)
+  uint64_t* guide_len = nullptr;         // n, row-guide lengths (creation only)
+  uint64_t* scan_tmp[3] = {};            // block sums of up to three scans
+  uint64_t* partials = nullptr;          // per-block Lambda partial sums
+  uint4* rec = nullptr;                  // per node: row start, degree, S_v, row-guide offset
+  int64_t n_items = 0;
+  int64_t row_guide_len = 0;             // entries of one row-guide array
+
   // sampling tables
   uint32_t* acc_sigma = nullptr;    // nnz
+  uint32_t* sig_guide = nullptr;    // row guides over ACC_sigma
+  uint64_t* edge_slots = nullptr;   // edge hash set for the induced-edge probes
+  uint64_t* filter = nullptr;       // edge filter in front of it
+  int edge_bits = 4;
+  int filter_bits = 1;
   uint64_t* acc_tau = nullptr;      // nnz
+  uint32_t* tau_guide = nullptr;    // row guides over ACC_tau
   uint64_t* acc_node[3] = {};       // n each: Gamma (MOSS-4), Gamma^(1) (T-5), Gamma^(2) (Path-5)
   uint32_t* guide[3] = {};          // 2^gbits + 1 each
   int gbits = 1;
@@ -30,26 +55,7 @@ struct moss_graph {
   uint64_t lambda3 = 0, lambda4 = 0;
   uint32_t built = 0;               // MOSS_TABLES_* bits
 
-  // work items of the O(|E|) kernels: rows cut into pieces of <= 256 entries
-  uint64_t* items = nullptr;             // n_items packed (row, piece)
-  uint64_t* item_sum = nullptr;          // n_items, per-piece totals / their scan
-  int64_t n_items = 0;
-  uint64_t* scan_tmp = nullptr;          // block sums of the scans
-  uint4* rec = nullptr;                  // per node: row start, degree, S_v, row-guide offset
-  int64_t row_guide_len = 0;             // entries of one row-guide array
-  uint32_t* sig_guide = nullptr;         // row guides over ACC_sigma
-  uint32_t* tau_guide = nullptr;         // row guides over ACC_tau
-  uint64_t* edge_slots = nullptr;        // edge hash set for the induced-edge probes
-  int edge_bits = 4;
-  uint64_t* partials = nullptr;          // per-block Lambda partial sums
-  bool sigma_ready = false;
-
-  // per-graph scratch
-  unsigned long long* d_hits = nullptr;  // 2 x 22
-  uint32_t* d_err = nullptr;             // error bits + max degree
-  uint64_t* d_meta = nullptr;            // [0] item count, [1] row-guide length
-  unsigned long long* d_lambda = nullptr;
-  uint64_t* h_stage = nullptr;           // pinned host staging, 64 words
+  uint64_t* h_stage = nullptr;      // pinned host staging, kWords words
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   std::atomic<int> busy{0};
@@ -90,8 +96,11 @@ void free_graph_tables(moss_graph* g, uint32_t mask);
 // Device bytes that building `mask` would add to the graph.
 uint64_t table_bytes_needed(const moss_graph* g, uint32_t mask);
 
-// Launch shape of the plain sampling kernel for `nsamples` samples.
-void plain_launch_shape(int device, int sampler, uint64_t nsamples, int* grid, int* block);
+// Launch shape of the plain sampling kernel for `nsamples` samples of graph g (the
+// process-wide tuning if set, else resident waves chosen by the graph's footprint).
+void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int* grid, int* block);
+int sampling_waves_per_cu(uint64_t footprint_bytes);
+uint64_t sampling_footprint(const moss_graph* g);
 
 struct Tuning {
   uint32_t tile_samples = 0;

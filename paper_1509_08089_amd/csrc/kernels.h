@@ -32,12 +32,25 @@ struct SamplerView {
   const uint32_t* sig_guide;  // row guides over ACC_sigma (rows with d >= kRowGuideMin)
   const uint32_t* tau_guide;  // row guides over ACC_tau (Path-5)
   const uint64_t* edge_slots; // edge hash set: 2^edge_bits slots, key min << 32 | max
+  const uint64_t* filter;     // edge filter: 2^filter_bits words of 64 bits
   uint64_t total;             // sum of the node weights
   int32_t n;
   int32_t gbits;
   int32_t edge_bits;
-  int32_t pad;
+  int32_t filter_bits;
 };
+
+// Per-graph block of 64-bit words shared by the kernels and the host (one copy back
+// per call instead of one per value).
+constexpr int kWErr = 0;       // error bits (u32, low half)
+constexpr int kWLambda = 2;    // Lambda_3, Lambda_4
+constexpr int kWItems = 4;     // number of work items
+constexpr int kWGuideLen = 5;  // entries of one row-guide array
+constexpr int kWUpper = 6;     // CSR entries (v, c) with c > v
+constexpr int kWMaxDeg = 7;    // largest degree
+constexpr int kWTotal = 8;     // totals of the Gamma, Gamma^(1), Gamma^(2) node weights
+constexpr int kWHits = 16;     // 2 x 22 hit counters of a plain estimate
+constexpr int kWords = 64;
 
 // Rows with at least this many entries get a guide table for their weighted picks.
 constexpr int32_t kRowGuideMin = 64;
@@ -57,54 +70,87 @@ hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], con
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
 
-hipError_t launch_check_rowptr(int32_t n, int64_t nnz, const int32_t* rp, uint32_t* err, hipStream_t s);
-// Work items: rows cut into pieces of at most 256 entries.  item_end (n u64) receives
-// the inclusive prefix of the piece counts; items (at most n + nnz/256 + 1 u64) the
-// packed (row, piece) pairs; the item count is item_end[n-1].
-hipError_t launch_items(int32_t n, const int32_t* rp, uint64_t* item_end, uint64_t* items, uint64_t* tmp,
-                        uint32_t* err, hipStream_t s);
-// n_items: device word holding the item count; max_items bounds it (grid size)
-hipError_t launch_check_items(int64_t max_items, const uint64_t* n_items, const uint64_t* items, int32_t n,
-                              const int32_t* rp, const int32_t* col, bool full, uint32_t* err, hipStream_t s);
+// Up to four fills of u64 ranges in one launch (unused entries: count 0).
+struct FillSet {
+  uint64_t* p[4];
+  int64_t count[4];
+  uint64_t value[4];
+};
+hipError_t launch_fill_set(const FillSet& f, hipStream_t s);
 
-// Row prefixes ACC_sigma (tau = false) or ACC_tau (tau = true, needs ACC_sigma);
-// item_sum holds n_items u64, tmp scan_tmp_elems(n_items) u64.
-hipError_t launch_row_prefix(bool tau, int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
-                             uint32_t* acc_sigma, uint64_t* acc_tau, uint64_t* item_sum, uint64_t* tmp, uint32_t* err,
-                             hipStream_t s);
+// In-place inclusive scans of up to three u64 arrays of length n in one set of
+// launches.  tmp[j] must hold scan_tmp_elems(n) u64; a wrap sets err_bit[j] in *err;
+// total[j] (may be null) receives the array's total.
+struct ScanSet {
+  uint64_t* data[3];
+  uint64_t* tmp[3];
+  uint64_t* total[3];
+  uint32_t err_bit[3];
+  int count;
+};
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scans(const ScanSet& set, int64_t n, uint32_t* err, hipStream_t s);
 
-// Row guides.  row_guide_sizes: per node the guide length (0, or 2^g + 1 with
-// g = floor(log2 d) - 1 when d >= kRowGuideMin) into sizes (n u64, scanned in place
-// afterwards by the caller into inclusive ends).  records: rec[v] = {row start,
-// degree, S_v, guide offset}.  row_guides: fills the guides of ACC_sigma (tau=false)
-// or ACC_tau (tau=true); goff_end is the scanned sizes array.
-hipError_t launch_row_guide_sizes(int32_t n, const int32_t* rp, uint64_t* sizes, hipStream_t s);
-hipError_t launch_records(int32_t n, const int32_t* rp, const uint32_t* acc_sigma, const uint64_t* goff_end,
-                          uint4* rec, hipStream_t s);
-hipError_t launch_row_guides(bool tau, int64_t n_items, const uint64_t* items, const int32_t* rp, const uint4* rec,
-                             const uint32_t* acc_sigma, const uint64_t* acc_tau, uint32_t* guide, hipStream_t s);
+// ---- graph creation (CSR validation and work items) ----
+// Work items: every row cut into pieces of at most 256 entries; items_cap =
+// n + nnz / 256 + 1 bounds their number for any row_ptr.
+int64_t items_cap(int32_t n, int64_t nnz);
+// Per node: row_ptr checks (monotone, rp[0] = 0, rp[n] = nnz: kErrArg), largest degree
+// (small[kWMaxDeg]), piece count into item_cnt and row-guide length into guide_len.
+hipError_t launch_node_prep(int32_t n, int64_t nnz, const int32_t* rp, uint64_t* item_cnt, uint64_t* guide_len,
+                            uint64_t* small, hipStream_t s);
+// After item_end (scanned piece counts) and goff_end (scanned guide lengths): the packed
+// (row, piece) items and the node records {row start, degree, 0, row-guide offset}.
+// Both do nothing once row_ptr has been rejected.
+hipError_t launch_items_records(int32_t n, const int32_t* rp, const uint64_t* item_end, const uint64_t* goff_end,
+                                int64_t cap, uint64_t* items, uint4* rec, uint64_t* small, hipStream_t s);
+// Column range; with `full` also self-loops, strict ascent and the mirror of every entry
+// (v, c) with c > v; counts those entries into small[kWUpper].
+hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
+                              bool full, uint64_t* small, hipStream_t s);
 
-// Edge hash set over the undirected edges (slots: 2^bits u64, filled with the empty
-// key first); bits is chosen by the caller so that the load factor stays low.
+// ---- table build ----
+// Row prefixes ACC_sigma (tau = false) or ACC_tau (tau = true, after ACC_sigma), their
+// row guides, and with ACC_sigma the node records' S_v and the edge hash set and filter
+// (filled with empty keys and zeros beforehand).  item_sum holds n_items u64.
+struct RowTables {
+  const uint64_t* items;
+  const int32_t* rp;
+  const int32_t* col;
+  uint32_t* acc_sigma;
+  uint64_t* acc_tau;
+  uint64_t* item_sum;
+  uint4* rec;
+  uint32_t* guide;
+  uint64_t* slots;
+  uint64_t* filter;
+  int64_t n_items;
+  int32_t hash_bits;
+  int32_t filter_bits;
+};
+hipError_t launch_row_tables(bool tau, const RowTables& t, uint32_t* err, hipStream_t s);
+
+// Edge hash set size (2^bits u64 slots for m edges, load factor <= 0.4) and edge
+// filter size (2^bits 64-bit words, bits >= 1).
 int edge_hash_bits(int64_t m);
-hipError_t launch_edge_hash(int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
-                            uint64_t* slots, int bits, uint32_t* err, hipStream_t s);
+int edge_filter_bits(int64_t m);
 
-// Node weights (any output may be null) and Lambda_3, Lambda_4 into lambdas[0..1];
-// partials must hold 2 * node_weight_blocks(n) u64.
+// Node weights (any output may be null) from the node records' S_v and the ACC_tau row
+// ends, and Lambda_3, Lambda_4 into lambdas[0..1]; partials must hold
+// 2 * node_weight_blocks(n) u64.
 int node_weight_blocks(int32_t n);
-hipError_t launch_node_weights(int32_t n, const int32_t* rp, const uint32_t* acc_sigma, const uint64_t* acc_tau,
+hipError_t launch_node_weights(int32_t n, const int32_t* rp, const uint4* rec, const uint64_t* acc_tau,
                                uint64_t* w_gamma, uint64_t* w_gamma1, uint64_t* w_gamma2, uint64_t* partials,
                                unsigned long long* lambdas, uint32_t* err, hipStream_t s);
 
-// In-place inclusive scan of u64[n]; `tmp` must hold scan_tmp_elems(n) u64; a wrap
-// sets `err_bit` in *err.
-int64_t scan_tmp_elems(int64_t n);
-hipError_t launch_scan_inplace(uint64_t* data, int64_t n, uint64_t* tmp, uint32_t* err, uint32_t err_bit,
-                               hipStream_t s);
-
-// The total is read on the device (acc[n-1]).
-hipError_t launch_guide(const uint64_t* acc, int32_t n, int gbits, uint32_t* guide, hipStream_t s);
+// Node-draw guides of up to three scanned weight arrays; total[j] receives acc[j][n-1].
+struct GuideSet {
+  const uint64_t* acc[3];
+  uint32_t* guide[3];
+  uint64_t* total[3];
+  int count;
+};
+hipError_t launch_guides(const GuideSet& set, int32_t n, int gbits, hipStream_t s);
 
 // Plain sampling launch: samples [k0, k1) of one sampler, hits[22] accumulated.
 hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,

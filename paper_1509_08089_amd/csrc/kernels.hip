@@ -1,17 +1,22 @@
 // HIP kernels of the Moss hot path for gfx950 (CDNA4, wave64).
 //
+// Graph creation (Section 2: an undirected simple graph as sorted CSR):
+//   k_node_prep        row_ptr checks, largest degree, work-item and row-guide sizes
+//   k_items_records    work items (rows cut into pieces) and node records
+//   k_check_items      column range, self-loops, strict ascent, symmetry
 // Table build (Section 4.1.3 "Initialization", O(|E|)):
-//   k_check_rowptr / k_check_cols   CSR validation (Section 2: undirected simple graph)
-//   k_row_tables                    one wave per node: ACC_sigma, ACC_tau row prefixes,
-//                                   Gamma_v, Gamma^(1)_v, Gamma^(2)_v, Lambda_3, Lambda_4
-//   k_scan_*                        node-level inclusive prefixes ACC_Gamma*
-//   k_guide                         search windows for the node draw
+//   k_prefix_local     each piece's local prefix of ACC_sigma or ACC_tau
+//   k_row_finish       stitches the pieces of a row, writes its row guide, S_v, and
+//                      (with ACC_sigma) inserts its edges into the hash set and filter
+//   k_node_weights     Gamma_v, Gamma^(1)_v, Gamma^(2)_v, Lambda_3, Lambda_4
+//   k_scan_*           node-level inclusive prefixes ACC_Gamma*
+//   k_guides           search windows for the node draws
 // Sampling (Algorithms 1, 3, 4):
-//   k_sample<S>                     grid-stride loop, one sample per lane per step,
-//                                   per-wave LDS histograms flushed with u64 atomics
-//   k_batch                         persistent kernel draining a tile list of many
-//                                   (graph, sampler, sample range) requests
-//   k_sample_nodes<S>               the same draw for chosen sample indices, with nodes
+//   k_sample<S>        grid-stride loop, one sample per lane per step,
+//                      per-wave LDS histograms flushed with u64 atomics
+//   k_batch            persistent kernel draining a tile list of many
+//                      (graph, sampler, sample range) requests
+//   k_sample_nodes<S>  the same draw for chosen sample indices, with nodes
 //
 // All counting is integer; a sample's outcome depends only on (graph, seed, sampler,
 // sample index), never on which lane, block or launch draws it.
@@ -39,6 +44,16 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t value, int64_t count) {
     p[i] = value;
 }
 
+// blockIdx.y selects the range
+__global__ void k_fill_set(FillSet f) {
+  const int j = blockIdx.y;
+  uint64_t* p = f.p[j];
+  const int64_t count = f.count[j];
+  const uint64_t value = f.value[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
 static int fill_grid(int64_t count) {
   int64_t g = (count + 255) / 256;
   if (g < 1) g = 1;
@@ -58,14 +73,19 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream
   return hipGetLastError();
 }
 
+hipError_t launch_fill_set(const FillSet& f, hipStream_t s) {
+  int64_t most = 0;
+  for (int j = 0; j < 4; ++j) most = std::max(most, f.count[j]);
+  if (most <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_set, dim3(fill_grid(most), 4), dim3(256), 0, s, f);
+  return hipGetLastError();
+}
+
 __device__ __forceinline__ uint64_t add_wrap(uint64_t a, uint64_t b, bool& wrapped) {
   const uint64_t z = a + b;
   wrapped |= z < a;
   return z;
 }
-
-hipError_t launch_scan_inplace(uint64_t* data, int64_t n, uint64_t* tmp, uint32_t* err, uint32_t err_bit,
-                               hipStream_t s);
 
 hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], const uint8_t lut5p[64]) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lut4), lut4, 8);
@@ -75,31 +95,13 @@ hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], con
   return hipMemcpyToSymbol(HIP_SYMBOL(c_lut5p), lut5p, 64);
 }
 
-// ---------------------------------------------------------------------------------
-// CSR validation.  row_ptr is checked first (its own launch), so that the column
-// checks only index rows that lie inside col[].
-// ---------------------------------------------------------------------------------
-__global__ void k_check_rowptr(int32_t n, int64_t nnz, const int32_t* __restrict__ rp, uint32_t* err) {
-  uint32_t bad = 0, dmax = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t d = rp[v + 1] - rp[v];
-    if (d < 0) bad = kErrArg;
-    else dmax = max(dmax, (uint32_t)d);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) bad = kErrArg;
-  bad = wave_or(bad);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, 64));
-  if (lane_id() == 0) {
-    if (bad) atomicOr(err, bad);
-    if (dmax) atomicMax(err + 1, dmax);
-  }
-}
-
-// err[0] receives error bits, err[1] the largest degree.
-hipError_t launch_check_rowptr(int32_t n, int64_t nnz, const int32_t* rp, uint32_t* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_rowptr, dim3(fill_grid(n > 0 ? n : 1)), dim3(256), 0, s, n, nnz, rp, err);
-  return hipGetLastError();
+// Grids of the node- and item-parallel kernels that end in one atomic per block:
+// enough blocks to fill the chip, few enough that the atomics do not queue up.
+static int reduce_grid(int64_t units, int64_t per_block) {
+  int64_t g = (units + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > 2048) g = 2048;
+  return (int)g;
 }
 
 // ---------------------------------------------------------------------------------
@@ -107,32 +109,95 @@ hipError_t launch_check_rowptr(int32_t n, int64_t nnz, const int32_t* rp, uint32
 // and each item is handled by one wave, so no wave walks a long row alone: the
 // costliest row (a hub with tens of thousands of neighbours) becomes many items
 // that run concurrently.  items[i] packs (row << 32 | piece index within the row).
-// Per-row quantities that span pieces are stitched with a scan over item totals.
 // ---------------------------------------------------------------------------------
 constexpr int32_t kItem = 256;
 
-__global__ void k_item_count(int32_t n, const int32_t* __restrict__ rp, uint64_t* __restrict__ cnt) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-    cnt[v] = (uint64_t)((rp[v + 1] - rp[v] + kItem - 1) / kItem);
+int64_t items_cap(int32_t n, int64_t nnz) { return (int64_t)n + nnz / kItem + 1; }
+
+// Row guides (used by the weighted picks inside a row, see row_pick): rows with
+// d >= kRowGuideMin get 2^g + 1 entries, g = floor(log2 d) - 1.
+__device__ __forceinline__ int row_guide_bits(int32_t d) { return 31 - __clz(d) - 1; }
+
+__device__ __forceinline__ uint64_t row_guide_len(int32_t d) {
+  return d >= kRowGuideMin ? (1ull << row_guide_bits(d)) + 1 : 0ull;
 }
 
-// item_end[v] = inclusive prefix of the piece counts
-__global__ void k_item_fill(int32_t n, const int32_t* __restrict__ rp, const uint64_t* __restrict__ item_end,
-                            uint64_t* __restrict__ items) {
+__device__ __forceinline__ int row_guide_shift(uint64_t total, int g) {
+  const int bl = total ? 64 - __clzll((long long)total) : 0;
+  return bl > g ? bl - g : 0;
+}
+
+// ---------------------------------------------------------------------------------
+// CSR validation and layout at creation.  k_node_prep checks row_ptr; the kernels
+// after it read the error word first and do nothing once row_ptr is rejected, so
+// no row range outside col[] is ever read and no item is written past the cap.
+// ---------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_node_prep(int32_t n, int64_t nnz, const int32_t* __restrict__ rp,
+                                                   uint64_t* __restrict__ item_cnt, uint64_t* __restrict__ guide_len,
+                                                   uint64_t* small) {
+  __shared__ uint32_t s_bad, s_max;
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    s_max = 0;
+  }
+  __syncthreads();
+  uint32_t bad = 0, dmax = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t c = (uint64_t)((rp[v + 1] - rp[v] + kItem - 1) / kItem);
-    const uint64_t first = item_end[v] - c;
-    for (uint64_t j = 0; j < c; ++j) items[first + j] = (uint64_t)v << 32 | j;
+    int64_t d = (int64_t)rp[v + 1] - (int64_t)rp[v];
+    if (d < 0) {
+      bad = kErrArg;
+      d = 0;
+    }
+    if (d > nnz) d = nnz;
+    dmax = max(dmax, (uint32_t)d);
+    item_cnt[v] = (uint64_t)((d + kItem - 1) / kItem);
+    guide_len[v] = row_guide_len((int32_t)d);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (rp[0] != 0 || (int64_t)rp[n] != nnz)) bad = kErrArg;
+  bad = wave_or(bad);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dmax = max(dmax, (uint32_t)__shfl_xor((int)dmax, off, 64));
+  if (lane_id() == 0) {
+    if (bad) atomicOr(&s_bad, bad);
+    if (dmax) atomicMax(&s_max, dmax);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_bad) atomicOr((uint32_t*)(small + kWErr), s_bad);
+    if (s_max) atomicMax((unsigned long long*)(small + kWMaxDeg), (unsigned long long)s_max);
   }
 }
 
-hipError_t launch_items(int32_t n, const int32_t* rp, uint64_t* item_end, uint64_t* items, uint64_t* tmp,
-                        uint32_t* err, hipStream_t s) {
+hipError_t launch_node_prep(int32_t n, int64_t nnz, const int32_t* rp, uint64_t* item_cnt, uint64_t* guide_len,
+                            uint64_t* small, hipStream_t s) {
+  hipLaunchKernelGGL(k_node_prep, dim3(reduce_grid(n, 1024)), dim3(256), 0, s, n, nnz, rp, item_cnt, guide_len, small);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ bool rowptr_rejected(const uint64_t* small) {
+  return (*(const volatile uint32_t*)(small + kWErr) & kErrArg) != 0;
+}
+
+// item_end / goff_end: inclusive prefixes of the piece counts and guide lengths
+__global__ void k_items_records(int32_t n, const int32_t* __restrict__ rp, const uint64_t* __restrict__ item_end,
+                                const uint64_t* __restrict__ goff_end, int64_t cap, uint64_t* __restrict__ items,
+                                uint4* __restrict__ rec, const uint64_t* small) {
+  if (rowptr_rejected(small)) return;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r0 = rp[v], d = rp[v + 1] - r0;
+    const uint64_t c = (uint64_t)((d + kItem - 1) / kItem);
+    const uint64_t first = item_end[v] - c;
+    for (uint64_t j = 0; j < c; ++j)
+      if (first + j < (uint64_t)cap) items[first + j] = (uint64_t)v << 32 | j;
+    rec[v] = make_uint4((uint32_t)r0, (uint32_t)d, 0u, (uint32_t)(goff_end[v] - row_guide_len(d)));
+  }
+}
+
+hipError_t launch_items_records(int32_t n, const int32_t* rp, const uint64_t* item_end, const uint64_t* goff_end,
+                                int64_t cap, uint64_t* items, uint4* rec, uint64_t* small, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_item_count, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, item_end);
-  hipError_t e = launch_scan_inplace(item_end, n, tmp, err, kErrArg, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_item_fill, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, item_end, items);
+  hipLaunchKernelGGL(k_items_records, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, item_end, goff_end, cap, items, rec,
+                     small);
   return hipGetLastError();
 }
 
@@ -160,16 +225,27 @@ __device__ __forceinline__ ItemRange item_range(const uint64_t* __restrict__ ite
   return r;
 }
 
-// Column range, self-loops, strict ascent (sorted, no repeats) and symmetry (v must
-// appear in the row of each of its neighbours).
-__global__ __launch_bounds__(256) void k_check_items(const uint64_t* __restrict__ n_items_p,
-                                                     const uint64_t* __restrict__ items, int32_t n,
+// Column range, self-loops, strict ascent (sorted, no repeats) and symmetry.  Only
+// entries (v, c) with c > v look for their mirror (v in the row of c); with repeats
+// excluded, those mirrors are distinct entries with c < v, so the graph is
+// symmetric exactly when every one is found and they are half of all entries
+// (the host compares the count in small[kWUpper] with nnz).
+__global__ __launch_bounds__(256) void k_check_items(int64_t cap, const uint64_t* __restrict__ items, int32_t n,
                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                     int full, uint32_t* err) {
+                                                     int full, uint64_t* small) {
+  __shared__ uint32_t s_bad, s_skip;
+  __shared__ unsigned long long s_upper;
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    s_upper = 0;
+    s_skip = rowptr_rejected(small) ? 1u : 0u;  // read once, so the whole block leaves together
+  }
+  __syncthreads();
+  if (s_skip) return;
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t n_items = (int64_t)*n_items_p;
-  uint32_t bad = 0;
+  const int64_t n_items = min((int64_t)small[kWItems], cap);
+  uint32_t bad = 0, upper = 0;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
     const ItemRange it = item_range(items, rp, i);
     for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
@@ -185,164 +261,192 @@ __global__ __launch_bounds__(256) void k_check_items(const uint64_t* __restrict_
         if (p == c) bad |= kErrDuplicate;
         else if (p > c) bad |= kErrUnsorted;
       }
-      const int32_t rc = rp[c];
-      if (!row_has(col, rc, rp[c + 1] - rc, it.v)) bad |= kErrAsymmetric;
+      if (c > it.v) {
+        ++upper;
+        const int32_t rc = rp[c];
+        if (!row_has(col, rc, rp[c + 1] - rc, it.v)) bad |= kErrAsymmetric;
+      }
     }
   }
   bad = wave_or(bad);
-  if (lane == 0 && bad) atomicOr(err, bad);
+  const uint64_t wu = wave_sum((uint64_t)upper);
+  if (lane == 0) {
+    if (bad) atomicOr(&s_bad, bad);
+    if (wu) atomicAdd(&s_upper, (unsigned long long)wu);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_bad) atomicOr((uint32_t*)(small + kWErr), s_bad);
+    if (s_upper) atomicAdd((unsigned long long*)(small + kWUpper), s_upper);
+  }
 }
 
-hipError_t launch_check_items(int64_t max_items, const uint64_t* n_items, const uint64_t* items, int32_t n,
-                              const int32_t* rp, const int32_t* col, bool full, uint32_t* err, hipStream_t s) {
-  if (max_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_check_items, dim3(item_grid(max_items)), dim3(256), 0, s, n_items, items, n, rp, col,
-                     full ? 1 : 0, err);
+hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
+                              bool full, uint64_t* small, hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_items, dim3(reduce_grid(cap, 4)), dim3(256), 0, s, cap, items, n, rp, col, full ? 1 : 0,
+                     small);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
 // Row prefixes (Section 4.1.3 ACC_sigma = ACC_mu of Section 5.1.5; the tau prefix of
-// Section 5.1.2), in three steps per table:
-//   local  each item scans its own entries and writes its total to item_sum
-//   scan   inclusive scan of item_sum (in place)
-//   fix    every later piece of a row adds the totals of the row's earlier pieces
+// Section 5.1.2), in two steps per table:
+//   local   each item scans its own entries and writes its total to item_sum
+//   finish  each item adds the totals of its row's earlier pieces (at most a few
+//           hundred, summed by the wave), then writes its share of the row guide;
+//           the ACC_sigma pass also records S_v and inserts the edges into the hash
+//           set and the filter
 // ACC_sigma entries are (d_x - 1) of the neighbours; ACC_tau entries are
 // (d_x - 1)(S_v - (d_x - 1)) with S_v the row total of ACC_sigma.
 // ---------------------------------------------------------------------------------
 template <bool TAU>
-__global__ __launch_bounds__(256) void k_prefix_local(int64_t n_items, const uint64_t* __restrict__ items,
-                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                      uint32_t* __restrict__ acc_sigma, uint64_t* __restrict__ acc_tau,
-                                                      uint64_t* __restrict__ item_sum) {
+__global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   bool wrapped = false;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
-    const ItemRange it = item_range(items, rp, i);
-    uint64_t S = 0;
-    if (TAU) S = acc_sigma[it.r1 - 1];
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
+    const ItemRange it = item_range(t.items, t.rp, i);
+    const uint64_t S = TAU ? (uint64_t)t.rec[it.v].z : 0ull;
     uint64_t carry = 0;
     for (int32_t e0 = it.e0; e0 < it.e1; e0 += 64) {
       const int32_t e = e0 + lane;
       uint64_t x = 0;
       if (e < it.e1) {
-        if (TAU) {
-          const uint64_t dx = (uint64_t)acc_sigma[e] - (e > it.r0 ? (uint64_t)acc_sigma[e - 1] : 0ull);
+        if (TAU) {  // the sigma entry d_x - 1, from the finished ACC_sigma
+          const uint64_t dx = (uint64_t)t.acc_sigma[e] - (e > it.r0 ? (uint64_t)t.acc_sigma[e - 1] : 0ull);
           x = dx * (S - dx);
         } else {
-          const int32_t c = col[e];
-          x = (uint64_t)(rp[c + 1] - rp[c] - 1);
+          const int32_t c = t.col[e];
+          x = (uint64_t)(t.rp[c + 1] - t.rp[c] - 1);
         }
       }
-      const uint64_t s = wave_inclusive_scan(x, wrapped) + carry;
+      const uint64_t s = add_wrap(wave_inclusive_scan(x, wrapped), carry, wrapped);
       if (e < it.e1) {
-        if (TAU) acc_tau[e] = s;
-        else acc_sigma[e] = (uint32_t)s;
+        if (TAU) t.acc_tau[e] = s;
+        else t.acc_sigma[e] = (uint32_t)s;
       }
       carry = __shfl(s, 63, 64);
     }
-    if (lane == 0) item_sum[i] = carry;
+    if (lane == 0) t.item_sum[i] = carry;
   }
-  (void)wrapped;  // row totals are checked in the fix step
+  // a wrap inside a tau row is a Gamma^(2)_v beyond 64 bits; sigma pieces cannot wrap
+  if (TAU && __ballot(wrapped) != 0 && lane == 0) atomicOr(err, kErrOverflowK5);
 }
 
 template <bool TAU>
-__global__ __launch_bounds__(256) void k_prefix_fix(int64_t n_items, const uint64_t* __restrict__ items,
-                                                    const int32_t* __restrict__ rp,
-                                                    const uint64_t* __restrict__ item_incl, uint32_t* __restrict__ acc_sigma,
-                                                    uint64_t* __restrict__ acc_tau, uint32_t* err) {
+__global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  bool over = false;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
-    const ItemRange it = item_range(items, rp, i);
-    const int64_t first = i - it.piece;  // the row's first item
-    const uint64_t before_row = first > 0 ? item_incl[first - 1] : 0;
-    if (it.e1 == it.r1 && !TAU) {
-      // last piece: the row total S_v must fit the 32-bit ACC_sigma
-      over |= item_incl[i] - before_row > 0xFFFFFFFFull;
+  const uint64_t hmask = (1ull << t.hash_bits) - 1;
+  bool over = false, full = false;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
+    const ItemRange it = item_range(t.items, t.rp, i);
+    const int32_t d = it.r1 - it.r0;
+    const int64_t first = i - it.piece, end = first + (d + kItem - 1) / kItem;
+    // totals of the row's pieces before this one, and of the whole row
+    bool wrapped = false;
+    uint64_t before = 0, rest = 0;
+    for (int64_t j = first + lane; j < end; j += 64) {
+      const uint64_t x = t.item_sum[j];
+      if (j < i) before = add_wrap(before, x, wrapped);
+      else rest = add_wrap(rest, x, wrapped);
     }
-    if (it.piece == 0) continue;
-    const uint64_t off = item_incl[i - 1] - before_row;
-    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
-      if (TAU) acc_tau[e] += off;
-      else acc_sigma[e] += (uint32_t)off;
-    }
-  }
-  if (__ballot(over) != 0 && lane == 0) atomicOr(err, kErrOverflow);
-}
-
-hipError_t launch_row_prefix(bool tau, int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
-                             uint32_t* acc_sigma, uint64_t* acc_tau, uint64_t* item_sum, uint64_t* tmp, uint32_t* err,
-                             hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  const dim3 grid(item_grid(n_items)), block(256);
-  if (tau) hipLaunchKernelGGL(k_prefix_local<true>, grid, block, 0, s, n_items, items, rp, col, acc_sigma, acc_tau, item_sum);
-  else hipLaunchKernelGGL(k_prefix_local<false>, grid, block, 0, s, n_items, items, rp, col, acc_sigma, acc_tau, item_sum);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // the sum of every row's tau total is Gamma^(2): a wrap there is a 5-node overflow
-  e = launch_scan_inplace(item_sum, n_items, tmp, err, tau ? kErrOverflowK5 : kErrOverflow, s);
-  if (e != hipSuccess) return e;
-  if (tau) hipLaunchKernelGGL(k_prefix_fix<true>, grid, block, 0, s, n_items, items, rp, item_sum, acc_sigma, acc_tau, err);
-  else hipLaunchKernelGGL(k_prefix_fix<false>, grid, block, 0, s, n_items, items, rp, item_sum, acc_sigma, acc_tau, err);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------------
-// Edge hash set for the induced-edge probes (the CIS() of Algorithms 1, 3, 4): each
-// undirected edge is inserted once (from its smaller endpoint's row) with a 64-bit
-// compare-and-swap, linear probing.  The table has at least 2.5 slots per edge, so a
-// lookup reads about 1.2-1.4 slots.  Every loop is bounded by the table size.
-// ---------------------------------------------------------------------------------
-int edge_hash_bits(int64_t m) {
-  int bits = 4;
-  while (bits < 40 && (double)(1ll << bits) < 2.5 * (double)m) ++bits;
-  return bits;
-}
-
-__global__ __launch_bounds__(256) void k_edge_hash(int64_t n_items, const uint64_t* __restrict__ items,
-                                                   const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                   unsigned long long* __restrict__ slots, int bits, uint32_t* err) {
-  const int lane = lane_id();
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const uint64_t mask = (1ull << bits) - 1;
-  bool full = false;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
-    const ItemRange it = item_range(items, rp, i);
-    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
-      const int32_t c = col[e];
-      if (c <= it.v) continue;  // each edge once, from its smaller endpoint
-      const uint64_t key = edge_key(it.v, c);
-      uint64_t h = edge_slot(key, bits);
-      uint64_t probes = 0;
-      for (;;) {
-        const unsigned long long old = atomicCAS(&slots[h], (unsigned long long)kEmptySlot, (unsigned long long)key);
-        if (old == kEmptySlot || old == key) break;
-        h = (h + 1) & mask;
-        if (++probes > mask) {
-          full = true;
-          break;
+    before = wave_sum_wrap(before, wrapped);
+    const uint64_t total = add_wrap(before, wave_sum_wrap(rest, wrapped), wrapped);
+    over |= TAU ? wrapped : total > 0xFFFFFFFFull;
+    const bool guided = d >= kRowGuideMin;
+    const int g = guided ? row_guide_bits(d) : 0;
+    const int sh = guided ? row_guide_shift(total, g) : 0;
+    uint32_t* gd = guided ? t.guide + t.rec[it.v].w : nullptr;
+    uint64_t carry = before;  // the finished prefix just before this 64-entry chunk
+    for (int32_t e0 = it.e0; e0 < it.e1; e0 += 64) {
+      const int32_t e = e0 + lane;
+      const bool in = e < it.e1;
+      uint64_t hi = carry;
+      int32_t c = 0;
+      if (in) {
+        if (TAU) {
+          hi = t.acc_tau[e] + before;
+          if (before) t.acc_tau[e] = hi;
+        } else {
+          c = t.col[e];
+          hi = (uint64_t)t.acc_sigma[e] + before;
+          if (before) t.acc_sigma[e] = (uint32_t)hi;
+        }
+      }
+      uint64_t lo = __shfl_up(hi, 1, 64);
+      if (lane == 0) lo = carry;
+      carry = __shfl(hi, 63, 64);
+      if (in && guided) {
+        // entry e answers the buckets whose lower bound b * 2^sh lies in [lo, hi);
+        // the last entry also those at or above the total
+        const uint64_t b0 = lo ? ((lo - 1) >> sh) + 1 : 0ull;
+        uint64_t b1 = hi ? ((hi - 1) >> sh) + 1 : 0ull;
+        if (e == it.r1 - 1) b1 = (1ull << g) + 1;
+        for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - it.r0);
+      }
+      if (!TAU && in && c > it.v) {  // each undirected edge once, from its smaller endpoint
+        const uint64_t key = edge_key(it.v, c);
+        const uint64_t z = mix64(key);
+        atomicOr((unsigned long long*)&t.filter[filter_word(z, t.filter_bits)], (unsigned long long)filter_mask(z));
+        uint64_t h = edge_slot(key, t.hash_bits);
+        for (uint64_t probes = 0;; ++probes) {
+          const unsigned long long old =
+              atomicCAS((unsigned long long*)&t.slots[h], (unsigned long long)kEmptySlot, (unsigned long long)key);
+          if (old == kEmptySlot || old == key) break;
+          h = (h + 1) & hmask;
+          if (probes >= hmask) {
+            full = true;
+            break;
+          }
         }
       }
     }
+    if (!TAU && it.e1 == it.r1 && lane == 0) t.rec[it.v].z = (uint32_t)total;
   }
-  if (__ballot(full) != 0 && lane == 0) atomicOr(err, kErrOverflow);
+  const bool any_over = __ballot(over) != 0, any_full = __ballot(full) != 0;
+  if (lane == 0 && (any_over || any_full))
+    atomicOr(err, (any_over ? (TAU ? kErrOverflowK5 : kErrOverflow) : 0u) | (any_full ? kErrOverflow : 0u));
 }
 
-hipError_t launch_edge_hash(int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
-                            uint64_t* slots, int bits, uint32_t* err, hipStream_t s) {
-  hipError_t e = launch_fill_u64(slots, kEmptySlot, 1ll << bits, s);
-  if (e != hipSuccess || n_items <= 0) return e;
-  hipLaunchKernelGGL(k_edge_hash, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, rp, col,
-                     (unsigned long long*)slots, bits, err);
+hipError_t launch_row_tables(bool tau, const RowTables& t, uint32_t* err, hipStream_t s) {
+  if (t.n_items <= 0) return hipSuccess;
+  const dim3 grid(item_grid(t.n_items)), block(256);
+  if (tau) hipLaunchKernelGGL(k_prefix_local<true>, grid, block, 0, s, t, err);
+  else hipLaunchKernelGGL(k_prefix_local<false>, grid, block, 0, s, t, err);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (tau) hipLaunchKernelGGL(k_row_finish<true>, grid, block, 0, s, t, err);
+  else hipLaunchKernelGGL(k_row_finish<false>, grid, block, 0, s, t, err);
   return hipGetLastError();
+}
+
+// Edge hash set: open addressing with linear probing, at least 2.5 slots per edge,
+// so a lookup reads about 1.2-1.4 slots.
+constexpr double kHashSlotsPerEdge = 2.5;
+
+int edge_hash_bits(int64_t m) {
+  int bits = 4;
+  while (bits < 40 && (double)(1ll << bits) < kHashSlotsPerEdge * (double)m) ++bits;
+  return bits;
+}
+
+// Edge filter: 2^bits 64-bit words with at least kFilterBitsPerEdge bits per edge.
+// A sparse filter wins: at 4 bits per edge about 16% of non-edges get through to the
+// hash set, but the filter is small enough (0.5 MB for a million edges) to stay in
+// L2; denser filters (8-16 bits) measured slower on every workload tried.
+constexpr double kFilterBitsPerEdge = 4.0;
+
+int edge_filter_bits(int64_t m) {
+  int bits = 1;
+  while (bits < 34 && (double)(64ll << bits) < kFilterBitsPerEdge * (double)m) ++bits;
+  return bits;
 }
 
 // ---------------------------------------------------------------------------------
 // Node weights, one thread per node, from the finished row prefixes:
-//   S_v = ACC_sigma at the row end;  Gamma_v = (d_v - 1) S_v  (Section 4.1.1)
+//   S_v = the row total of ACC_sigma (node record);  Gamma_v = (d_v - 1) S_v  (Section 4.1.1)
 //   Gamma^(1)_v = (d_v - 1)(d_v - 2) S_v                      (Section 5.1.1)
 //   Gamma^(2)_v = ACC_tau at the row end = S_v^2 - sum (d_x - 1)^2 (Section 5.1.2)
 //   Lambda_3 = sum C(d_v, 3), Lambda_4 = sum C(d_v, 4)        (Table 1)
@@ -352,7 +456,7 @@ hipError_t launch_edge_hash(int64_t n_items, const uint64_t* items, const int32_
 constexpr int kWeightThreads = 256;
 
 __global__ __launch_bounds__(256) void k_node_weights(int32_t n, const int32_t* __restrict__ rp,
-                                                      const uint32_t* __restrict__ acc_sigma,
+                                                      const uint4* __restrict__ rec,
                                                       const uint64_t* __restrict__ acc_tau, uint64_t* __restrict__ w_gamma,
                                                       uint64_t* __restrict__ w_gamma1, uint64_t* __restrict__ w_gamma2,
                                                       uint64_t* __restrict__ partials, uint32_t* err) {
@@ -364,7 +468,7 @@ __global__ __launch_bounds__(256) void k_node_weights(int32_t n, const int32_t* 
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r0 = rp[v], r1 = rp[v + 1];
     const uint64_t d = (uint64_t)(r1 - r0);
-    const uint64_t S = d > 0 ? (uint64_t)acc_sigma[r1 - 1] : 0;
+    const uint64_t S = (uint64_t)rec[v].z;
     if (w_gamma) w_gamma[v] = d >= 1 ? (d - 1) * S : 0;
     if (w_gamma1) {
       const uint64_t dd = d >= 2 ? (d - 1) * (d - 2) : 0;
@@ -441,25 +545,26 @@ __global__ __launch_bounds__(256) void k_lambda_final(const uint64_t* __restrict
 
 int node_weight_blocks(int32_t n) { return std::max(1, std::min(2048, (int)((n + 255) / 256))); }
 
-hipError_t launch_node_weights(int32_t n, const int32_t* rp, const uint32_t* acc_sigma, const uint64_t* acc_tau,
+hipError_t launch_node_weights(int32_t n, const int32_t* rp, const uint4* rec, const uint64_t* acc_tau,
                                uint64_t* w_gamma, uint64_t* w_gamma1, uint64_t* w_gamma2, uint64_t* partials,
                                unsigned long long* lambdas, uint32_t* err, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int nb = node_weight_blocks(n);
-  hipLaunchKernelGGL(k_node_weights, dim3(nb), dim3(kWeightThreads), 0, s, n, rp, acc_sigma, acc_tau, w_gamma,
+  hipLaunchKernelGGL(k_node_weights, dim3(nb), dim3(kWeightThreads), 0, s, n, rp, rec, acc_tau, w_gamma,
                      w_gamma1, w_gamma2, partials, err);
   hipLaunchKernelGGL(k_lambda_final, dim3(1), dim3(256), 0, s, partials, nb, lambdas, err);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------
-// Inclusive scan of u64 node arrays (reduce, scan of block sums, apply), blocked
-// layout of 8 items per thread, wrap detection on every addition.
+// Inclusive scans of u64 node arrays (reduce, scan of block sums, apply), blocked
+// layout of 8 items per thread, wrap detection on every addition.  Up to three
+// arrays of the same length go through one set of launches (blockIdx.y, or the
+// block index of the middle step, selects the array).
 // ---------------------------------------------------------------------------------
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int64_t kScanTile = kScanThreads * kScanItems;
-
 
 // Scans one tile in place (inclusive or exclusive), starting from `offset`; returns
 // the tile total.  Must be called by all 256 threads.
@@ -493,9 +598,10 @@ __device__ uint64_t block_scan_tile(uint64_t* data, int64_t base, int64_t n, uin
   return total;
 }
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint64_t* __restrict__ in, int64_t n,
-                                                     uint64_t* __restrict__ sums, uint32_t* err, uint32_t err_bit) {
+__global__ __launch_bounds__(256) void k_scan_reduce(ScanSet set, int64_t n, uint32_t* err) {
   __shared__ uint64_t wave_tot[kScanThreads / 64];
+  const int j = blockIdx.y;
+  const uint64_t* __restrict__ in = set.data[j];
   bool wrapped = false;
   const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint64_t t = 0;
@@ -507,40 +613,43 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint64_t* __restrict_
   if (threadIdx.x == 0) {
     uint64_t total = 0;
     for (int w = 0; w < kScanThreads / 64; ++w) total = add_wrap(total, wave_tot[w], wrapped);
-    sums[blockIdx.x] = total;
+    set.tmp[j][blockIdx.x] = total;
   }
-  if (__ballot(wrapped) != 0 && lane_id() == 0) atomicOr(err, err_bit);
+  if (__ballot(wrapped) != 0 && lane_id() == 0) atomicOr(err, set.err_bit[j]);
 }
 
-// Exclusive scan of the block sums by one block, tile after tile.
-__global__ __launch_bounds__(256) void k_scan_top(uint64_t* sums, int64_t nb, uint32_t* err, uint32_t err_bit) {
+// Exclusive scan of one array's block sums by one block, tile after tile; the
+// carry at the end is the array's total.
+__global__ __launch_bounds__(256) void k_scan_top(ScanSet set, int64_t nb, uint32_t* err) {
   __shared__ uint64_t wave_tot[kScanThreads / 64];
+  const int j = blockIdx.x;
   bool wrapped = false;
   uint64_t carry = 0;
   for (int64_t base = 0; base < nb; base += kScanTile) {
-    const uint64_t tot = block_scan_tile(sums, base, nb, carry, true, wrapped, wave_tot);
+    const uint64_t tot = block_scan_tile(set.tmp[j], base, nb, carry, true, wrapped, wave_tot);
     carry = add_wrap(carry, tot, wrapped);
   }
-  if (__ballot(wrapped) != 0 && lane_id() == 0) atomicOr(err, err_bit);
+  if (threadIdx.x == 0 && set.total[j]) *set.total[j] = carry;
+  if (__ballot(wrapped) != 0 && lane_id() == 0) atomicOr(err, set.err_bit[j]);
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(uint64_t* data, int64_t n, const uint64_t* __restrict__ offsets,
-                                                    uint32_t* err, uint32_t err_bit) {
+__global__ __launch_bounds__(256) void k_scan_apply(ScanSet set, int64_t n, uint32_t* err) {
   __shared__ uint64_t wave_tot[kScanThreads / 64];
+  const int j = blockIdx.y;
   bool wrapped = false;
-  block_scan_tile(data, (int64_t)blockIdx.x * kScanTile, n, offsets[blockIdx.x], false, wrapped, wave_tot);
-  if (__ballot(wrapped) != 0 && lane_id() == 0) atomicOr(err, err_bit);
+  block_scan_tile(set.data[j], (int64_t)blockIdx.x * kScanTile, n, set.tmp[j][blockIdx.x], false, wrapped, wave_tot);
+  if (__ballot(wrapped) != 0 && lane_id() == 0) atomicOr(err, set.err_bit[j]);
 }
 
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-hipError_t launch_scan_inplace(uint64_t* data, int64_t n, uint64_t* tmp, uint32_t* err, uint32_t err_bit,
-                               hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_scans(const ScanSet& set, int64_t n, uint32_t* err, hipStream_t s) {
+  if (n <= 0 || set.count <= 0) return hipSuccess;
+  if (set.count > 3) return hipErrorInvalidValue;
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp, err, err_bit);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, err, err_bit);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp, err, err_bit);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb, set.count), dim3(kScanThreads), 0, s, set, n, err);
+  hipLaunchKernelGGL(k_scan_top, dim3(set.count), dim3(kScanThreads), 0, s, set, nb, err);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb, set.count), dim3(kScanThreads), 0, s, set, n, err);
   return hipGetLastError();
 }
 
@@ -550,9 +659,13 @@ hipError_t launch_scan_inplace(uint64_t* data, int64_t n, uint64_t* tmp, uint32_
 // monotone in the word, so every word of bucket b picks a node in
 // [guide[b], guide[b+1]], and the search runs over that window only.
 // ---------------------------------------------------------------------------------
-__global__ void k_guide(const uint64_t* __restrict__ acc, int32_t n, int gbits, uint32_t* __restrict__ guide) {
+__global__ void k_guides(GuideSet set, int32_t n, int gbits) {
+  const int j = blockIdx.y;
+  const uint64_t* __restrict__ acc = set.acc[j];
+  uint32_t* __restrict__ guide = set.guide[j];
   const int64_t G = 1ll << gbits;
   const uint64_t total = acc[n - 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && set.total[j]) *set.total[j] = total;
   if (total == 0) return;  // nothing can be drawn; the guide is never read
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= G; b += (int64_t)gridDim.x * blockDim.x) {
     if (b == G) {
@@ -564,114 +677,39 @@ __global__ void k_guide(const uint64_t* __restrict__ acc, int32_t n, int gbits, 
   }
 }
 
-hipError_t launch_guide(const uint64_t* acc, int32_t n, int gbits, uint32_t* guide, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_guides(const GuideSet& set, int32_t n, int gbits, hipStream_t s) {
+  if (n <= 0 || set.count <= 0) return hipSuccess;
+  if (set.count > 3) return hipErrorInvalidValue;
   const int64_t G = (1ll << gbits) + 1;
-  hipLaunchKernelGGL(k_guide, dim3(fill_grid(G)), dim3(256), 0, s, acc, n, gbits, guide);
+  hipLaunchKernelGGL(k_guides, dim3(fill_grid(G), set.count), dim3(256), 0, s, set, n, gbits);
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------------
-// Node records and row guides.  A weighted pick inside a row (sigma, mu, tau) is a
-// search for the first entry of the row's prefix above a value x < total.  For rows
-// with d >= kRowGuideMin the value range is cut into 2^g buckets of width 2^s
-// (g = floor(log2 d) - 1, s = max(0, bitlen(total) - g)); guide[b] is the first
-// entry above b * 2^s, and guide[2^g] = d - 1.  A value x in bucket b = x >> s has
-// its answer in [guide[b], guide[b+1]], a window of about two entries.  The pick is
-// the same entry as the plain binary search; only the number of reads changes.
-// ---------------------------------------------------------------------------------
-__device__ __forceinline__ int row_guide_bits(int32_t d) { return 31 - __clz(d) - 1; }
-
-__device__ __forceinline__ int row_guide_shift(uint64_t total, int g) {
-  const int bl = total ? 64 - __clzll((long long)total) : 0;
-  return bl > g ? bl - g : 0;
-}
-
-__global__ void k_row_guide_sizes(int32_t n, const int32_t* __restrict__ rp, uint64_t* __restrict__ sizes) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t d = rp[v + 1] - rp[v];
-    sizes[v] = d >= kRowGuideMin ? (1ull << row_guide_bits(d)) + 1 : 0ull;
-  }
-}
-
-hipError_t launch_row_guide_sizes(int32_t n, const int32_t* rp, uint64_t* sizes, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_guide_sizes, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, sizes);
-  return hipGetLastError();
-}
-
-// With goff_end: writes whole records (S_v = 0 when acc_sigma is null).  Without:
-// only refreshes S_v of existing records.
-__global__ void k_records(int32_t n, const int32_t* __restrict__ rp, const uint32_t* __restrict__ acc_sigma,
-                          const uint64_t* __restrict__ goff_end, uint4* __restrict__ rec) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r0 = rp[v], r1 = rp[v + 1], d = r1 - r0;
-    const uint32_t S = (acc_sigma && d > 0) ? acc_sigma[r1 - 1] : 0u;
-    if (goff_end) {
-      const uint64_t size = d >= kRowGuideMin ? (1ull << row_guide_bits(d)) + 1 : 0ull;
-      rec[v] = make_uint4((uint32_t)r0, (uint32_t)d, S, (uint32_t)(goff_end[v] - size));
-    } else {
-      rec[v].z = S;
-    }
-  }
-}
-
-hipError_t launch_records(int32_t n, const int32_t* rp, const uint32_t* acc_sigma, const uint64_t* goff_end, uint4* rec,
-                          hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_records, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, acc_sigma, goff_end, rec);
-  return hipGetLastError();
-}
-
-// One wave per work item: entry i of the row covers the buckets whose lower bound
-// lies in [ACC[i-1], ACC[i]); the last entry also covers the buckets at or above the
-// total.
-template <typename T>
-__global__ __launch_bounds__(256) void k_row_guides(int64_t n_items, const uint64_t* __restrict__ items,
-                                                    const int32_t* __restrict__ rp, const uint4* __restrict__ rec,
-                                                    const T* __restrict__ acc, uint32_t* __restrict__ guide) {
-  const int lane = lane_id();
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
-    const ItemRange it = item_range(items, rp, i);
-    const int32_t d = it.r1 - it.r0;
-    if (d < kRowGuideMin) continue;
-    const int g = row_guide_bits(d);
-    const uint64_t total = acc[it.r1 - 1];
-    const int s = row_guide_shift(total, g);
-    const uint64_t last_bucket = 1ull << g;
-    uint32_t* gd = guide + rec[it.v].w;
-    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
-      const uint64_t lo = e > it.r0 ? (uint64_t)acc[e - 1] : 0ull, hi = (uint64_t)acc[e];
-      const uint64_t b0 = lo ? ((lo - 1) >> s) + 1 : 0ull;
-      uint64_t b1 = hi ? ((hi - 1) >> s) + 1 : 0ull;
-      if (e == it.r1 - 1) b1 = last_bucket + 1;
-      for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - it.r0);
-    }
-  }
-}
-
-hipError_t launch_row_guides(bool tau, int64_t n_items, const uint64_t* items, const int32_t* rp, const uint4* rec,
-                             const uint32_t* acc_sigma, const uint64_t* acc_tau, uint32_t* guide, hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  if (tau)
-    hipLaunchKernelGGL(k_row_guides<uint64_t>, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, rp, rec,
-                       acc_tau, guide);
-  else
-    hipLaunchKernelGGL(k_row_guides<uint32_t>, dim3(item_grid(n_items)), dim3(256), 0, s, n_items, items, rp, rec,
-                       acc_sigma, guide);
-  return hipGetLastError();
-}
-
-// Weighted pick in a row: the first entry of acc[0..d) above x (x < total = acc[d-1]).
-template <typename T>
-__device__ __forceinline__ int32_t row_pick(const T* __restrict__ acc, int32_t d, uint64_t total, uint64_t x,
+// Weighted pick in a row: the first entry i of the row whose inclusive prefix
+// value(i) exceeds x (x < total = value(d-1)).
+template <typename F>
+__device__ __forceinline__ int32_t row_pick(F value, int32_t d, uint64_t total, uint64_t x,
                                             const uint32_t* __restrict__ guide, uint32_t goff) {
-  if (d < kRowGuideMin) return first_above(acc, 0, d - 1, x);
+  if (d < kRowGuideMin) return first_above_by(value, 0, d - 1, x);
   const int g = row_guide_bits(d);
   const uint64_t b = x >> row_guide_shift(total, g);
   const uint32_t* gd = guide + goff;
-  return first_above(acc, (int32_t)gd[b], (int32_t)gd[b + 1], x);
+  return first_above_by(value, (int32_t)gd[b], (int32_t)gd[b + 1], x);
+}
+
+struct PrefixOf32 {
+  const uint32_t* __restrict__ acc;
+  __device__ uint64_t operator()(int32_t i) const { return (uint64_t)acc[i]; }
+};
+
+struct PrefixOf64 {
+  const uint64_t* __restrict__ acc;
+  __device__ uint64_t operator()(int32_t i) const { return acc[i]; }
+};
+
+// row start and degree of a node (the first half of its record)
+__device__ __forceinline__ uint2 row_of(const uint4* __restrict__ rec, int32_t x) {
+  return *reinterpret_cast<const uint2*>(rec + x);
 }
 
 // ---------------------------------------------------------------------------------
@@ -693,9 +731,26 @@ __device__ __forceinline__ int32_t neighbour_except(const int32_t* __restrict__ 
   return x >= skip ? col[ra + j + 1] : x;
 }
 
-// row start and degree of a node (the first half of its record)
-__device__ __forceinline__ uint2 row_of(const uint4* __restrict__ rec, int32_t x) {
-  return *reinterpret_cast<const uint2*>(rec + x);
+// Induced-edge probes of one sample (the CIS() step of Algorithms 1, 3 and 4): bit i
+// of the result is set when {x[i], y[i]} is an edge.  A pair the filter turns away is
+// no edge; the others are looked up in the hash set.  The pairs go one after another:
+// the empty asm statement keeps the compiler from hoisting later pairs' reads above
+// earlier ones, which measured a few per cent faster than issuing all of a sample's
+// reads at once (the memory system is already saturated by the other waves).
+template <int P>
+__device__ __forceinline__ int probe_edges(const SamplerView& a, const int32_t (&x)[P], const int32_t (&y)[P]) {
+  int m = 0;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    asm volatile("" ::: "memory");
+    const uint64_t key = edge_key(x[i], y[i]);
+    const uint64_t z = mix64(key);
+    const uint64_t fm = filter_mask(z);
+    if ((a.filter[filter_word(z, a.filter_bits)] & fm) != fm) continue;
+    const uint64_t h = edge_slot(key, a.edge_bits);
+    if (edge_hash_rest(a.edge_slots, a.edge_bits, key, h, a.edge_slots[h])) m |= 1 << i;
+  }
+  return m;
 }
 
 // MOSS-4 (Algorithm 1): v ~ Gamma_v, u ~ d_u - 1 over N_v, w uniform in N_v - {u},
@@ -709,7 +764,7 @@ __device__ __forceinline__ int draw_moss4(const SamplerView& a, const uint8_t* l
   const int32_t v = pick_node(a, W[0]);
   const uint4 R = a.rec[v];
   const int32_t rv = (int32_t)R.x, dv = (int32_t)R.y;
-  const int32_t iu = row_pick(a.acc_sigma + rv, dv, R.z, bounded(W[1], R.z), a.sig_guide, R.w);
+  const int32_t iu = row_pick(PrefixOf32{a.acc_sigma + rv}, dv, R.z, bounded(W[1], R.z), a.sig_guide, R.w);
   const int32_t u = col[rv + iu];
   int32_t iw = (int32_t)bounded(W[2], (uint64_t)(dv - 1));
   iw += iw >= iu;
@@ -721,11 +776,8 @@ __device__ __forceinline__ int draw_moss4(const SamplerView& a, const uint8_t* l
     nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = -1;
   }
   if (r == w) return 0;
-  const uint64_t* __restrict__ hs = a.edge_slots;
-  const int hb = a.edge_bits;
-  const int m = (int)edge_hash_has(hs, hb, u, w) | (int)edge_hash_has(hs, hb, v, r) << 1 |
-                (int)edge_hash_has(hs, hb, w, r) << 2;
-  return lut[m];
+  const int32_t px[3] = {u, v, w}, py[3] = {w, r, r};
+  return lut[probe_edges<3>(a, px, py)];
 }
 
 // T-5 (Algorithm 3): v ~ Gamma^(1)_v, u ~ d_u - 1 over N_v, w then r uniform over
@@ -741,7 +793,7 @@ __device__ __forceinline__ int draw_t5(const SamplerView& a, const uint8_t* lut,
   const int32_t v = pick_node(a, W[0]);
   const uint4 R = a.rec[v];
   const int32_t rv = (int32_t)R.x, dv = (int32_t)R.y;
-  const int32_t iu = row_pick(a.acc_sigma + rv, dv, R.z, bounded(W[1], R.z), a.sig_guide, R.w);
+  const int32_t iu = row_pick(PrefixOf32{a.acc_sigma + rv}, dv, R.z, bounded(W[1], R.z), a.sig_guide, R.w);
   const int32_t u = col[rv + iu];
   int32_t iw = (int32_t)bounded(W[2], (uint64_t)(dv - 1));
   iw += iw >= iu;
@@ -758,12 +810,8 @@ __device__ __forceinline__ int draw_t5(const SamplerView& a, const uint8_t* lut,
     nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = t;
   }
   if (t == w || t == r) return 0;
-  const uint64_t* __restrict__ hs = a.edge_slots;
-  const int hb = a.edge_bits;
-  const int m = (int)edge_hash_has(hs, hb, u, w) | (int)edge_hash_has(hs, hb, u, r) << 1 |
-                (int)edge_hash_has(hs, hb, w, r) << 2 | (int)edge_hash_has(hs, hb, v, t) << 3 |
-                (int)edge_hash_has(hs, hb, w, t) << 4 | (int)edge_hash_has(hs, hb, r, t) << 5;
-  return lut[m];
+  const int32_t px[6] = {u, u, w, v, w, r}, py[6] = {w, r, r, t, t, t};
+  return lut[probe_edges<6>(a, px, py)];
 }
 
 // Path-5 (Algorithm 4): v ~ Gamma^(2)_v, u ~ tau^(v) (row prefix ACC_tau), w ~ mu^(v,u)
@@ -782,7 +830,7 @@ __device__ __forceinline__ int draw_path5(const SamplerView& a, const uint8_t* l
   const int32_t rv = (int32_t)R.x, dv = (int32_t)R.y;
   const uint64_t* __restrict__ tau = a.acc_tau + rv;
   const uint64_t T = tau[dv - 1];
-  const int32_t iu = row_pick(tau, dv, T, bounded(W[1], T), a.tau_guide, R.w);
+  const int32_t iu = row_pick(PrefixOf64{tau}, dv, T, bounded(W[1], T), a.tau_guide, R.w);
   const int32_t u = col[rv + iu];
   const uint32_t* __restrict__ sig = a.acc_sigma + rv;
   const uint64_t Sv = R.z;
@@ -790,7 +838,7 @@ __device__ __forceinline__ int draw_path5(const SamplerView& a, const uint8_t* l
   const uint64_t du1 = (uint64_t)sig[iu] - blk_lo;
   uint64_t x = bounded(W[2], Sv - du1);
   x += x >= blk_lo ? du1 : 0;
-  const int32_t iw = row_pick(sig, dv, Sv, x, a.sig_guide, R.w);
+  const int32_t iw = row_pick(PrefixOf32{sig}, dv, Sv, x, a.sig_guide, R.w);
   const int32_t w = col[rv + iw];
   const uint2 U = row_of(a.rec, u), Wr = row_of(a.rec, w);
   const int32_t ru = (int32_t)U.x, du = (int32_t)U.y, rw = (int32_t)Wr.x, dw = (int32_t)Wr.y;
@@ -800,12 +848,8 @@ __device__ __forceinline__ int draw_path5(const SamplerView& a, const uint8_t* l
     nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = t;
   }
   if (t == u || r == w || t == r) return 0;
-  const uint64_t* __restrict__ hs = a.edge_slots;
-  const int hb = a.edge_bits;
-  const int m = (int)edge_hash_has(hs, hb, v, r) | (int)edge_hash_has(hs, hb, v, t) << 1 |
-                (int)edge_hash_has(hs, hb, u, w) << 2 | (int)edge_hash_has(hs, hb, u, t) << 3 |
-                (int)edge_hash_has(hs, hb, w, r) << 4 | (int)edge_hash_has(hs, hb, r, t) << 5;
-  return lut[m];
+  const int32_t px[6] = {v, v, u, u, w, r}, py[6] = {r, t, w, t, r, t};
+  return lut[probe_edges<6>(a, px, py)];
 }
 
 template <int S>

@@ -180,6 +180,11 @@ def test_validation_errors_on_gpu():
     bad(np.array([0, 1, 2], np.int32), np.array([0, 0], np.int32), moss.MOSS_E_SELF_LOOP)
     bad(np.array([0, 2, 4], np.int32), np.array([1, 1, 0, 0], np.int32), moss.MOSS_E_DUPLICATE)
     bad(np.array([0, 1, 1], np.int32), np.array([1], np.int32), moss.MOSS_E_ASYMMETRIC)
+    # symmetry: a lower entry without its mirror; as many upper as lower entries but a
+    # mirror missing; every upper entry mirrored but one lower entry too many
+    bad(np.array([0, 0, 1], np.int32), np.array([0], np.int32), moss.MOSS_E_ASYMMETRIC)
+    bad(np.array([0, 1, 1, 1, 2], np.int32), np.array([1, 2], np.int32), moss.MOSS_E_ASYMMETRIC)
+    bad(np.array([0, 1, 2, 3], np.int32), np.array([1, 0, 0], np.int32), moss.MOSS_E_ASYMMETRIC)
     bad(np.array([0, 1, 1], np.int32), np.array([5], np.int32), moss.MOSS_E_ARG)
     bad(np.array([0, 2, 1], np.int32), np.array([1, 0], np.int32), moss.MOSS_E_ARG)
     bad(np.array([1, 2, 2], np.int32), np.array([1, 0], np.int32), moss.MOSS_E_ARG)
