@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_check_items(int64_t cap, const uint64_t
       if (c > it.v) {
         ++upper;
         const int32_t rc = rp[c];
-        if (!row_has(col, rc, rp[c + 1] - rc, it.v)) bad |= kErrAsymmetric;
+        if (!row_has_near(col, rc, rp[c + 1] - rc, it.v, n)) bad |= kErrAsymmetric;
       }
     }
   }
@@ -693,8 +693,8 @@ __device__ __forceinline__ int32_t row_pick(F value, int32_t d, uint64_t total, 
   if (d < kRowGuideMin) return first_above_by(value, 0, d - 1, x);
   const int g = row_guide_bits(d);
   const uint64_t b = x >> row_guide_shift(total, g);
-  const uint32_t* gd = guide + goff;
-  return first_above_by(value, (int32_t)gd[b], (int32_t)gd[b + 1], x);
+  const uint2 w = load_pair(guide + goff + b);  // guide[b], guide[b + 1]
+  return first_above_by(value, (int32_t)w.x, (int32_t)w.y, x);
 }
 
 struct PrefixOf32 {
@@ -719,7 +719,8 @@ __device__ __forceinline__ uint2 row_of(const uint4* __restrict__ rec, int32_t x
 __device__ __forceinline__ int32_t pick_node(const SamplerView& a, uint64_t x) {
   const uint64_t r = bounded(x, a.total);
   const uint32_t b = (uint32_t)(x >> (64 - a.gbits));
-  return first_above(a.acc_node, (int32_t)a.guide[b], (int32_t)a.guide[b + 1], r);
+  const uint2 w = load_pair(a.guide + b);  // guide[b], guide[b + 1]
+  return first_above(a.acc_node, (int32_t)w.x, (int32_t)w.y, r);
 }
 
 // RandomVertex(N_a - {skip}) with skip in N_a: index j uniform over the row with
@@ -727,8 +728,8 @@ __device__ __forceinline__ int32_t pick_node(const SamplerView& a, uint64_t x) {
 __device__ __forceinline__ int32_t neighbour_except(const int32_t* __restrict__ col, int32_t ra, int32_t da,
                                                     int32_t skip, uint64_t word) {
   const int32_t j = (int32_t)bounded(word, (uint64_t)(da - 1));
-  const int32_t x = col[ra + j];
-  return x >= skip ? col[ra + j + 1] : x;
+  const uint2 x = load_pair(col + ra + j);  // j + 1 <= da - 1: both inside the row
+  return (int32_t)x.x >= skip ? (int32_t)x.y : (int32_t)x.x;
 }
 
 // Induced-edge probes of one sample (the CIS() step of Algorithms 1, 3 and 4): bit i
@@ -834,8 +835,16 @@ __device__ __forceinline__ int draw_path5(const SamplerView& a, const uint8_t* l
   const int32_t u = col[rv + iu];
   const uint32_t* __restrict__ sig = a.acc_sigma + rv;
   const uint64_t Sv = R.z;
-  const uint64_t blk_lo = iu > 0 ? sig[iu - 1] : 0;
-  const uint64_t du1 = (uint64_t)sig[iu] - blk_lo;
+  uint64_t blk_lo, blk_hi;  // u's block of ACC_sigma: [sig[iu - 1], sig[iu])
+  if (iu > 0) {
+    const uint2 s2 = load_pair(sig + iu - 1);
+    blk_lo = s2.x;
+    blk_hi = s2.y;
+  } else {
+    blk_lo = 0;
+    blk_hi = sig[0];
+  }
+  const uint64_t du1 = blk_hi - blk_lo;
   uint64_t x = bounded(W[2], Sv - du1);
   x += x >= blk_lo ? du1 : 0;
   const int32_t iw = row_pick(PrefixOf32{sig}, dv, Sv, x, a.sig_guide, R.w);

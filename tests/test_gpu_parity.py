@@ -192,6 +192,42 @@ def test_validation_errors_on_gpu():
     bad(np.array([0, 1, 1], np.int32), np.array([7], np.int32), moss.MOSS_E_ARG, moss.MOSS_TRUST_CSR)
 
 
+def _csr_from_rows(rows, n):
+    rp = np.zeros(n + 1, np.int32)
+    for v in range(n):
+        rp[v + 1] = rp[v] + len(rows.get(v, ()))
+    col = np.concatenate([np.array(sorted(rows.get(v, ())), np.int32) for v in range(n)] + [np.zeros(0, np.int32)])
+    return rp, col.astype(np.int32)
+
+
+@pytest.mark.parametrize("hub_row,missing", [
+    (list(range(0, 399)), None),                          # symmetric: every mirror found
+    ([c for c in range(0, 399) if c != 150], 150),        # missing id inside the first window
+    (list(range(0, 10)) + list(range(300, 399)), 200),    # missing id below the window
+    (list(range(0, 100)) + list(range(390, 399)), 200),   # missing id above the window
+    ([c for c in range(0, 399) if c != 0], 0),            # missing id at the row's start
+])
+def test_symmetry_check_on_long_rows(hub_row, missing):
+    """The windowed search of a long row for a mirror entry: hub 399 with every leaf
+    entry (c, 399); one leaf's mirror is missing from the hub row, and one unmatched
+    lower entry keeps the upper and lower counts equal, so only the search can tell."""
+    n, hub = 400, 399
+    leaves = sorted(set(hub_row) | ({missing} if missing is not None else set()))
+    rows = {hub: hub_row}
+    for c in leaves:
+        rows[c] = [hub]
+    if missing is not None:
+        a, b = leaves[-1], leaves[0]
+        rows[a] = sorted(rows[a] + [b])  # lower entry (a, b) whose mirror is absent
+    rp, col = _csr_from_rows(rows, n)
+    if missing is None:
+        moss.moss_graph_destroy(moss.moss_graph_create(n, len(col), rp, col, 0, 0))
+        return
+    with pytest.raises(moss.MossError) as e:
+        moss.moss_graph_create(n, len(col), rp, col, 0, 0)
+    assert e.value.status == moss.MOSS_E_ASYMMETRIC
+
+
 def test_overflow_reported_per_table_set():
     """Lambda_4 of K_{1,150000} exceeds 64 bits; Lambda_3 does not: the 4-node tables
     build, the 5-node tables report overflow."""
