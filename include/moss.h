@@ -213,12 +213,21 @@ typedef struct {
 moss_status moss_estimate_batch(const moss_request *reqs, int32_t n, moss_result *out, void *hip_stream);
 
 /* Launch shape knobs (0 = automatic).  tile_samples: samples per tile in the batched
-   kernel; blocks_per_cu: resident workgroups per compute unit for the sampling kernels. */
+   kernel; blocks_per_cu: resident workgroups per compute unit for the sampling kernels;
+   schedule: how a plain estimate spreads its samples (MOSS_SCHEDULE_*).  No knob
+   changes any result. */
+enum {
+  MOSS_SCHEDULE_AUTO = 0,   /* by the graph's footprint */
+  MOSS_SCHEDULE_PLAIN = 1,  /* grid-stride over the sample indices */
+  MOSS_SCHEDULE_XCD = 2     /* samples grouped by the top bits of their first random word,
+                               one group per XCD (see moss_estimate) */
+};
+
 typedef struct {
   uint32_t tile_samples;
   uint32_t blocks_per_cu;
   uint32_t threads_per_block;
-  uint32_t reserved;
+  uint32_t schedule;
 } moss_tuning;
 
 moss_status moss_set_tuning(const moss_tuning *t);

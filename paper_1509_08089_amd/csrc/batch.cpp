@@ -360,11 +360,12 @@ moss_status moss_estimate_batch(const moss_request* reqs, int32_t n, moss_result
 moss_status moss_set_tuning(const moss_tuning* t) {
   if (!t) return MOSS_E_ARG;
   if (t->threads_per_block && (t->threads_per_block % 64 != 0 || t->threads_per_block > 256)) return MOSS_E_ARG;
-  if (t->blocks_per_cu > 64) return MOSS_E_ARG;
+  if (t->blocks_per_cu > 64 || t->schedule > MOSS_SCHEDULE_XCD) return MOSS_E_ARG;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuning.tile_samples = t->tile_samples;
   g_tuning.blocks_per_cu = t->blocks_per_cu;
   g_tuning.threads_per_block = t->threads_per_block;
+  g_tuning.schedule = t->schedule;
   return MOSS_OK;
 }
 
@@ -374,7 +375,7 @@ moss_status moss_get_tuning(moss_tuning* t) {
   t->tile_samples = g_tuning.tile_samples;
   t->blocks_per_cu = g_tuning.blocks_per_cu;
   t->threads_per_block = g_tuning.threads_per_block;
-  t->reserved = 0;
+  t->schedule = g_tuning.schedule;
   return MOSS_OK;
 }
 
@@ -404,6 +405,7 @@ moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best
       }
     }
   }
+  b.schedule = current_tuning().schedule;
   st = moss_set_tuning(&b);
   if (st != MOSS_OK) return st;
   *best = b;

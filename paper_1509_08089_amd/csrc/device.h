@@ -85,21 +85,6 @@ __device__ __forceinline__ bool row_has(const int32_t* __restrict__ col, int32_t
   return n == 1 && col[lo] == key;
 }
 
-// The same for a key that is a node id in [0, n): ids spread over [0, n), so the key
-// usually sits near position len * key / n of the row.  The search first compares the
-// ends of a 64-entry window there (two cache lines) and then searches the window or
-// the part of the row on the key's side of it; the answer never depends on where the
-// window falls.
-__device__ __forceinline__ bool row_has_near(const int32_t* __restrict__ col, int32_t base, int32_t len, int32_t key,
-                                             int32_t n) {
-  if (len <= 64) return row_has(col, base, len, key);
-  const int32_t est = (int32_t)(((uint64_t)(uint32_t)key * (uint64_t)len) / (uint64_t)n);
-  const int32_t lo = max(0, min(est - 32, len - 64));
-  if (key < col[base + lo]) return row_has(col, base, lo, key);
-  if (key > col[base + lo + 63]) return row_has(col, base + lo + 64, len - lo - 64, key);
-  return row_has(col, base + lo, 64, key);
-}
-
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // ---- edge hash set: open addressing with linear probing over 2^bits u64 slots ----

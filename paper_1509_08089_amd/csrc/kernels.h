@@ -156,6 +156,14 @@ hipError_t launch_guides(const GuideSet& set, int32_t n, int gbits, hipStream_t 
 hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
                          unsigned long long* hits, uint8_t* class_out, int grid, int block, hipStream_t s);
 
+// The same samples drawn XCD-grouped: `scratch` holds grouped_scratch_bytes(max_n)
+// bytes (a group byte per sample and 8 cursors); launches of at most max_n samples.
+// block must be 64, 128, 192 or 256 threads.
+int64_t grouped_scratch_bytes(uint64_t max_n);
+hipError_t launch_sample_grouped(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
+                                 unsigned long long* hits, uint8_t* class_out, void* scratch, uint64_t max_n,
+                                 int grid, int block, hipStream_t s);
+
 hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed, const uint64_t* index,
                                int64_t count, int32_t* nodes_out, uint8_t* class_out, hipStream_t s);
 

@@ -26,6 +26,7 @@ STATUS = {
 globals().update({v: k for k, v in STATUS.items()})
 
 MOSS_SAMPLER_MOSS4, MOSS_SAMPLER_T5, MOSS_SAMPLER_PATH5 = 0x4, 0x51, 0x52
+MOSS_SCHEDULE_AUTO, MOSS_SCHEDULE_PLAIN, MOSS_SCHEDULE_XCD = 0, 1, 2
 MOSS_TRUST_CSR = 0x1
 MOSS_MIX_POOLED, MOSS_MIX_PAPER = 0x0, 0x1
 MOSS_TABLES_K4, MOSS_TABLES_K5 = 1 << 4, 1 << 5
@@ -81,7 +82,7 @@ class moss_request(ctypes.Structure):
 
 class moss_tuning(ctypes.Structure):
     _fields_ = [("tile_samples", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("threads_per_block", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("threads_per_block", ctypes.c_uint32), ("schedule", ctypes.c_uint32)]
 
 
 class moss_server_config(ctypes.Structure):
@@ -260,8 +261,8 @@ def _requests(requests):
     return reqs, n
 
 
-def moss_set_tuning(tile_samples: int = 0, blocks_per_cu: int = 0, threads_per_block: int = 0):
-    t = moss_tuning(tile_samples, blocks_per_cu, threads_per_block, 0)
+def moss_set_tuning(tile_samples: int = 0, blocks_per_cu: int = 0, threads_per_block: int = 0, schedule: int = 0):
+    t = moss_tuning(tile_samples, blocks_per_cu, threads_per_block, schedule)
     _check(lib().moss_set_tuning(ctypes.byref(t)), "moss_set_tuning")
 
 
