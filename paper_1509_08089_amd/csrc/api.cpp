@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -108,7 +109,9 @@ int sampling_waves_per_cu(uint64_t footprint_bytes) {
 }
 
 uint64_t sampling_footprint(const moss_graph* g) {
-  return g->table_bytes + ((uint64_t)g->n + 1 + (uint64_t)g->nnz) * sizeof(int32_t);
+  const uint64_t csr = ((uint64_t)g->n + 1 + (uint64_t)g->nnz) * sizeof(int32_t);
+  const uint64_t edge_set = (8ull << g->edge_bits) + (8ull << g->filter_bits);
+  return g->table_bytes + csr + edge_set;
 }
 
 // Whether a plain estimate on g draws its samples XCD-grouped (the tuning's schedule,
@@ -146,24 +149,92 @@ using namespace moss;
 
 namespace {
 
-// Device memory is stream-ordered (hipMallocAsync on the graph's stream from the
-// device's default pool, which keeps freed blocks for reuse), so building and
-// dropping tables costs no device-wide synchronisation.  Each graph holds a few
-// blocks, every array carved out of one of them at a 256-byte boundary.
+// Device memory.  Each graph holds a few blocks, every array carved out of one of them
+// at a 256-byte boundary.  Blocks come from the device's stream-ordered pool
+// (hipMallocAsync on the graph's stream), and released blocks are kept per device for
+// reuse by a later request of the same rounded size: on MI355X a hipFreeAsync call
+// costs about 19 us and a hipMallocAsync call about 7 us of host time, more than the
+// small kernels of a table build.  Callers release a block only once its stream has
+// drained (after a synchronisation), so a cached block is idle and serves any stream.
+// The cache holds at most kCacheBytes per device and drops its oldest blocks first.
+constexpr size_t kCacheBytes = 1ull << 30;
+
+size_t block_size(size_t bytes) {
+  const size_t g = bytes <= (8u << 20) ? (64u << 10) : (2u << 20);
+  return (std::max<size_t>(bytes, 256) + g - 1) / g * g;
+}
+
+struct BlockCache {
+  std::mutex mu;
+  struct Entry {
+    int device;
+    size_t bytes;
+    void* p;
+  };
+  std::vector<Entry> idle;  // oldest first
+  std::vector<size_t> held;  // per device
+  std::map<void*, size_t> live;
+};
+BlockCache g_blocks;
+
 moss_status dev_alloc_bytes(hipStream_t s, void** p, size_t bytes) {
   *p = nullptr;
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMallocAsync(p, bytes, s);
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return MOSS_E_DEVICE;
+  const size_t sz = block_size(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_blocks.mu);
+    for (size_t i = g_blocks.idle.size(); i-- > 0;) {
+      const BlockCache::Entry& en = g_blocks.idle[i];
+      if (en.device == device && en.bytes == sz) {
+        *p = en.p;
+        g_blocks.held[device] -= sz;
+        g_blocks.idle.erase(g_blocks.idle.begin() + (std::ptrdiff_t)i);
+        g_blocks.live[*p] = sz;
+        return MOSS_OK;
+      }
+    }
+  }
+  hipError_t e = hipMallocAsync(p, sz, s);
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
     return MOSS_E_NOMEM;
   }
+  std::lock_guard<std::mutex> lk(g_blocks.mu);
+  g_blocks.live[*p] = sz;
   return MOSS_OK;
 }
 
+// p must be idle: no work that uses it may still be queued on any stream.
 void dev_free(hipStream_t s, void*& p) {
-  if (p) (void)hipFreeAsync(p, s);
+  if (!p) return;
+  int device = 0;
+  (void)hipGetDevice(&device);
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_blocks.mu);
+    auto it = g_blocks.live.find(p);
+    const size_t sz = it != g_blocks.live.end() ? it->second : 0;
+    if (it != g_blocks.live.end()) g_blocks.live.erase(it);
+    if ((int)g_blocks.held.size() <= device) g_blocks.held.resize(device + 1, 0);
+    if (sz > 0 && sz <= kCacheBytes) {
+      g_blocks.idle.push_back({device, sz, p});
+      g_blocks.held[device] += sz;
+      for (size_t i = 0; g_blocks.held[device] > kCacheBytes && i < g_blocks.idle.size();) {
+        if (g_blocks.idle[i].device == device) {
+          g_blocks.held[device] -= g_blocks.idle[i].bytes;
+          drop.push_back(g_blocks.idle[i].p);
+          g_blocks.idle.erase(g_blocks.idle.begin() + (std::ptrdiff_t)i);
+        } else {
+          ++i;
+        }
+      }
+    } else {
+      drop.push_back(p);
+    }
+  }
+  for (void* q : drop) (void)hipFreeAsync(q, s);
   p = nullptr;
 }
 
@@ -182,9 +253,10 @@ T* at(void* base, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
-// per graph: word block, items, item sums, row-guide lengths, scan scratch, partials, records
+// per graph: word block, edge hash set and filter, items, item sums, row-guide lengths,
+// scan scratch, partials, records
 struct GraphLayout {
-  size_t small, items, item_sum, guide_len, tmp[3], partials, rec, bytes;
+  size_t small, slots, filter, items, item_sum, guide_len, tmp[3], partials, rec, bytes;
 };
 
 GraphLayout graph_layout(int32_t n, int64_t nnz) {
@@ -192,6 +264,8 @@ GraphLayout graph_layout(int32_t n, int64_t nnz) {
   GraphLayout L;
   Carve c;
   L.small = c.take<uint64_t>(kWords);
+  L.slots = c.take<uint64_t>((size_t)1 << edge_hash_bits(nnz / 2));
+  L.filter = c.take<uint64_t>((size_t)1 << edge_filter_bits(nnz / 2));
   L.items = c.take<uint64_t>((size_t)cap);
   L.item_sum = c.take<uint64_t>((size_t)std::max<int64_t>(cap, (int64_t)n));
   L.guide_len = c.take<uint64_t>((size_t)n);
@@ -203,7 +277,7 @@ GraphLayout graph_layout(int32_t n, int64_t nnz) {
 }
 
 struct SigLayout {
-  size_t acc_sigma, guide, slots, filter, bytes;
+  size_t acc_sigma, guide, bytes;
 };
 
 SigLayout sig_layout(const moss_graph* g) {
@@ -211,8 +285,6 @@ SigLayout sig_layout(const moss_graph* g) {
   Carve c;
   L.acc_sigma = c.take<uint32_t>((size_t)g->nnz);
   L.guide = c.take<uint32_t>((size_t)g->row_guide_len);
-  L.slots = c.take<uint64_t>((size_t)1 << edge_hash_bits(g->nnz / 2));
-  L.filter = c.take<uint64_t>((size_t)1 << edge_filter_bits(g->nnz / 2));
   L.bytes = c.off;
   return L;
 }
@@ -305,8 +377,6 @@ void free_tables(moss_graph* g, uint32_t mask) {
     dev_free(g->stream, g->mem_sig);
     g->acc_sigma = nullptr;
     g->sig_guide = nullptr;
-    g->edge_slots = nullptr;
-    g->filter = nullptr;
   }
   g->table_bytes = moss::table_bytes_needed(g, 0);
 }
@@ -345,6 +415,10 @@ moss_status finish_create(moss_graph* g) {
   if (st != MOSS_OK) return st;
   void* m = g->mem_graph;
   g->small = at<uint64_t>(m, L.small);
+  g->edge_slots = at<uint64_t>(m, L.slots);
+  g->filter = at<uint64_t>(m, L.filter);
+  g->edge_bits = edge_hash_bits(g->nnz / 2);
+  g->filter_bits = edge_filter_bits(g->nnz / 2);
   g->items = at<uint64_t>(m, L.items);
   g->item_sum = at<uint64_t>(m, L.item_sum);
   g->guide_len = at<uint64_t>(m, L.guide_len);
@@ -356,7 +430,15 @@ moss_status finish_create(moss_graph* g) {
   hipStream_t s = g->stream;
   const int64_t cap = items_cap(g->n, g->nnz);
   uint32_t* err = (uint32_t*)(g->small + kWErr);
-  hipError_t e = launch_fill_u64(g->small, 0, kWords, s);
+  FillSet f{};
+  f.p[0] = g->small;
+  f.count[0] = kWords;
+  f.p[1] = g->edge_slots;
+  f.count[1] = (int64_t)1 << g->edge_bits;
+  f.value[1] = ~0ull;
+  f.p[2] = g->filter;
+  f.count[2] = (int64_t)1 << g->filter_bits;
+  hipError_t e = launch_fill_set(f, s);
   // item_sum holds the piece counts here, scanned into each row's item end
   if (e == hipSuccess) e = launch_node_prep(g->n, g->nnz, g->rp, g->item_sum, g->guide_len, g->small, s);
   if (e == hipSuccess) {
@@ -374,13 +456,17 @@ moss_status finish_create(moss_graph* g) {
   if (e == hipSuccess)
     e = launch_items_records(g->n, g->rp, g->item_sum, g->guide_len, cap, g->items, g->rec, g->small, s);
   if (e == hipSuccess)
-    e = launch_check_items(cap, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->small, s);
+    e = launch_edge_insert(cap, g->items, g->rp, g->col, g->n, g->edge_slots, g->edge_bits, g->filter, g->filter_bits,
+                           g->small, s);
+  if (e == hipSuccess)
+    e = launch_check_items(cap, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->edge_slots,
+                           g->edge_bits, g->small, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->small, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return status_of(e);
   const uint64_t* h = g->h_stage;
   uint32_t bits = (uint32_t)(h[kWErr] & 0xFFFFFFFFu);
-  if (bits) return (moss_status)validate_error_status(bits);
+  if (bits) return (moss_status)validate_error_status(bits);  // a full hash set reads as overflow
   g->max_degree = (int32_t)h[kWMaxDeg];
   g->n_items = (int64_t)h[kWItems];
   g->row_guide_len = (int64_t)h[kWGuideLen];
@@ -571,10 +657,6 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     if (st == MOSS_OK) {
       g->acc_sigma = at<uint32_t>(g->mem_sig, L.acc_sigma);
       g->sig_guide = at<uint32_t>(g->mem_sig, L.guide);
-      g->edge_slots = at<uint64_t>(g->mem_sig, L.slots);
-      g->filter = at<uint64_t>(g->mem_sig, L.filter);
-      g->edge_bits = edge_hash_bits(g->nnz / 2);
-      g->filter_bits = edge_filter_bits(g->nnz / 2);
     }
   }
   if (st == MOSS_OK && want4) {
@@ -598,25 +680,18 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     }
   }
   if (st != MOSS_OK) {
+    (void)hipStreamSynchronize(g->stream);  // the blocks it did get are idle before release
     free_tables(g, need);
     return st;
   }
   hipStream_t s = g->stream;
   uint32_t* err = (uint32_t*)(g->small + kWErr);
-  // error bits, Lambdas and totals to zero; with the first set the hash set to empty
-  // keys and the filter to zero
+  // error bits, Lambdas and totals to zero
   FillSet f{};
   f.p[0] = g->small + kWErr;
   f.count[0] = kWLambda + 2;
   f.p[1] = g->small + kWTotal;
   f.count[1] = 3;
-  if (!sig_ready) {
-    f.p[2] = g->edge_slots;
-    f.count[2] = (int64_t)1 << g->edge_bits;
-    f.value[2] = ~0ull;
-    f.p[3] = g->filter;
-    f.count[3] = (int64_t)1 << g->filter_bits;
-  }
   hipError_t e = launch_fill_set(f, s);
   RowTables t{};
   t.items = g->items;
@@ -626,19 +701,13 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   t.item_sum = g->item_sum;
   t.rec = g->rec;
   t.n_items = g->n_items;
-  t.hash_bits = g->edge_bits;
-  t.filter_bits = g->filter_bits;
   if (e == hipSuccess && !sig_ready) {
     t.guide = g->sig_guide;
-    t.slots = g->edge_slots;
-    t.filter = g->filter;
     e = launch_row_tables(false, t, err, s);
   }
   if (e == hipSuccess && want5) {
     t.acc_tau = g->acc_tau;
     t.guide = g->tau_guide;
-    t.slots = nullptr;
-    t.filter = nullptr;
     e = launch_row_tables(true, t, err, s);
   }
   if (e == hipSuccess)
@@ -662,7 +731,8 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   if (e == hipSuccess) e = launch_guides(guides, g->n, g->gbits, s);
   uint64_t* h = g->h_stage;
   if (e == hipSuccess) e = hipMemcpyAsync(h, g->small, kWHits * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t es = hipStreamSynchronize(s);  // also drains work queued before a failed launch
+  if (e == hipSuccess) e = es;
   if (e != hipSuccess) {
     free_tables(g, need);
     return status_of(e);
@@ -729,10 +799,11 @@ moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0,
                         grid, block, s);
   }
   if (e == hipSuccess) e = hipEventRecord(g->ev1, s);
-  dev_free(s, scratch);
   if (e == hipSuccess)
     e = hipMemcpyAsync(g->h_stage, d_hits, 2 * 22 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t es = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = es;
+  dev_free(s, scratch);  // idle after the synchronisation
   if (e != hipSuccess) return status_of(e);
   for (int i = 0; i < count; ++i) std::memcpy(hits[i], g->h_stage + 22 * i, 22 * sizeof(uint64_t));
   float ms = 0.f;

@@ -104,15 +104,20 @@ hipError_t launch_node_prep(int32_t n, int64_t nnz, const int32_t* rp, uint64_t*
 // Both do nothing once row_ptr has been rejected.
 hipError_t launch_items_records(int32_t n, const int32_t* rp, const uint64_t* item_end, const uint64_t* goff_end,
                                 int64_t cap, uint64_t* items, uint4* rec, uint64_t* small, hipStream_t s);
-// Column range; with `full` also self-loops, strict ascent and the mirror of every entry
-// (v, c) with c > v; counts those entries into small[kWUpper].
+// The edge hash set (filled with empty keys beforehand) and the edge filter (zeroed)
+// from the entries (v, c) with v < c < n; nothing once row_ptr has been rejected.
+hipError_t launch_edge_insert(int64_t cap, const uint64_t* items, const int32_t* rp, const int32_t* col, int32_t n,
+                              uint64_t* slots, int hash_bits, uint64_t* filter, int filter_bits, uint64_t* small,
+                              hipStream_t s);
+// Column range; with `full` also self-loops, strict ascent and, through the hash set,
+// the mirror of every entry (v, c) with c < v; counts the entries with c > v into
+// small[kWUpper].
 hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
-                              bool full, uint64_t* small, hipStream_t s);
+                              bool full, const uint64_t* slots, int hash_bits, uint64_t* small, hipStream_t s);
 
 // ---- table build ----
 // Row prefixes ACC_sigma (tau = false) or ACC_tau (tau = true, after ACC_sigma), their
-// row guides, and with ACC_sigma the node records' S_v and the edge hash set and filter
-// (filled with empty keys and zeros beforehand).  item_sum holds n_items u64.
+// row guides, and with ACC_sigma the node records' S_v.  item_sum holds n_items u64.
 struct RowTables {
   const uint64_t* items;
   const int32_t* rp;
@@ -122,11 +127,7 @@ struct RowTables {
   uint64_t* item_sum;
   uint4* rec;
   uint32_t* guide;
-  uint64_t* slots;
-  uint64_t* filter;
   int64_t n_items;
-  int32_t hash_bits;
-  int32_t filter_bits;
 };
 hipError_t launch_row_tables(bool tau, const RowTables& t, uint32_t* err, hipStream_t s);
 

@@ -225,14 +225,63 @@ __device__ __forceinline__ ItemRange item_range(const uint64_t* __restrict__ ite
   return r;
 }
 
-// Column range, self-loops, strict ascent (sorted, no repeats) and symmetry.  Only
-// entries (v, c) with c > v look for their mirror (v in the row of c); with repeats
-// excluded, those mirrors are distinct entries with c < v, so the graph is
-// symmetric exactly when every one is found and they are half of all entries
-// (the host compares the count in small[kWUpper] with nnz).
+// The edge hash set and the filter, built at creation: every entry (v, c) with
+// v < c < n inserts the key min << 32 | max (each undirected edge once, from its
+// smaller endpoint) with a 64-bit compare-and-swap, linear probing, and sets its 4 bits
+// in the filter.  The set has at least 1.25 slots per such entry, so it never fills;
+// a full set would still be reported (kErrOverflow) and every probe loop is bounded.
+__global__ __launch_bounds__(256) void k_edge_insert(int64_t cap, const uint64_t* __restrict__ items,
+                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                     int32_t n, unsigned long long* __restrict__ slots, int hash_bits,
+                                                     unsigned long long* __restrict__ filter, int filter_bits,
+                                                     uint64_t* small) {
+  if (rowptr_rejected(small)) return;  // no barrier below: threads may leave one by one
+  const int lane = lane_id();
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t n_items = min((int64_t)small[kWItems], cap);
+  const uint64_t hmask = (1ull << hash_bits) - 1;
+  bool full = false;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
+      const int32_t c = col[e];
+      if (c <= it.v || c >= n) continue;
+      const uint64_t key = edge_key(it.v, c);
+      const uint64_t z = mix64(key);
+      atomicOr(&filter[filter_word(z, filter_bits)], (unsigned long long)filter_mask(z));
+      uint64_t h = edge_slot(key, hash_bits);
+      for (uint64_t probes = 0;; ++probes) {
+        const unsigned long long old = atomicCAS(&slots[h], (unsigned long long)kEmptySlot, (unsigned long long)key);
+        if (old == kEmptySlot || old == key) break;
+        h = (h + 1) & hmask;
+        if (probes >= hmask) {
+          full = true;
+          break;
+        }
+      }
+    }
+  }
+  if (__ballot(full) != 0 && lane == 0) atomicOr((uint32_t*)(small + kWErr), kErrOverflow);
+}
+
+hipError_t launch_edge_insert(int64_t cap, const uint64_t* items, const int32_t* rp, const int32_t* col, int32_t n,
+                              uint64_t* slots, int hash_bits, uint64_t* filter, int filter_bits, uint64_t* small,
+                              hipStream_t s) {
+  if (cap <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edge_insert, dim3(item_grid(cap)), dim3(256), 0, s, cap, items, rp, col, n,
+                     (unsigned long long*)slots, hash_bits, (unsigned long long*)filter, filter_bits, small);
+  return hipGetLastError();
+}
+
+// Column range, self-loops, strict ascent (sorted, no repeats) and symmetry.  Every
+// entry (v, c) with c < v looks up its mirror (c, v) in the edge hash set, which holds
+// exactly the entries with c > v; with repeats excluded those mirrors are distinct, so
+// the graph is symmetric exactly when all are found and the entries with c > v are
+// half of all entries (the host compares their count in small[kWUpper] with nnz).
 __global__ __launch_bounds__(256) void k_check_items(int64_t cap, const uint64_t* __restrict__ items, int32_t n,
                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                     int full, uint64_t* small) {
+                                                     int full, const uint64_t* __restrict__ slots, int hash_bits,
+                                                     uint64_t* small) {
   __shared__ uint32_t s_bad, s_skip;
   __shared__ unsigned long long s_upper;
   if (threadIdx.x == 0) {
@@ -263,8 +312,10 @@ __global__ __launch_bounds__(256) void k_check_items(int64_t cap, const uint64_t
       }
       if (c > it.v) {
         ++upper;
-        const int32_t rc = rp[c];
-        if (!row_has(col, rc, rp[c + 1] - rc, it.v)) bad |= kErrAsymmetric;
+      } else if (c < it.v) {
+        const uint64_t key = edge_key(c, it.v);
+        const uint64_t h = edge_slot(key, hash_bits);
+        if (!edge_hash_rest(slots, hash_bits, key, h, slots[h])) bad |= kErrAsymmetric;
       }
     }
   }
@@ -282,10 +333,10 @@ __global__ __launch_bounds__(256) void k_check_items(int64_t cap, const uint64_t
 }
 
 hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
-                              bool full, uint64_t* small, hipStream_t s) {
+                              bool full, const uint64_t* slots, int hash_bits, uint64_t* small, hipStream_t s) {
   if (cap <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_check_items, dim3(reduce_grid(cap, 4)), dim3(256), 0, s, cap, items, n, rp, col, full ? 1 : 0,
-                     small);
+                     slots, hash_bits, small);
   return hipGetLastError();
 }
 
@@ -295,8 +346,7 @@ hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, con
 //   local   each item scans its own entries and writes its total to item_sum
 //   finish  each item adds the totals of its row's earlier pieces (at most a few
 //           hundred, summed by the wave), then writes its share of the row guide;
-//           the ACC_sigma pass also records S_v and inserts the edges into the hash
-//           set and the filter
+//           the ACC_sigma pass also records S_v
 // ACC_sigma entries are (d_x - 1) of the neighbours; ACC_tau entries are
 // (d_x - 1)(S_v - (d_x - 1)) with S_v the row total of ACC_sigma.
 // ---------------------------------------------------------------------------------
@@ -338,8 +388,7 @@ template <bool TAU>
 __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const uint64_t hmask = (1ull << t.hash_bits) - 1;
-  bool over = false, full = false;
+  bool over = false;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
     const ItemRange it = item_range(t.items, t.rp, i);
     const int32_t d = it.r1 - it.r0;
@@ -364,13 +413,11 @@ __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) 
       const int32_t e = e0 + lane;
       const bool in = e < it.e1;
       uint64_t hi = carry;
-      int32_t c = 0;
       if (in) {
         if (TAU) {
           hi = t.acc_tau[e] + before;
           if (before) t.acc_tau[e] = hi;
         } else {
-          c = t.col[e];
           hi = (uint64_t)t.acc_sigma[e] + before;
           if (before) t.acc_sigma[e] = (uint32_t)hi;
         }
@@ -386,28 +433,10 @@ __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) 
         if (e == it.r1 - 1) b1 = (1ull << g) + 1;
         for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - it.r0);
       }
-      if (!TAU && in && c > it.v) {  // each undirected edge once, from its smaller endpoint
-        const uint64_t key = edge_key(it.v, c);
-        const uint64_t z = mix64(key);
-        atomicOr((unsigned long long*)&t.filter[filter_word(z, t.filter_bits)], (unsigned long long)filter_mask(z));
-        uint64_t h = edge_slot(key, t.hash_bits);
-        for (uint64_t probes = 0;; ++probes) {
-          const unsigned long long old =
-              atomicCAS((unsigned long long*)&t.slots[h], (unsigned long long)kEmptySlot, (unsigned long long)key);
-          if (old == kEmptySlot || old == key) break;
-          h = (h + 1) & hmask;
-          if (probes >= hmask) {
-            full = true;
-            break;
-          }
-        }
-      }
     }
     if (!TAU && it.e1 == it.r1 && lane == 0) t.rec[it.v].z = (uint32_t)total;
   }
-  const bool any_over = __ballot(over) != 0, any_full = __ballot(full) != 0;
-  if (lane == 0 && (any_over || any_full))
-    atomicOr(err, (any_over ? (TAU ? kErrOverflowK5 : kErrOverflow) : 0u) | (any_full ? kErrOverflow : 0u));
+  if (__ballot(over) != 0 && lane == 0) atomicOr(err, TAU ? kErrOverflowK5 : kErrOverflow);
 }
 
 hipError_t launch_row_tables(bool tau, const RowTables& t, uint32_t* err, hipStream_t s) {
