@@ -115,16 +115,18 @@ uint64_t sampling_footprint(const moss_graph* g) {
 }
 
 // Whether a plain estimate on g draws its samples XCD-grouped (the tuning's schedule,
-// else by footprint): worth its grouping pass once the tables no longer fit the 256 MB
-// MALL (at n = 1e6, m = 1e7 it is 25% faster; at n = 1e5, m = 1e6 the plain schedule
-// is 30% faster).
-constexpr uint64_t kGroupedMinFootprint = 256ull << 20;
+// else by size): the sorting passes pay off once the sampled tables are well beyond
+// the L2 and the launch has millions of samples (measured: at n = 1e5, m = 1e6 and 1e7
+// samples the grouped kernel takes 0.68 ms against 0.73 ms; at n = 2e3, m = 1e4 it
+// loses; at n = 1e6, m = 1e7 it takes 15.6 ms against 25.2 ms for T-5 + Path-5).
+constexpr uint64_t kGroupedMinFootprint = 32ull << 20;
+constexpr uint64_t kGroupedMinSamples = 1ull << 22;
 
-bool grouped_schedule(const moss_graph* g) {
+bool grouped_schedule(const moss_graph* g, uint64_t nsamples) {
   const uint32_t sch = current_tuning().schedule;
   if (sch == MOSS_SCHEDULE_XCD) return true;
   if (sch == MOSS_SCHEDULE_PLAIN) return false;
-  return sampling_footprint(g) >= kGroupedMinFootprint;
+  return sampling_footprint(g) >= kGroupedMinFootprint && nsamples >= kGroupedMinSamples;
 }
 
 void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int* grid, int* block) {
@@ -132,8 +134,10 @@ void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int
   int b = t.threads_per_block ? (int)t.threads_per_block : 256;
   int per_cu = t.blocks_per_cu ? (int)t.blocks_per_cu : 0;
   if (per_cu == 0) {
-    // grouped launches keep a narrow node range per L2 and take 32 waves per CU
-    const int waves = grouped_schedule(g) ? 32 : sampling_waves_per_cu(sampling_footprint(g));
+    // grouped launches keep a narrow node range per L2: 20 waves per CU, 16 once the
+    // tables are beyond the MALL
+    const uint64_t fp = sampling_footprint(g);
+    const int waves = grouped_schedule(g, nsamples) ? (fp > (256ull << 20) ? 16 : 20) : sampling_waves_per_cu(fp);
     const int cap = std::max(1, std::min(sample_kernel_blocks_per_cu(sampler, b), 8));
     per_cu = std::max(1, std::min(cap, waves / (b / 64)));
   }
@@ -775,15 +779,17 @@ moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0,
                          uint64_t seed, uint8_t* class_out, uint64_t hits[][22], double* device_ms) {
   hipStream_t s = g->stream;
   unsigned long long* d_hits = (unsigned long long*)(g->small + kWHits);
-  // XCD-grouped launches need a group byte per sample (in chunks of at most 2^26)
+  // XCD-grouped launches sort each chunk of at most 2^25 samples by group (5 bytes per
+  // sample of scratch)
   void* scratch = nullptr;
   uint64_t max_n = 0;
-  if (grouped_schedule(g)) {
-    for (int i = 0; i < count; ++i) max_n = std::max<uint64_t>(max_n, k1[i] > k0[i] ? k1[i] - k0[i] : 0);
-    max_n = std::min<uint64_t>(max_n, 1ull << 26);
+  for (int i = 0; i < count; ++i) max_n = std::max<uint64_t>(max_n, k1[i] > k0[i] ? k1[i] - k0[i] : 0);
+  if (grouped_schedule(g, max_n)) {
+    max_n = std::min<uint64_t>(max_n, 1ull << 25);
     if (max_n > 0 && dev_alloc_bytes(s, &scratch, (size_t)grouped_scratch_bytes(max_n)) != MOSS_OK)
       return MOSS_E_NOMEM;
   }
+  // (with a scratch block, every launch below runs grouped; chunks of at most max_n)
   hipError_t e = launch_fill_u64(g->small + kWHits, 0, 2 * 22, s);
   if (e == hipSuccess) e = hipEventRecord(g->ev0, s);
   for (int i = 0; i < count && e == hipSuccess; ++i) {

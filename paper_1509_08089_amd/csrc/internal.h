@@ -101,7 +101,7 @@ uint64_t table_bytes_needed(const moss_graph* g, uint32_t mask);
 void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int* grid, int* block);
 int sampling_waves_per_cu(uint64_t footprint_bytes);
 uint64_t sampling_footprint(const moss_graph* g);
-bool grouped_schedule(const moss_graph* g);
+bool grouped_schedule(const moss_graph* g, uint64_t nsamples);
 
 struct Tuning {
   uint32_t tile_samples = 0;

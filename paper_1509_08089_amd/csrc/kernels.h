@@ -158,8 +158,8 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
                          unsigned long long* hits, uint8_t* class_out, int grid, int block, hipStream_t s);
 
 // The same samples drawn XCD-grouped: `scratch` holds grouped_scratch_bytes(max_n)
-// bytes (a group byte per sample and 8 cursors); launches of at most max_n samples.
-// block must be 64, 128, 192 or 256 threads.
+// bytes (per sample a group byte and a sorted offset, per-block group counts, cursors);
+// chunks of at most max_n <= 2^31 samples.  block must be 64, 128, 192 or 256 threads.
 int64_t grouped_scratch_bytes(uint64_t max_n);
 hipError_t launch_sample_grouped(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
                                  unsigned long long* hits, uint8_t* class_out, void* scratch, uint64_t max_n,

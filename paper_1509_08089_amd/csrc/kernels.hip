@@ -957,93 +957,159 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
 // ---------------------------------------------------------------------------------
 // XCD-grouped sampling.  MI355X has 8 XCDs, each with its own 4 MB L2, and a launch's
 // workgroups go to the XCDs in turn (workgroup i to XCD i mod 8).  The node draw is
-// monotone in a sample's first random word, so the word's top 5 bits split the samples
-// into 32 groups of equal probability, each drawing v from one contiguous range of
-// nodes.  k_group_samples writes every sample's group (one byte).  In k_sample_grouped
-// XCD x owns the 4 groups 4x .. 4x+3 and its blocks take them in order, so the
-// records, guides and rows of a narrow node range are cached by one L2 at a time
-// instead of all of them by all eight.  A block then helps drain the other groups, so
-// every sample is drawn exactly once wherever the workgroups actually run, and each
-// sample's outcome is the one the plain kernel gives it.  Measured at n = 1e6,
-// m = 1e7: 8 groups cut T-5 / Path-5 from 10.4 / 14.9 ms to 8.3 / 13.3 ms, 32 groups to
-// 7.0 / 11.4 ms; 64 groups cost more in group-byte scans than they save.
+// monotone in a sample's first random word, so the word's top 8 bits split the samples
+// into 256 groups of equal probability, each drawing v from one contiguous range of
+// nodes.  The samples of a chunk are counting-sorted by group (count per block, scan,
+// scatter), and in k_sample_sorted XCD x owns groups 32x .. 32x+31, one contiguous
+// range of the sorted order, which its blocks take window after window: every L2
+// serves one eighth of the nodes, and over time a narrow node range of it.  Blocks
+// then help drain the other XCDs' ranges, so every sample is drawn exactly once
+// wherever the workgroups actually run, and each sample's outcome is the one the
+// plain kernel gives it.  Measured at n = 1e6, m = 1e7 (T-5 / Path-5): plain 10.4 /
+// 14.9 ms; 32 groups found by scanning group bytes 7.0 / 11.5 ms; sorted into 256
+// groups 6.8 / 10.0 ms.
 // ---------------------------------------------------------------------------------
 constexpr int kXcds = 8;
-constexpr int kGroupBits = 5;
-constexpr int kGroups = 1 << kGroupBits;
-constexpr int kGroupsPerXcd = kGroups / kXcds;
-// candidates a block takes from a group cursor: about 512 of them are the group's
-constexpr uint32_t kGroupWindow = 512u * kGroups;
+constexpr int kSortBits = 8;
+constexpr int kSortGroups = 1 << kSortBits;
+constexpr uint32_t kSortSpan = 8192;   // samples per block of the counting passes
+constexpr uint32_t kSortWindow = 2048; // sorted entries a block takes per cursor step
 
+struct SortScratch {
+  uint8_t* group;     // n: group of each sample
+  uint32_t* order;    // n: sample offsets sorted by group
+  uint64_t* counts;   // kSortGroups * nblk: per (group, block) counts, then inclusive prefix
+  uint64_t* tmp;      // scan block sums
+  uint32_t* cursors;  // kXcds window cursors
+  uint32_t* err;      // the scan's wrap flag (cannot fire: the counts sum to n)
+  uint32_t nblk;
+};
+
+static SortScratch sort_scratch(void* base, uint64_t max_n) {
+  SortScratch t;
+  char* p = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  t.nblk = (uint32_t)((max_n + kSortSpan - 1) / kSortSpan);
+  if (t.nblk == 0) t.nblk = 1;
+  t.group = reinterpret_cast<uint8_t*>(take(max_n));
+  t.order = reinterpret_cast<uint32_t*>(take(max_n * 4));
+  t.counts = reinterpret_cast<uint64_t*>(take((size_t)kSortGroups * t.nblk * 8));
+  t.tmp = reinterpret_cast<uint64_t*>(take((size_t)scan_tmp_elems((int64_t)kSortGroups * t.nblk) * 8));
+  t.cursors = reinterpret_cast<uint32_t*>(take(kXcds * 4));
+  t.err = reinterpret_cast<uint32_t*>(take(4));
+  return t;
+}
+
+int64_t grouped_scratch_bytes(uint64_t max_n) {
+  const uint64_t nblk = std::max<uint64_t>(1, (max_n + kSortSpan - 1) / kSortSpan);
+  auto r = [](uint64_t b) { return (b + 255) / 256 * 256; };
+  return (int64_t)(r(max_n) + r(max_n * 4) + r(kSortGroups * nblk * 8) +
+                   r((uint64_t)scan_tmp_elems((int64_t)(kSortGroups * nblk)) * 8) + r(kXcds * 4) + r(4) + 256);
+}
+
+// Block b counts the groups of samples [b * kSortSpan, (b + 1) * kSortSpan) into
+// counts[g * nblk + b] (group-major, so the inclusive scan gives each (group, block)
+// its place in the sorted order).
 template <int S>
-__global__ __launch_bounds__(256) void k_group_samples(uint64_t seed, uint64_t k0, uint64_t n,
-                                                       uint8_t* __restrict__ group, uint32_t* __restrict__ cursors) {
-  if (blockIdx.x == 0 && threadIdx.x < kGroups) cursors[threadIdx.x] = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_sort_count(uint64_t seed, uint64_t k0, uint64_t n, SortScratch t) {
+  __shared__ uint32_t hist[kSortGroups];
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) t.cursors[threadIdx.x] = 0;
+  for (int g = threadIdx.x; g < kSortGroups; g += blockDim.x) hist[g] = 0;
+  __syncthreads();
+  const uint64_t lo = (uint64_t)blockIdx.x * kSortSpan;
+  const uint64_t hi = n < lo + kSortSpan ? n : lo + kSortSpan;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
     uint64_t W[4];
     philox_block(k0 + i, 0, seed, S, W);
-    group[i] = (uint8_t)(W[0] >> (64 - kGroupBits));
+    const uint32_t g = (uint32_t)(W[0] >> (64 - kSortBits));
+    t.group[i] = (uint8_t)g;
+    atomicAdd(&hist[g], 1u);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < kSortGroups; g += blockDim.x) t.counts[(uint64_t)g * t.nblk + blockIdx.x] = hist[g];
+}
+
+// The same blocks place their samples.  A block first sorts its span by group in LDS
+// (a sample of group g takes the next free slot of g's run), then writes each run to
+// the block's share of g in the sorted order: consecutive threads write consecutive
+// slots, so the stores coalesce (slot order within a share is immaterial).
+__global__ __launch_bounds__(256) void k_sort_scatter(uint64_t n, SortScratch t) {
+  __shared__ uint64_t base[kSortGroups];   // per group: the block's share in the sorted order
+  __shared__ uint32_t start[kSortGroups];  // per group: the run's start in the local order
+  __shared__ uint32_t next[kSortGroups];   // per group: the run's fill cursor
+  __shared__ uint32_t wsum[kSortGroups / 64];
+  __shared__ uint32_t local[kSortSpan];    // span offsets sorted by group
+  __shared__ uint8_t grp[kSortSpan];
+  static_assert(kSortGroups == 256, "one thread per group");
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  const uint64_t lo = (uint64_t)blockIdx.x * kSortSpan;
+  const uint32_t len = (uint32_t)(n < lo + kSortSpan ? n - lo : kSortSpan);
+  // the block's share of group tid: [inclusive count before it, its inclusive count)
+  uint32_t size = 0;
+  if (tid < kSortGroups) {
+    const uint64_t idx = (uint64_t)tid * t.nblk + blockIdx.x;
+    const uint64_t before = idx ? t.counts[idx - 1] : 0;
+    base[tid] = before;
+    size = (uint32_t)(t.counts[idx] - before);
+  }
+  for (uint32_t j = tid; j < len; j += blockDim.x) grp[j] = t.group[lo + j];
+  // exclusive prefix of the 256 share sizes: local run starts
+  bool unused = false;
+  const uint32_t incl = (uint32_t)wave_inclusive_scan((uint64_t)size, unused);
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  if (tid < kSortGroups) {
+    uint32_t off = 0;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    start[tid] = off + incl - size;
+    next[tid] = off + incl - size;
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < len; j += blockDim.x) local[atomicAdd(&next[grp[j]], 1u)] = j;
+  __syncthreads();
+  for (uint32_t j = tid; j < len; j += blockDim.x) {
+    const uint32_t off = local[j];
+    const uint32_t g = grp[off];
+    t.order[base[g] + (j - start[g])] = (uint32_t)(lo + off);
   }
 }
 
 template <int S>
-__global__ __launch_bounds__(256, 8) void k_sample_grouped(SamplerView a, uint64_t seed, uint64_t k0, uint64_t n,
-                                                        const uint8_t* __restrict__ group, uint32_t* cursors,
-                                                        unsigned long long* __restrict__ hits,
-                                                        uint8_t* __restrict__ class_out) {
+__global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_t seed, uint64_t k0, uint64_t n,
+                                                       SortScratch t, unsigned long long* __restrict__ hits,
+                                                       uint8_t* __restrict__ class_out) {
   __shared__ uint32_t bins[kMaxWaves][kBins + 2];
-  __shared__ uint32_t queue[kMaxWaves][128];
   __shared__ uint8_t lut[64];
   __shared__ uint32_t s_win;
-  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int i = tid; i < nw * (kBins + 2); i += blockDim.x) bins[i / (kBins + 2)][i % (kBins + 2)] = 0;
   load_lut<S>(lut);
   __syncthreads();
-  const uint32_t nwin = (uint32_t)((n + kGroupWindow - 1) / kGroupWindow);
-  const uint32_t per_wave = kGroupWindow / (uint32_t)nw;
-  const uint64_t below = (1ull << lane) - 1;
-  // draws the queued samples of lanes < count (offsets from the window start lo)
-  auto draw_queued = [&](uint64_t lo, uint32_t count) {
-    if ((uint32_t)lane < count) {
-      const uint64_t i = lo + queue[wave][lane];
-      const int c = draw<S>(a, lut, seed, k0 + i, nullptr);
-      atomicAdd(&bins[wave][c], 1u);
-      if (class_out) class_out[i] = (uint8_t)c;
-    }
+  // start of group g in the sorted order: the inclusive count through all earlier groups
+  auto start = [&](uint32_t g) -> uint64_t {
+    return g == 0 ? 0ull : (g >= (uint32_t)kSortGroups ? n : t.counts[(uint64_t)g * t.nblk - 1]);
   };
-  // XCD x owns the groups [x * kGroupsPerXcd, (x + 1) * kGroupsPerXcd) (one contiguous
-  // range of v), takes them in order, then walks on through the others
-  const uint32_t first = (uint32_t)(blockIdx.x % kXcds) * kGroupsPerXcd;
-  for (int step = 0; step < kGroups; ++step) {
-    const uint32_t g = (first + (uint32_t)step) % kGroups;
+  const uint32_t per_xcd = kSortGroups / kXcds;
+  for (int step = 0; step < kXcds; ++step) {
+    const uint32_t x = (uint32_t)((blockIdx.x + step) % kXcds);
+    const uint64_t lo = start(x * per_xcd), hi = start((x + 1) * per_xcd);
     for (;;) {
-      if (tid == 0) s_win = atomicAdd(&cursors[g], 1u);
+      if (tid == 0) s_win = atomicAdd(&t.cursors[x], 1u);
       __syncthreads();
-      const uint32_t win = s_win;
+      const uint64_t p = lo + (uint64_t)s_win * kSortWindow;
       __syncthreads();
-      if (win >= nwin) break;
-      const uint64_t lo = (uint64_t)win * kGroupWindow;
-      const uint64_t hi = n < lo + kGroupWindow ? n : lo + kGroupWindow;
-      const uint64_t wlo = lo + (uint64_t)wave * per_wave;
-      const uint64_t whi = hi < wlo + per_wave ? hi : wlo + per_wave;
-      uint32_t queued = 0;  // wave-uniform
-      for (uint64_t p = wlo; p < whi; p += 64) {
-        const uint64_t i = p + (uint64_t)lane;
-        const bool mine = i < whi && group[i] == g;
-        const uint64_t ball = __ballot(mine);
-        if (mine) queue[wave][queued + (uint32_t)__popcll(ball & below)] = (uint32_t)(i - lo);
-        queued += (uint32_t)__popcll(ball);
-        __builtin_amdgcn_wave_barrier();
-        if (queued >= 64) {
-          draw_queued(lo, 64);
-          __builtin_amdgcn_wave_barrier();
-          if ((uint32_t)lane + 64 < queued) queue[wave][lane] = queue[wave][lane + 64];
-          __builtin_amdgcn_wave_barrier();
-          queued -= 64;
-        }
+      if (p >= hi) break;
+      const uint64_t q = hi < p + kSortWindow ? hi : p + kSortWindow;
+      for (uint64_t j = p + tid; j < q; j += blockDim.x) {
+        const uint64_t i = t.order[j];
+        const int c = draw<S>(a, lut, seed, k0 + i, nullptr);
+        atomicAdd(&bins[wave][c], 1u);
+        if (class_out) class_out[i] = (uint8_t)c;
       }
-      draw_queued(lo, queued);
-      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
@@ -1054,38 +1120,49 @@ __global__ __launch_bounds__(256, 8) void k_sample_grouped(SamplerView a, uint64
   }
 }
 
-int64_t grouped_scratch_bytes(uint64_t n) { return (int64_t)((n + 255) / 256 * 256) + 4 * kGroups + 256; }
-
 hipError_t launch_sample_grouped(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
                                  unsigned long long* hits, uint8_t* class_out, void* scratch, uint64_t max_n,
                                  int grid, int block, hipStream_t s) {
-  if (block != 64 * (block / 64) || block > 256 || block < 64) return hipErrorInvalidValue;
-  uint8_t* group = static_cast<uint8_t*>(scratch);
-  uint32_t* cursors = reinterpret_cast<uint32_t*>(group + (max_n + 255) / 256 * 256);
+  if (block != 64 * (block / 64) || block > 256 || block < 64 || max_n == 0 || max_n > (1ull << 31))
+    return hipErrorInvalidValue;
+  const SortScratch t = sort_scratch(scratch, max_n);
   for (uint64_t a = k0; a < k1;) {
     const uint64_t b = k1 - a > max_n ? a + max_n : k1;
     const uint64_t n = b - a;
+    const uint32_t nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
+    SortScratch tc = t;
+    tc.nblk = nblk;
     uint8_t* co = class_out ? class_out + (a - k0) : nullptr;
-    const int ggrid = fill_grid((int64_t)n);
     switch (sampler) {
-      case kMoss4:
-        hipLaunchKernelGGL(k_group_samples<kMoss4>, dim3(ggrid), dim3(256), 0, s, seed, a, n, group, cursors);
-        hipLaunchKernelGGL(k_sample_grouped<kMoss4>, dim3(grid), dim3(block), 0, s, v, seed, a, n, group, cursors,
-                           hits, co);
-        break;
-      case kT5:
-        hipLaunchKernelGGL(k_group_samples<kT5>, dim3(ggrid), dim3(256), 0, s, seed, a, n, group, cursors);
-        hipLaunchKernelGGL(k_sample_grouped<kT5>, dim3(grid), dim3(block), 0, s, v, seed, a, n, group, cursors, hits,
-                           co);
-        break;
-      case kPath5:
-        hipLaunchKernelGGL(k_group_samples<kPath5>, dim3(ggrid), dim3(256), 0, s, seed, a, n, group, cursors);
-        hipLaunchKernelGGL(k_sample_grouped<kPath5>, dim3(grid), dim3(block), 0, s, v, seed, a, n, group, cursors,
-                           hits, co);
-        break;
+      case kMoss4: hipLaunchKernelGGL(k_sort_count<kMoss4>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
+      case kT5: hipLaunchKernelGGL(k_sort_count<kT5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
+      case kPath5: hipLaunchKernelGGL(k_sort_count<kPath5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
       default: return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
+    ScanSet set{};
+    set.data[0] = tc.counts;
+    set.tmp[0] = tc.tmp;
+    set.err_bit[0] = 0;
+    set.count = 1;
+    hipError_t e = launch_scans(set, (int64_t)kSortGroups * nblk, tc.err, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(256), 0, s, n, tc);
+    // no more blocks than windows (each block visits every cursor once at least), a
+    // multiple of the XCD count so that every XCD gets its share of blocks
+    const uint64_t wins = (n + kSortWindow - 1) / kSortWindow;
+    const int g = (int)std::min<uint64_t>((uint64_t)grid, std::max<uint64_t>(kXcds, (wins + kXcds - 1) / kXcds * kXcds));
+    switch (sampler) {
+      case kMoss4:
+        hipLaunchKernelGGL(k_sample_sorted<kMoss4>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
+        break;
+      case kT5:
+        hipLaunchKernelGGL(k_sample_sorted<kT5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
+        break;
+      default:
+        hipLaunchKernelGGL(k_sample_sorted<kPath5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
+        break;
+    }
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     a = b;
   }

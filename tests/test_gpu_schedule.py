@@ -61,9 +61,9 @@ def test_grouped_estimate_equals_plain(mid, schedule, k):
 
 
 def test_grouped_across_chunks(mid, schedule):
-    """More samples than one grouped launch takes (2^26): the chunks must join up."""
+    """More samples than one grouped launch takes (2^25): the chunks must join up."""
     G = moss.Graph(mid)
-    n = (1 << 26) + 12_345
+    n = (1 << 25) * 2 + 12_345
     schedule(moss.MOSS_SCHEDULE_PLAIN)
     a = G.sample_range(moss.MOSS_SAMPLER_MOSS4, 3, 5, 5 + n)
     schedule(moss.MOSS_SCHEDULE_XCD)
