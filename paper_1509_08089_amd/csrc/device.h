@@ -119,9 +119,11 @@ __device__ __forceinline__ bool edge_hash_rest(const uint64_t* __restrict__ slot
 // ---- edge filter: a blocked Bloom filter in front of the hash set ----
 // Every edge sets 4 bits of one 64-bit word.  A pair whose 4 bits are not all set
 // is certainly not an edge, so most non-edges are settled by one read of a table
-// of 1-2 bytes per edge, small enough to stay in L2 or the MALL; the others and
-// every edge go on to the hash set.  Word and bit positions come from the
-// splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014) of the edge key.
+// small enough to stay cached; the others and every edge go on to the hash set.  The
+// word of a key is the top filter_bits bits of its Fibonacci hash (the high part of
+// its home slot in the hash set, so the filter can be built from the set slot range by
+// slot range); the 4 bit positions come from the splitmix64 finaliser (Steele, Lea and
+// Flood, OOPSLA 2014) of the key.
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z ^= z >> 30;
   z *= 0xBF58476D1CE4E5B9ull;
@@ -129,8 +131,6 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z *= 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
-
-__device__ __forceinline__ uint64_t filter_word(uint64_t z, int fbits) { return z >> (64 - fbits); }
 
 __device__ __forceinline__ uint64_t filter_mask(uint64_t z) {
   return (1ull << (z & 63)) | (1ull << ((z >> 6) & 63)) | (1ull << ((z >> 12) & 63)) | (1ull << ((z >> 18) & 63));

@@ -233,7 +233,6 @@ __device__ __forceinline__ ItemRange item_range(const uint64_t* __restrict__ ite
 __global__ __launch_bounds__(256) void k_edge_insert(int64_t cap, const uint64_t* __restrict__ items,
                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                      int32_t n, unsigned long long* __restrict__ slots, int hash_bits,
-                                                     unsigned long long* __restrict__ filter, int filter_bits,
                                                      uint64_t* small) {
   if (rowptr_rejected(small)) return;  // no barrier below: threads may leave one by one
   const int lane = lane_id();
@@ -247,8 +246,6 @@ __global__ __launch_bounds__(256) void k_edge_insert(int64_t cap, const uint64_t
       const int32_t c = col[e];
       if (c <= it.v || c >= n) continue;
       const uint64_t key = edge_key(it.v, c);
-      const uint64_t z = mix64(key);
-      atomicOr(&filter[filter_word(z, filter_bits)], (unsigned long long)filter_mask(z));
       uint64_t h = edge_slot(key, hash_bits);
       for (uint64_t probes = 0;; ++probes) {
         const unsigned long long old = atomicCAS(&slots[h], (unsigned long long)kEmptySlot, (unsigned long long)key);
@@ -264,12 +261,50 @@ __global__ __launch_bounds__(256) void k_edge_insert(int64_t cap, const uint64_t
   if (__ballot(full) != 0 && lane == 0) atomicOr((uint32_t*)(small + kWErr), kErrOverflow);
 }
 
+// The filter from the finished hash set: lane s of the grid reads slot s; the keys whose
+// home slot lies in the same filter word as s (all but the few that linear probing
+// carried over a word boundary) are OR-ed together across the lanes of that word, one
+// atomic per word; the others set their bits with an atomic each.
+__global__ __launch_bounds__(256) void k_filter_build(const uint64_t* __restrict__ slots, int hash_bits,
+                                                      unsigned long long* __restrict__ filter, int filter_bits,
+                                                      const uint64_t* small) {
+  if (rowptr_rejected(small)) return;  // no barrier below
+  const int lane = lane_id();
+  const int shift = hash_bits - filter_bits;           // slots per filter word: 2^shift
+  const int seg = shift >= 6 ? 64 : 1 << shift;        // lanes that share a word
+  const uint64_t nslots = 1ull << hash_bits;
+  // each wave takes 64 consecutive slots (its lanes' global indices)
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s - lane < nslots;
+       s += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t mine = 0;
+    if (s < nslots) {
+      const uint64_t key = slots[s];
+      if (key != kEmptySlot) {
+        const uint64_t m = filter_mask(mix64(key));
+        const uint64_t w = edge_slot(key, filter_bits);
+        if (w == (s >> shift)) mine = m;
+        else atomicOr(&filter[w], (unsigned long long)m);
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1)
+      if (off < seg) mine |= __shfl_xor(mine, off, 64);
+    if ((lane & (seg - 1)) == 0 && mine && s < nslots) atomicOr(&filter[s >> shift], (unsigned long long)mine);
+  }
+}
+
 hipError_t launch_edge_insert(int64_t cap, const uint64_t* items, const int32_t* rp, const int32_t* col, int32_t n,
                               uint64_t* slots, int hash_bits, uint64_t* filter, int filter_bits, uint64_t* small,
                               hipStream_t s) {
   if (cap <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_edge_insert, dim3(item_grid(cap)), dim3(256), 0, s, cap, items, rp, col, n,
-                     (unsigned long long*)slots, hash_bits, (unsigned long long*)filter, filter_bits, small);
+                     (unsigned long long*)slots, hash_bits, small);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (filter_bits > hash_bits) return hipErrorInvalidValue;
+  const int64_t nslots = 1ll << hash_bits;
+  hipLaunchKernelGGL(k_filter_build, dim3((unsigned)std::min<int64_t>((nslots + 255) / 256, 8192)), dim3(256), 0, s,
+                     slots, hash_bits, (unsigned long long*)filter, filter_bits, small);
   return hipGetLastError();
 }
 
@@ -350,40 +385,85 @@ hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, con
 // ACC_sigma entries are (d_x - 1) of the neighbours; ACC_tau entries are
 // (d_x - 1)(S_v - (d_x - 1)) with S_v the row total of ACC_sigma.
 // ---------------------------------------------------------------------------------
+// Entry e of a row answers the guide buckets whose lower bound b * 2^sh lies in
+// [lo, hi) (lo, hi: the finished prefix before and through e); the row's last entry
+// also those at or above the total.
+__device__ __forceinline__ void guide_entries(uint32_t* gd, int g, int sh, uint64_t lo, uint64_t hi, int32_t e,
+                                              int32_t r0, int32_t r1) {
+  const uint64_t b0 = lo ? ((lo - 1) >> sh) + 1 : 0ull;
+  uint64_t b1 = hi ? ((hi - 1) >> sh) + 1 : 0ull;
+  if (e == r1 - 1) b1 = (1ull << g) + 1;
+  for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - r0);
+}
+
+// Local prefix of every piece.  A row of one piece (d <= 256) is finished here: its
+// prefix is final, and its guide and (sigma) S_v are written from the values the wave
+// just computed; k_row_finish then only handles rows of several pieces.
 template <bool TAU>
 __global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  bool wrapped = false;
+  bool wrapped = false, over = false;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
     const ItemRange it = item_range(t.items, t.rp, i);
     const uint64_t S = TAU ? (uint64_t)t.rec[it.v].z : 0ull;
+    const bool single = it.e0 == it.r0 && it.e1 == it.r1;
     uint64_t carry = 0;
-    for (int32_t e0 = it.e0; e0 < it.e1; e0 += 64) {
-      const int32_t e = e0 + lane;
+    uint64_t keep[kItem / 64];  // this lane's prefix values (single-piece rows)
+#pragma unroll
+    for (int c = 0; c < kItem / 64; ++c) {
+      const int32_t e = it.e0 + c * 64 + lane;
+      keep[c] = 0;
+      if (it.e0 + c * 64 >= it.e1) continue;  // wave-uniform
       uint64_t x = 0;
       if (e < it.e1) {
         if (TAU) {  // the sigma entry d_x - 1, from the finished ACC_sigma
           const uint64_t dx = (uint64_t)t.acc_sigma[e] - (e > it.r0 ? (uint64_t)t.acc_sigma[e - 1] : 0ull);
           x = dx * (S - dx);
         } else {
-          const int32_t c = t.col[e];
-          x = (uint64_t)(t.rp[c + 1] - t.rp[c] - 1);
+          const int32_t c2 = t.col[e];
+          x = (uint64_t)(t.rp[c2 + 1] - t.rp[c2] - 1);
         }
       }
-      const uint64_t s = add_wrap(wave_inclusive_scan(x, wrapped), carry, wrapped);
+      const uint64_t sv = add_wrap(wave_inclusive_scan(x, wrapped), carry, wrapped);
       if (e < it.e1) {
-        if (TAU) t.acc_tau[e] = s;
-        else t.acc_sigma[e] = (uint32_t)s;
+        if (TAU) t.acc_tau[e] = sv;
+        else t.acc_sigma[e] = (uint32_t)sv;
       }
-      carry = __shfl(s, 63, 64);
+      keep[c] = sv;
+      carry = __shfl(sv, 63, 64);
     }
     if (lane == 0) t.item_sum[i] = carry;
+    if (!single) continue;
+    const uint64_t total = carry;
+    if (!TAU && total > 0xFFFFFFFFull) over = true;
+    const int32_t d = it.r1 - it.r0;
+    if (d >= kRowGuideMin) {
+      const int g = row_guide_bits(d);
+      const int sh = row_guide_shift(total, g);
+      uint32_t* gd = t.guide + t.rec[it.v].w;
+      uint64_t before = 0;
+#pragma unroll
+      for (int c = 0; c < kItem / 64; ++c) {
+        if (it.e0 + c * 64 >= it.e1) continue;
+        const int32_t e = it.e0 + c * 64 + lane;
+        uint64_t lo = __shfl_up(keep[c], 1, 64);
+        if (lane == 0) lo = before;
+        before = __shfl(keep[c], 63, 64);
+        if (e < it.e1) guide_entries(gd, g, sh, lo, keep[c], e, it.r0, it.r1);
+      }
+    }
+    if (!TAU && lane == 0) t.rec[it.v].z = (uint32_t)total;
   }
-  // a wrap inside a tau row is a Gamma^(2)_v beyond 64 bits; sigma pieces cannot wrap
+  // a wrap inside a tau row is a Gamma^(2)_v beyond 64 bits; a sigma row total beyond
+  // 32 bits does not fit ACC_sigma
   if (TAU && __ballot(wrapped) != 0 && lane == 0) atomicOr(err, kErrOverflowK5);
+  if (!TAU && __ballot(over) != 0 && lane == 0) atomicOr(err, kErrOverflow);
 }
 
+// Rows of several pieces: each piece adds the totals of its row's earlier pieces (at
+// most a few hundred, summed by the wave), then writes its share of the row guide;
+// the last piece records S_v (sigma).
 template <bool TAU>
 __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) {
   const int lane = lane_id();
@@ -391,6 +471,7 @@ __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) 
   bool over = false;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
     const ItemRange it = item_range(t.items, t.rp, i);
+    if (it.e0 == it.r0 && it.e1 == it.r1) continue;  // finished by k_prefix_local
     const int32_t d = it.r1 - it.r0;
     const int64_t first = i - it.piece, end = first + (d + kItem - 1) / kItem;
     // totals of the row's pieces before this one, and of the whole row
@@ -425,14 +506,7 @@ __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) 
       uint64_t lo = __shfl_up(hi, 1, 64);
       if (lane == 0) lo = carry;
       carry = __shfl(hi, 63, 64);
-      if (in && guided) {
-        // entry e answers the buckets whose lower bound b * 2^sh lies in [lo, hi);
-        // the last entry also those at or above the total
-        const uint64_t b0 = lo ? ((lo - 1) >> sh) + 1 : 0ull;
-        uint64_t b1 = hi ? ((hi - 1) >> sh) + 1 : 0ull;
-        if (e == it.r1 - 1) b1 = (1ull << g) + 1;
-        for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - it.r0);
-      }
+      if (in && guided) guide_entries(gd, g, sh, lo, hi, e, it.r0, it.r1);
     }
     if (!TAU && it.e1 == it.r1 && lane == 0) t.rec[it.v].z = (uint32_t)total;
   }
@@ -774,9 +848,8 @@ __device__ __forceinline__ int probe_edges(const SamplerView& a, const int32_t (
   for (int i = 0; i < P; ++i) {
     asm volatile("" ::: "memory");
     const uint64_t key = edge_key(x[i], y[i]);
-    const uint64_t z = mix64(key);
-    const uint64_t fm = filter_mask(z);
-    if ((a.filter[filter_word(z, a.filter_bits)] & fm) != fm) continue;
+    const uint64_t fm = filter_mask(mix64(key));
+    if ((a.filter[edge_slot(key, a.filter_bits)] & fm) != fm) continue;
     const uint64_t h = edge_slot(key, a.edge_bits);
     if (edge_hash_rest(a.edge_slots, a.edge_bits, key, h, a.edge_slots[h])) m |= 1 << i;
   }
