@@ -98,7 +98,9 @@ typedef struct {
   uint64_t gamma2;         /* Gamma^(2)  (Table 1) */
   uint64_t lambda3;        /* Lambda_3 = sum_v C(d_v, 3) (Table 1) */
   uint64_t lambda4;        /* Lambda_4 = sum_v C(d_v, 4) (Table 1) */
-  uint64_t device_bytes;   /* device memory held by the graph's tables (and CSR copy) */
+  uint64_t device_bytes;   /* device memory held by the graph's sampling tables (and CSR
+                              copy); the per-graph block made at creation (edge hash
+                              set and filter, work items, node records) is not counted */
 } moss_graph_info;
 
 typedef struct {
@@ -131,7 +133,11 @@ const char *moss_status_string(moss_status s);
  * and the first defect found is reported as MOSS_E_ARG / _UNSORTED / _SELF_LOOP /
  * _DUPLICATE / _ASYMMETRIC. */
 
-/* Copies host arrays row_ptr[n+1] and col[nnz] to the device.  The caller keeps
+/* Creation also builds the graph's edge hash set and edge filter (the induced-edge
+   probes of every sampler read them; the symmetry check uses the hash set) and the
+   work items and node records of the O(|E|) kernels.
+
+   Copies host arrays row_ptr[n+1] and col[nnz] to the device.  The caller keeps
    ownership of its arrays, which may be freed when the call returns. */
 moss_status moss_graph_create(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col,
                               uint32_t flags, void *hip_stream, moss_graph **out);
@@ -142,7 +148,8 @@ moss_status moss_graph_create_device(int32_t n, int64_t nnz, const int32_t *d_ro
                                      const int32_t *d_col, uint32_t flags, void *hip_stream,
                                      moss_graph **out);
 
-/* Waits for the graph's work, then frees its device tables (and CSR copy). */
+/* Waits for the graph's work, then releases all its device memory (the library keeps
+   released blocks, up to 1 GiB per device, for later graphs of the same size). */
 moss_status moss_graph_destroy(moss_graph *g);
 
 /* Initialization of Section 4.1.3 on the device, O(|E|): degrees, the node weights

@@ -412,7 +412,8 @@ int validate_error_status(uint32_t bits) {
 
 // Per-graph memory, events and the CSR checks shared by both creation paths: one
 // pass over the nodes, one scan pair (piece counts and row-guide lengths), items and
-// records, the column checks, one copy back and one synchronisation.
+// records, the edge hash set and filter, the column and symmetry checks, one copy
+// back and one synchronisation.
 moss_status finish_create(moss_graph* g) {
   const GraphLayout L = graph_layout(g->n, g->nnz);
   moss_status st = dev_alloc_bytes(g->stream, &g->mem_graph, L.bytes);
