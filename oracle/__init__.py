@@ -18,11 +18,12 @@ _LIB = os.path.join(_HERE, "libmoss_oracle.so")
 
 OK = 0
 E_ARG, E_UNSORTED, E_SELF_LOOP, E_DUPLICATE, E_ASYMMETRIC, E_OVERFLOW, E_NOMEM = -1, -2, -3, -4, -5, -6, -7
-MOSS4, T5, PATH5 = 4, 0x51, 0x52
+MOSS4, MOSS4MIN, T5, PATH5 = 4, 0x41, 0x51, 0x52
 MIX_POOLED, MIX_PAPER = 0, 1
 
 TAB_S, TAB_Q, TAB_GAMMA, TAB_GAMMA1, TAB_GAMMA2 = 0, 1, 2, 3, 4
 TAB_ACC_GAMMA, TAB_ACC_GAMMA1, TAB_ACC_GAMMA2, TAB_ACC_SIGMA, TAB_ACC_TAU = 5, 6, 7, 8, 9
+TAB_GAMMA_MIN, TAB_ACC_GAMMA_MIN, TAB_ACC_CHECK, TAB_RANK, TAB_RANK_MIRROR, TAB_COL_RANK = 10, 11, 12, 13, 14, 15
 
 _lock = threading.Lock()
 _lib = None
@@ -40,7 +41,8 @@ def build(force: bool = True) -> str:
 
 class _Totals(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_uint64), ("gamma1", ctypes.c_uint64), ("gamma2", ctypes.c_uint64),
-                ("lambda3", ctypes.c_uint64), ("lambda4", ctypes.c_uint64)]
+                ("lambda3", ctypes.c_uint64), ("lambda4", ctypes.c_uint64), ("gamma_min", ctypes.c_uint64),
+                ("min_status", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -72,6 +74,9 @@ def lib():
             L.orc_run.argtypes = [P, ctypes.c_int, u64, u64, u64, ctypes.c_int, P]
             L.orc_finals4.argtypes = [u64, P, u64, u64, P, P]
             L.orc_finals5.argtypes = [u64, u64, P, P, u64, u64, u64, ctypes.c_int, P, P, P]
+            L.orc_finals4min.argtypes = [u64, P, u64, u64, u64, P, u64, ctypes.c_int, P, P]
+            L.orc_ways_of.argtypes = [P, P]
+            L.orc_estimate4min.argtypes = [P, u64, u64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Result)]
             L.orc_estimate.argtypes = [P, ctypes.c_int, u64, u64, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(_Result)]
             L.orc_count_cis.argtypes = [P, ctypes.c_int, P]
@@ -149,12 +154,15 @@ class Graph:
     def totals(self) -> dict:
         t = _Totals()
         lib().orc_totals_get(self._h, ctypes.byref(t))
-        return dict(gamma=t.gamma, gamma1=t.gamma1, gamma2=t.gamma2, lambda3=t.lambda3, lambda4=t.lambda4)
+        return dict(gamma=t.gamma, gamma1=t.gamma1, gamma2=t.gamma2, lambda3=t.lambda3, lambda4=t.lambda4,
+                    gamma_min=t.gamma_min, min_status=t.min_status)
 
     def table(self, which: int) -> np.ndarray:
-        if which == TAB_ACC_SIGMA:
+        if which in (TAB_ACC_SIGMA, TAB_RANK, TAB_RANK_MIRROR):
             out = np.zeros(self.nnz, np.uint32)
-        elif which == TAB_ACC_TAU:
+        elif which == TAB_COL_RANK:
+            out = np.zeros(self.nnz, np.int32)
+        elif which in (TAB_ACC_TAU, TAB_ACC_CHECK):
             out = np.zeros(self.nnz, np.uint64)
         else:
             out = np.zeros(self.n, np.uint64)
@@ -182,6 +190,13 @@ class Graph:
         st = lib().orc_estimate(self._h, k, n_samples, seed, mix, threads, ctypes.byref(r))
         if st != OK:
             raise OracleError(st, "orc_estimate")
+        return Result(r)
+
+    def estimate4min(self, n_samples: int, seed: int, mix: int = MIX_POOLED, threads: int = 1) -> Result:
+        r = _Result()
+        st = lib().orc_estimate4min(self._h, n_samples, seed, mix, threads, ctypes.byref(r))
+        if st != OK:
+            raise OracleError(st, "orc_estimate4min")
         return Result(r)
 
     def count_cis(self, k: int) -> np.ndarray:
@@ -227,3 +242,21 @@ def finals5(K1: int, K2: int, hits1, hits2, gamma1: int, gamma2: int, lambda4: i
     if st != OK:
         raise OracleError(st, "orc_finals5")
     return est, var, cov.reshape(21, 21)
+
+
+def finals4min(K: int, hits, gamma: int, lambda3: int, Kc: int, hits_min, gamma_min: int, mix: int = MIX_POOLED):
+    h = np.ascontiguousarray(np.asarray(hits, dtype=np.uint64)[:7])
+    hm = np.ascontiguousarray(np.asarray(hits_min, dtype=np.uint64)[:10])
+    est = np.zeros(6)
+    var = np.zeros(6)
+    st = lib().orc_finals4min(K, _ptr(h), gamma, lambda3, Kc, _ptr(hm), gamma_min, mix, _ptr(est), _ptr(var))
+    if st != OK:
+        raise OracleError(st, "orc_finals4min")
+    return est, var
+
+
+def ways_of(adj, keys) -> int:
+    """Ordered MOSS-4Min draws (w, v, u, r) that give a 4-node set (adjacency 4x4, order keys)."""
+    a = np.ascontiguousarray(np.asarray(adj, dtype=np.uint8).reshape(16))
+    k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64).reshape(4))
+    return int(lib().orc_ways_of(_ptr(a), _ptr(k)))

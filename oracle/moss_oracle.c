@@ -32,6 +32,11 @@ struct orc_graph {
   uint64_t *acc_gam, *acc_gam1, *acc_gam2;
   uint32_t *acc_sigma;
   uint64_t *acc_tau;
+  /* MOSS-4Min (Section 4.2.1) */
+  uint32_t *rank, *rank_mirror;  /* per entry (v, x): d_{v,x} and d_{x,v} */
+  int32_t *col_rank;             /* rows in descending order */
+  uint64_t *acc_check;           /* per entry: row prefix of d_{v,x} d_{x,v} */
+  uint64_t *gmin, *acc_gmin;     /* check-Gamma_v and its prefix */
   orc_totals tot;
 };
 
@@ -215,10 +220,90 @@ static u128 choose(uint64_t d, int r) {
   return c;
 }
 
+/* ------------------------------------------------------------------------ */
+/* MOSS-4Min tables (Section 4.2.1).  The total order is the example of      */
+/* Section 3.2: a > b when d_a > d_b, or d_a = d_b and the id of a is larger. */
+/* As a number, key(a) = d_a * 2^32 + a, and a > b exactly when key(a) >     */
+/* key(b).  From Table 1: N_{u,v} = {x in N_u : x > v}, d_{u,v} = |N_{u,v}|. */
+/* MOSS-4Min weighs node v by check-Gamma_v = sum_{x in N_v} d_{v,x} d_{x,v}, */
+/* and u in N_v by d_{u,v} d_{v,u}.  Each row is also kept sorted by the      */
+/* order, largest first: there N_{v,x} is the first d_{v,x} entries of row v. */
+/* ------------------------------------------------------------------------ */
+static uint64_t order_key(const orc_graph *g, int32_t a) {
+  return ((uint64_t)(uint32_t)degree(g, a) << 32) | (uint64_t)(uint32_t)a;
+}
+
+static int key_descending(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? 1 : (x > y ? -1 : 0);
+}
+
+static int build_min_tables(orc_graph *g) {
+  size_t nn = (size_t)g->n + 1, ne = (size_t)g->nnz + 1;
+  int32_t dmax = 0;
+  for (int32_t v = 0; v < g->n; ++v) if (degree(g, v) > dmax) dmax = degree(g, v);
+  g->rank = (uint32_t *)calloc(ne, 4);
+  g->rank_mirror = (uint32_t *)calloc(ne, 4);
+  g->col_rank = (int32_t *)calloc(ne, 4);
+  g->acc_check = (uint64_t *)calloc(ne, 8);
+  g->gmin = (uint64_t *)calloc(nn, 8);
+  g->acc_gmin = (uint64_t *)calloc(nn, 8);
+  uint64_t *sorted = (uint64_t *)malloc((size_t)(dmax + 1) * 8);
+  if (!g->rank || !g->rank_mirror || !g->col_rank || !g->acc_check || !g->gmin || !g->acc_gmin || !sorted) {
+    free(sorted);
+    return ORC_E_NOMEM;
+  }
+  /* d_{v,x}: the number of keys of row v above key(x), i.e. x's place in the row
+     sorted largest first */
+  for (int32_t v = 0; v < g->n; ++v) {
+    int64_t base = g->rp[v], d = degree(g, v);
+    for (int64_t j = 0; j < d; ++j) sorted[j] = order_key(g, g->col[base + j]);
+    qsort(sorted, (size_t)d, sizeof(uint64_t), key_descending);
+    for (int64_t j = 0; j < d; ++j) g->col_rank[base + j] = (int32_t)(uint32_t)(sorted[j] & 0xFFFFFFFFu);
+    for (int64_t j = 0; j < d; ++j) {
+      uint64_t key = order_key(g, g->col[base + j]);
+      int64_t lo = 0, hi = d; /* first place whose key is not above `key` */
+      while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (sorted[mid] > key) lo = mid + 1; else hi = mid;
+      }
+      g->rank[base + j] = (uint32_t)lo;
+    }
+  }
+  free(sorted);
+  /* d_{x,v} from the entry (x, v) of row x; weights, row prefixes and node weights */
+  u128 tot = 0;
+  g->tot.min_status = ORC_OK;
+  for (int32_t v = 0; v < g->n; ++v) {
+    u128 s = 0;
+    for (int64_t e = g->rp[v]; e < g->rp[v + 1]; ++e) {
+      int32_t x = g->col[e];
+      int64_t lo = g->rp[x], hi = g->rp[x + 1], m = -1;
+      while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (g->col[mid] == v) { m = mid; break; }
+        if (g->col[mid] < v) lo = mid + 1; else hi = mid;
+      }
+      if (m < 0) return ORC_E_ASYMMETRIC; /* only without validation */
+      g->rank_mirror[e] = g->rank[m];
+      s += (u128)g->rank[e] * g->rank_mirror[e];
+      if (!fits(s)) g->tot.min_status = ORC_E_OVERFLOW;
+      g->acc_check[e] = (uint64_t)s;
+    }
+    g->gmin[v] = (uint64_t)s;
+    tot += s;
+    if (!fits(tot)) g->tot.min_status = ORC_E_OVERFLOW;
+    g->acc_gmin[v] = (uint64_t)tot;
+  }
+  g->tot.gamma_min = g->tot.min_status == ORC_OK ? (uint64_t)tot : 0;
+  return ORC_OK;
+}
+
 void orc_free(orc_graph *g) {
   if (!g) return;
   free(g->rp); free(g->col); free(g->S); free(g->Q); free(g->gam); free(g->gam1); free(g->gam2);
   free(g->acc_gam); free(g->acc_gam1); free(g->acc_gam2); free(g->acc_sigma); free(g->acc_tau);
+  free(g->rank); free(g->rank_mirror); free(g->col_rank); free(g->acc_check); free(g->gmin); free(g->acc_gmin);
   free(g);
 }
 
@@ -298,6 +383,8 @@ int orc_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col
   g->tot.gamma2 = (uint64_t)tot_gam2;
   g->tot.lambda3 = (uint64_t)lam3;
   g->tot.lambda4 = (uint64_t)lam4;
+  int st = build_min_tables(g);
+  if (st != ORC_OK) { orc_free(g); return st; }
   *out = g;
   return ORC_OK;
 }
@@ -322,6 +409,12 @@ int orc_table(const orc_graph *g, int which, void *out) {
     case ORC_TAB_ACC_GAMMA2: memcpy(out, g->acc_gam2, n8); break;
     case ORC_TAB_ACC_SIGMA: memcpy(out, g->acc_sigma, (size_t)g->nnz * 4); break;
     case ORC_TAB_ACC_TAU: memcpy(out, g->acc_tau, (size_t)g->nnz * 8); break;
+    case ORC_TAB_GAMMA_MIN: memcpy(out, g->gmin, n8); break;
+    case ORC_TAB_ACC_GAMMA_MIN: memcpy(out, g->acc_gmin, n8); break;
+    case ORC_TAB_ACC_CHECK: memcpy(out, g->acc_check, (size_t)g->nnz * 8); break;
+    case ORC_TAB_RANK: memcpy(out, g->rank, (size_t)g->nnz * 4); break;
+    case ORC_TAB_RANK_MIRROR: memcpy(out, g->rank_mirror, (size_t)g->nnz * 4); break;
+    case ORC_TAB_COL_RANK: memcpy(out, g->col_rank, (size_t)g->nnz * 4); break;
     default: return ORC_E_ARG;
   }
   return ORC_OK;
@@ -330,7 +423,8 @@ int orc_table(const orc_graph *g, int which, void *out) {
 /* ------------------------------------------------------------------------ */
 /* Memory-read recorder for the line-count mode (inactive when rec == NULL).  */
 /* ------------------------------------------------------------------------ */
-enum { ARR_RP = 0, ARR_COL, ARR_ACC_NODE, ARR_ACC_SIGMA, ARR_ACC_TAU };
+enum { ARR_RP = 0, ARR_COL, ARR_ACC_NODE, ARR_ACC_SIGMA, ARR_ACC_TAU, ARR_ACC_CHECK, ARR_RANK, ARR_RANK_MIRROR,
+       ARR_COL_RANK };
 typedef struct { int n; uint64_t key[512]; } reads;
 
 static void note(reads *rec, int arr, int64_t idx, int width) {
@@ -369,6 +463,16 @@ static int64_t pick_tau(const orc_graph *g, int64_t base, int64_t len, uint64_t 
     int64_t mid = lo + (hi - lo) / 2;
     note(rec, ARR_ACC_TAU, base + mid, 8);
     if (g->acc_tau[base + mid] > r) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+static int64_t pick_check(const orc_graph *g, int64_t base, int64_t len, uint64_t r, reads *rec) {
+  int64_t lo = 0, hi = len - 1;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    note(rec, ARR_ACC_CHECK, base + mid, 8);
+    if (g->acc_check[base + mid] > r) hi = mid; else lo = mid + 1;
   }
   return lo;
 }
@@ -438,6 +542,10 @@ static const int KNOWN5_T[10] = {1, 1, 1, 0, 0, 0, 1, 0, 0, 0};
 /* tau^(v), w ~ mu^(v,u) over N_v - {u}, r uniform in N_u - {v}, t uniform in  */
 /* N_w - {v}; dropped when t = u, r = w or t = r.  Known edges vu, vw, ur, wt. */
 static const int KNOWN5_P[10] = {1, 1, 0, 0, 0, 1, 0, 0, 1, 0};
+/* MOSS-4Min (Section 4.2.1, Algorithm 2): v ~ check-pi (weights check-Gamma_v), u ~  */
+/* check-sigma^(v) (weights d_{u,v} d_{v,u} over N_v), w uniform in N_{v,u}, r       */
+/* uniform in N_{u,v}; dropped when r = w (r = u cannot happen).  Known edges vu,   */
+/* vw, ur, as for MOSS-4.                                                           */
 /* pair order for 5 nodes (v,u,w,r,t):
    (v,u),(v,w),(v,r),(v,t),(u,w),(u,r),(u,t),(w,r),(w,t),(r,t) */
 
@@ -456,6 +564,28 @@ static int sample_one(const orc_graph *g, int sampler, uint64_t seed, uint64_t k
     if (j >= iu) ++j;
     int32_t w = col_at(g, base + j, rec);
     int32_t r = neighbour_skipping(g, u, v, W[3], rec);
+    nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = -1;
+    if (r == w) return 0;
+    return rec ? class_of_counting(4, nodes, g, rec, KNOWN4) : class_of(4, nodes, g, NULL);
+  }
+  if (sampler == ORC_MOSS4MIN) {
+    if (g->tot.min_status != ORC_OK) return g->tot.min_status;
+    if (g->tot.gamma_min == 0) return ORC_E_ARG;
+    int32_t v = (int32_t)pick_node(g->acc_gmin, g->n, orc_bounded(W[0], g->tot.gamma_min), rec);
+    int64_t base = rp_at(g, v, rec), dv = rp_at(g, v + 1, rec) - base;
+    note(rec, ARR_ACC_CHECK, base + dv - 1, 8);
+    int64_t iu = pick_check(g, base, dv, orc_bounded(W[1], g->acc_check[base + dv - 1]), rec);
+    int32_t u = col_at(g, base + iu, rec);
+    note(rec, ARR_RANK, base + iu, 4);
+    note(rec, ARR_RANK_MIRROR, base + iu, 4);
+    uint64_t dvu = g->rank[base + iu], duv = g->rank_mirror[base + iu];
+    /* N_{v,u} is the first d_{v,u} entries of row v taken largest first */
+    int64_t jw = base + (int64_t)orc_bounded(W[2], dvu);
+    note(rec, ARR_COL_RANK, jw, 4);
+    int32_t w = g->col_rank[jw];
+    int64_t jr = rp_at(g, u, rec) + (int64_t)orc_bounded(W[3], duv);
+    note(rec, ARR_COL_RANK, jr, 4);
+    int32_t r = g->col_rank[jr];
     nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = -1;
     if (r == w) return 0;
     return rec ? class_of_counting(4, nodes, g, rec, KNOWN4) : class_of(4, nodes, g, NULL);
@@ -517,6 +647,32 @@ int orc_sample(const orc_graph *g, int sampler, uint64_t seed, uint64_t k, int32
   return sample_one(g, sampler, seed, k, nodes, NULL);
 }
 
+/* The draws of MOSS-4Min that give a node set s: ordered tuples (w, v, u, r) of its
+   nodes with edges w-v, v-u, u-r, w > u (w in N_{v,u}) and r > v (r in N_{u,v}).  Each
+   such tuple has probability 1/check-Gamma (the node, edge and two uniform draws of
+   Section 4.2.1 multiply to it), so s is drawn with probability c(s)/check-Gamma. */
+int orc_ways_of(const uint8_t adj[16], const uint64_t key[4]) {
+  int c = 0;
+  for (int w = 0; w < 4; ++w)
+    for (int v = 0; v < 4; ++v)
+      for (int u = 0; u < 4; ++u)
+        for (int r = 0; r < 4; ++r) {
+          if (w == v || w == u || w == r || v == u || v == r || u == r) continue;
+          if (adj[w * 4 + v] && adj[v * 4 + u] && adj[u * 4 + r] && key[w] > key[u] && key[r] > key[v]) ++c;
+        }
+  return c;
+}
+
+static int ways_of_nodes(const orc_graph *g, const int32_t nodes[4]) {
+  uint8_t adj[16];
+  uint64_t key[4];
+  for (int i = 0; i < 4; ++i) {
+    key[i] = order_key(g, nodes[i]);
+    for (int j = 0; j < 4; ++j) adj[i * 4 + j] = i != j && is_adj(g, nodes[i], nodes[j], NULL);
+  }
+  return orc_ways_of(adj, key);
+}
+
 typedef struct {
   const orc_graph *g;
   int sampler;
@@ -532,6 +688,7 @@ static void *run_range(void *arg) {
     int c = sample_one(job->g, job->sampler, job->seed, k, nodes, NULL);
     if (c < 0) { job->status = c; return NULL; }
     ++job->hits[c];
+    if (job->sampler == ORC_MOSS4MIN && c == 5) ++job->hits[6 + ways_of_nodes(job->g, nodes) / 2];
   }
   return NULL;
 }
@@ -539,9 +696,14 @@ static void *run_range(void *arg) {
 int orc_run(const orc_graph *g, int sampler, uint64_t seed, uint64_t k0, uint64_t k1, int nthreads,
             uint64_t hits[22]) {
   if (!g || !hits || k1 < k0) return ORC_E_ARG;
-  if (sampler != ORC_MOSS4 && sampler != ORC_T5 && sampler != ORC_PATH5) return ORC_E_ARG;
+  if (sampler != ORC_MOSS4 && sampler != ORC_MOSS4MIN && sampler != ORC_T5 && sampler != ORC_PATH5)
+    return ORC_E_ARG;
+  if (sampler == ORC_MOSS4MIN && g->tot.min_status != ORC_OK) return g->tot.min_status;
   memset(hits, 0, 22 * sizeof(uint64_t));
-  uint64_t total = sampler == ORC_MOSS4 ? g->tot.gamma : sampler == ORC_T5 ? g->tot.gamma1 : g->tot.gamma2;
+  uint64_t total = sampler == ORC_MOSS4      ? g->tot.gamma
+                   : sampler == ORC_MOSS4MIN ? g->tot.gamma_min
+                   : sampler == ORC_T5       ? g->tot.gamma1
+                                             : g->tot.gamma2;
   if (total == 0 || k1 == k0) return ORC_OK; /* nothing can be drawn */
   if (nthreads < 1) nthreads = 1;
   if ((uint64_t)nthreads > k1 - k0) nthreads = (int)(k1 - k0);
@@ -676,6 +838,109 @@ int orc_finals5(uint64_t K1, uint64_t K2, const uint64_t hits1[22], const uint64
       }
   }
   return ORC_OK;
+}
+
+/* MOSS-4 together with MOSS-4Min (Section 4.2: Algorithm 2, Theorems 4 and 5, and
+   Theorem 1's mix for n_3, n_5, n_6).
+   MOSS-4Min reaches a CIS s with probability c(s)/check-Gamma (orc_ways_of).  For
+   the 4-cycle c = 2 and for the 4-clique c = 6, as Theorem 4 states; a diamond has
+   c = 2, 4 or 6 depending on how its nodes are ordered, so Theorem 4's constant is
+   replaced by each sample's own c (a Horvitz-Thompson weight):
+     check-n_i = (check-Gamma / Kc) sum_c m_{i,c} / c,
+     Var = (A_i - n_i^2) / Kc with A_i = sum_{s in C_i} check-Gamma / c(s),
+   A_i estimated by (check-Gamma^2 / Kc) sum_c m_{i,c} / c^2 (unbiased); for c fixed
+   this is Theorem 5.  Mix weights lambda_i (on MOSS-4), as for 5 nodes:
+     pooled: lambda_i = K p_i / (K p_i + Kc q_i), q_3 = 2/check-Gamma, q_6 = 6/check-Gamma,
+             q_5 = 2/check-Gamma (the least reach; a fixed weight keeps the mix
+             unbiased), Var = lambda^2 V_1 + (1 - lambda)^2 V_2 with both variances at
+             the mixed estimate (A_3 = n_3 / q_3, A_6 = n_6 / q_6, A_5 from the samples);
+     paper:  lambda_i = V_2 / (V_1 + V_2) with V_1, V_2 at the pooled estimate,
+             Var = V_1 V_2 / (V_1 + V_2).
+   n_1, n_4 as MOSS-4 alone; n_2 = Lambda_3 - n_4 - 2 n_5 - 4 n_6 with variance
+     (n_4/p_4 + 4 l_5^2 n_5/p_5 + 16 l_6^2 n_6/p_6 - (n_4 + 2 l_5 n_5 + 4 l_6 n_6)^2) / K
+   + (4 (1-l_5)^2 A_5 + 16 (1-l_6)^2 A_6 - (2 (1-l_5) n_5 + 4 (1-l_6) n_6)^2) / Kc,
+   each part taken as 0 when negative (the samplers are independent). */
+int orc_finals4min(uint64_t K, const uint64_t hits[7], uint64_t gamma, uint64_t lambda3, uint64_t Kc,
+                   const uint64_t hits_min[10], uint64_t gamma_min, int mix, double est[6], double var[6]) {
+  if (!hits || !hits_min || !est || !var || (K == 0 && Kc == 0)) return ORC_E_ARG;
+  if (mix != ORC_MIX_POOLED && mix != ORC_MIX_PAPER) return ORC_E_ARG;
+  const double Kd = (double)K, Kcd = (double)Kc, G = (double)gamma, Gc = (double)gamma_min;
+  double p[7] = {0}, q[7] = {0}, nhat[7] = {0}, ncheck[7] = {0}, lam[7], A5 = 0.0;
+  for (int i = 0; i < 6; ++i) { est[i] = 0.0; var[i] = 0.0; }
+  for (int i = 0; i < 7; ++i) lam[i] = 1.0;
+  if (K > 0 && gamma > 0)
+    for (int i = 1; i <= 6; ++i) {
+      if (PHI4_PATH[i] == 0) continue;
+      p[i] = 2.0 * (double)PHI4_PATH[i] / G;
+      nhat[i] = (double)hits[i] / (Kd * p[i]);
+    }
+  if (Kc > 0 && gamma_min > 0) {
+    q[3] = 2.0 / Gc; q[5] = 2.0 / Gc; q[6] = 6.0 / Gc;
+    ncheck[3] = (double)hits_min[3] * Gc / (2.0 * Kcd);
+    ncheck[6] = (double)hits_min[6] * Gc / (6.0 * Kcd);
+    ncheck[5] = Gc / Kcd * ((double)hits_min[7] / 2.0 + (double)hits_min[8] / 4.0 + (double)hits_min[9] / 6.0);
+    A5 = Gc * Gc / Kcd * ((double)hits_min[7] / 4.0 + (double)hits_min[8] / 16.0 + (double)hits_min[9] / 36.0);
+  }
+  /* n_1, n_4: MOSS-4 alone (Theorems 2 and 3) */
+  for (int i = 1; i <= 4; i += 3) {
+    if (p[i] == 0.0) continue;
+    est[i - 1] = nhat[i];
+    double v = nhat[i] / Kd * (1.0 / p[i] - nhat[i]);
+    var[i - 1] = v > 0.0 ? v : 0.0;
+  }
+  for (int i = 3; i <= 6; ++i) {
+    if (i == 4) continue;
+    double a = Kd * p[i], b = Kcd * q[i], D = a + b;
+    if (D == 0.0) continue;
+    double l = a / D;
+    double e = l * nhat[i] + (1.0 - l) * ncheck[i];
+    double v1 = p[i] > 0.0 ? e / Kd * (1.0 / p[i] - e) : 0.0;
+    double Ai = i == 5 ? A5 : (q[i] > 0.0 ? e / q[i] : 0.0);
+    double v2 = q[i] > 0.0 ? (Ai - e * e) / Kcd : 0.0;
+    if (v1 < 0.0) v1 = 0.0;
+    if (v2 < 0.0) v2 = 0.0;
+    double v;
+    if (mix == ORC_MIX_PAPER && p[i] > 0.0 && q[i] > 0.0 && v1 + v2 > 0.0) {
+      l = v2 / (v1 + v2);
+      e = l * nhat[i] + (1.0 - l) * ncheck[i];
+      v = v1 * v2 / (v1 + v2);
+    } else {
+      v = l * l * v1 + (1.0 - l) * (1.0 - l) * v2;
+    }
+    lam[i] = l;
+    est[i - 1] = e;
+    var[i - 1] = v > 0.0 ? v : 0.0;
+  }
+  double n4 = est[3], n5 = est[4], n6 = est[5];
+  est[1] = (double)lambda3 - n4 - 2.0 * n5 - 4.0 * n6;
+  double X = 0.0, Y = 0.0;
+  if (p[4] > 0.0) {
+    double s = n4 + 2.0 * lam[5] * n5 + 4.0 * lam[6] * n6;
+    X = (n4 / p[4] + 4.0 * lam[5] * lam[5] * n5 / p[5] + 16.0 * lam[6] * lam[6] * n6 / p[6] - s * s) / Kd;
+    if (X < 0.0) X = 0.0;
+  }
+  if (q[6] > 0.0) {
+    double m5 = 1.0 - lam[5], m6 = 1.0 - lam[6];
+    double t = 2.0 * m5 * n5 + 4.0 * m6 * n6;
+    Y = (4.0 * m5 * m5 * A5 + 16.0 * m6 * m6 * (n6 / q[6]) - t * t) / Kcd;
+    if (Y < 0.0) Y = 0.0;
+  }
+  var[1] = X + Y;
+  return ORC_OK;
+}
+
+int orc_estimate4min(const orc_graph *g, uint64_t n_samples, uint64_t seed, int mix, int nthreads,
+                     orc_result *res) {
+  if (!g || !res || n_samples < 2) return ORC_E_ARG;
+  memset(res, 0, sizeof(*res));
+  uint64_t K = (n_samples + 1) / 2, Kc = n_samples / 2;
+  res->k = 4; res->n_motifs = 6; res->K[0] = K; res->K[1] = Kc;
+  int st = orc_run(g, ORC_MOSS4, seed, 0, K, nthreads, res->hits[0]);
+  if (st) return st;
+  st = orc_run(g, ORC_MOSS4MIN, seed, 0, Kc, nthreads, res->hits[1]);
+  if (st) return st;
+  return orc_finals4min(K, res->hits[0], g->tot.gamma, g->tot.lambda3, Kc, res->hits[1], g->tot.gamma_min, mix,
+                        res->estimate, res->variance);
 }
 
 int orc_estimate(const orc_graph *g, int k, uint64_t n_samples, uint64_t seed, int mix, int nthreads,

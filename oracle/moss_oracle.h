@@ -11,7 +11,8 @@
  * mapped to an outcome, how an excluded element is skipped), the oracle follows
  * one fixed sampling contract:
  *   words    B(k, j) = Philox4x64-10(counter = (k, j, 0, 0), key = (seed, tag)),
- *            tag 0x4 for MOSS-4, 0x51 for T-5, 0x52 for Path-5, k the sample index
+ *            tag 0x4 for MOSS-4, 0x41 for MOSS-4Min, 0x51 for T-5, 0x52 for Path-5,
+ *            k the sample index
  *   bounded  U(x, N) = floor(x * N / 2^64)
  *   pick     pick(A, x) = min{ i : A[i] > U(x, A[L-1]) } over an inclusive prefix A
  *   skips    an index draw that must avoid positions a < b is shifted past them in
@@ -32,7 +33,7 @@ enum {
 };
 
 /* sampler ids */
-enum { ORC_MOSS4 = 4, ORC_T5 = 0x51, ORC_PATH5 = 0x52 };
+enum { ORC_MOSS4 = 4, ORC_MOSS4MIN = 0x41, ORC_T5 = 0x51, ORC_PATH5 = 0x52 };
 
 /* mix modes for 5-node finals */
 enum { ORC_MIX_POOLED = 0, ORC_MIX_PAPER = 1 };
@@ -50,11 +51,21 @@ enum {
   ORC_TAB_ACC_GAMMA1 = 6, /* u64[n]                                               */
   ORC_TAB_ACC_GAMMA2 = 7, /* u64[n]                                               */
   ORC_TAB_ACC_SIGMA = 8,  /* u32[nnz] row-local inclusive prefix of (d_x - 1)     */
-  ORC_TAB_ACC_TAU = 9     /* u64[nnz] row-local inclusive prefix of the tau weights */
+  ORC_TAB_ACC_TAU = 9,    /* u64[nnz] row-local inclusive prefix of the tau weights */
+  /* MOSS-4Min (Section 4.2.1), with the order a > b when d_a > d_b, or d_a = d_b and a > b */
+  ORC_TAB_GAMMA_MIN = 10,     /* u64[n]   check-Gamma_v = sum_{x in N_v} d_{v,x} d_{x,v}    */
+  ORC_TAB_ACC_GAMMA_MIN = 11, /* u64[n]   inclusive prefix of check-Gamma_v                  */
+  ORC_TAB_ACC_CHECK = 12,     /* u64[nnz] row-local inclusive prefix of d_{v,x} d_{x,v}      */
+  ORC_TAB_RANK = 13,          /* u32[nnz] d_{v,x} for the entry (v, x)                       */
+  ORC_TAB_RANK_MIRROR = 14,   /* u32[nnz] d_{x,v} for the entry (v, x)                       */
+  ORC_TAB_COL_RANK = 15       /* i32[nnz] each row N_v in descending order                   */
 };
 
 typedef struct {
   uint64_t gamma, gamma1, gamma2, lambda3, lambda4;
+  uint64_t gamma_min;        /* check-Gamma (Table 1), valid when min_status == ORC_OK */
+  int32_t min_status;        /* ORC_OK, or ORC_E_OVERFLOW when a MOSS-4Min prefix needs > 64 bits */
+  int32_t pad;
 } orc_totals;
 
 typedef struct {
@@ -79,7 +90,9 @@ int64_t orc_pick_u64(const uint64_t *acc, int64_t len, uint64_t x);
 int orc_classify(int k, const uint8_t *adj /* k*k row-major 0/1 */);
 
 /* one sample by index; nodes[] gets v,u,w,r(,t); returns class (0 = rejected),
-   or a negative status */
+   or a negative status.  MOSS-4Min hits: [0] rejected, [1..6] per class, and the
+   diamonds (class 5) once more by the number of ways c(s) in {2, 4, 6} that the
+   sampler can reach them: [7] c = 2, [8] c = 4, [9] c = 6. */
 int orc_sample(const orc_graph *g, int sampler, uint64_t seed, uint64_t k, int32_t nodes[5]);
 
 /* hits over sample indices [k0, k1) of one sampler, split over nthreads threads */
@@ -93,10 +106,28 @@ int orc_finals5(uint64_t K1, uint64_t K2, const uint64_t hits1[22], const uint64
                 uint64_t gamma1, uint64_t gamma2, uint64_t lambda4, int mix,
                 double est[21], double var[21], double *cov /* 21*21 or NULL */);
 
+/* MOSS-4 with K samples and MOSS-4Min with Kc samples, mixed for n_3, n_5, n_6
+   (Section 4.2 with Theorem 1).  MOSS-4Min's estimate weights each sample by the
+   inverse of its own CIS's probability c(s) / check-Gamma (c(s) the number of
+   ordered draws that reach s; Theorem 4's constants hold for c = 2 of the 4-cycle and
+   c = 6 of the 4-clique, but a diamond has c in {2, 4, 6}).  K = 0 or Kc = 0 leaves
+   that sampler out (not both). */
+int orc_finals4min(uint64_t K, const uint64_t hits[7], uint64_t gamma, uint64_t lambda3, uint64_t Kc,
+                   const uint64_t hits_min[10], uint64_t gamma_min, int mix, double est[6], double var[6]);
+
+/* Number of ordered node tuples (w, v, u, r) of the 4-node set whose pairwise
+   adjacency is adj (4x4, 0/1) and whose order keys are key[] (a > b iff key[a] >
+   key[b]) with edges w-v, v-u, u-r, w > u and r > v: the draws of MOSS-4Min that
+   give this set. */
+int orc_ways_of(const uint8_t adj[16], const uint64_t key[4]);
+
 /* the whole estimate: k=4 -> MOSS-4 with K samples; k=5 -> T-5 with ceil(K/2) and
    Path-5 with floor(K/2) samples, then the mix */
 int orc_estimate(const orc_graph *g, int k, uint64_t n_samples, uint64_t seed, int mix,
                  int nthreads, orc_result *res);
+/* k = 4 with MOSS-4 on ceil(n/2) and MOSS-4Min on floor(n/2) samples (n >= 2), mixed */
+int orc_estimate4min(const orc_graph *g, uint64_t n_samples, uint64_t seed, int mix, int nthreads,
+                     orc_result *res);
 
 /* exact counts of k-node connected induced subgraphs per class (ESU enumeration) */
 int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]);

@@ -261,3 +261,66 @@ def class_distribution(csr, sampler):
 
 def choose(n, r):
     return comb(n, r) if n >= r >= 0 else 0
+
+
+# --- MOSS-4Min (Section 4.2.1), exact rationals ------------------------------
+# The order of Section 3.2's example: a above b when d_a > d_b, or d_a = d_b and a > b.
+def above(d, a, b) -> bool:
+    return d[a] > d[b] or (d[a] == d[b] and a > b)
+
+
+def moss4min_weights(csr):
+    """d_{v,x} = |{y in N_v : y above x}| for every entry, check-Gamma_v and each row in
+    descending order, counted pair by pair from Table 1's definitions."""
+    A = [sorted(s) for s in csr.adjacency_sets()]
+    d = [len(a) for a in A]
+    dvx = {}
+    for v in range(csr.n):
+        for x in A[v]:
+            dvx[(v, x)] = sum(1 for y in A[v] if above(d, y, x))
+    gmin = [sum(dvx[(v, x)] * dvx[(x, v)] for x in A[v]) for v in range(csr.n)]
+    desc = []
+    for v in range(csr.n):
+        row = list(A[v])
+        # insertion by pairwise comparison: y goes before every x it is above
+        ordered = []
+        for y in row:
+            pos = 0
+            while pos < len(ordered) and above(d, ordered[pos], y):
+                pos += 1
+            ordered.insert(pos, y)
+        desc.append(ordered)
+    return A, d, dvx, gmin, desc
+
+
+def moss4min_distribution(csr):
+    """{(v, u, w, r): probability} of the five steps of Section 4.2.1: v with weight
+    check-Gamma_v, u in N_v with weight d_{u,v} d_{v,u}, w uniform in N_{v,u}, r uniform
+    in N_{u,v}."""
+    A, d, dvx, gmin, _ = moss4min_weights(csr)
+    G = sum(gmin)
+    out = {}
+    for v in range(csr.n):
+        if gmin[v] == 0:
+            continue
+        for u in A[v]:
+            wu = dvx[(u, v)] * dvx[(v, u)]
+            if wu == 0:
+                continue
+            pu = Fraction(gmin[v], G) * Fraction(wu, gmin[v])
+            Nvu = [x for x in A[v] if above(d, x, u)]
+            Nuv = [x for x in A[u] if above(d, x, v)]
+            for w in Nvu:
+                for r in Nuv:
+                    out[(v, u, w, r)] = pu / len(Nvu) / len(Nuv)
+    return out, G
+
+
+def ways(adjsets, d, nodes) -> int:
+    """c(s): ordered tuples (w, v, u, r) of the set with edges w-v, v-u, u-r, w above u and
+    r above v (by permutations)."""
+    c = 0
+    for w, v, u, r in itertools.permutations(nodes):
+        if v in adjsets[w] and u in adjsets[v] and r in adjsets[u] and above(d, w, u) and above(d, r, v):
+            c += 1
+    return c
