@@ -4,10 +4,10 @@
  * of 4-node connected induced subgraphs (CISes) of each motif class of an
  * undirected simple graph, and eta_1..eta_21 for 5 nodes (problem statement,
  * Section 2), by drawing independent samples with degree-based probabilities
- * (MOSS-4, Section 4.1, Algorithm 1; T-5 and Path-5, Section 5.1, Algorithms 3
- * and 4), classifying each sample and scaling the per-class hit counts by the
- * inverse sampling probability (Theorems 2, 6, 8), with the exact variance
- * formulas of Theorems 3 and 10.
+ * (MOSS-4, Section 4.1, Algorithm 1; MOSS-4Min, Section 4.2, Algorithm 2; T-5 and
+ * Path-5, Section 5.1, Algorithms 3 and 4), classifying each sample and scaling the
+ * per-class hit counts by the inverse sampling probability (Theorems 2, 4, 6, 8),
+ * with the exact variance formulas of Theorems 3, 5 and 10.
  *
  * Conventions for every call:
  *  - Every call returns a moss_status; outputs are written only on MOSS_OK.
@@ -59,6 +59,7 @@ typedef enum {
 
 /* sampler ids (also the Philox key tag of each sampler) */
 #define MOSS_SAMPLER_MOSS4 0x4   /* Algorithm 1 */
+#define MOSS_SAMPLER_MOSS4MIN 0x41 /* Algorithm 2 */
 #define MOSS_SAMPLER_T5 0x51     /* Algorithm 3 */
 #define MOSS_SAMPLER_PATH5 0x52  /* Algorithm 4 */
 
@@ -71,10 +72,16 @@ typedef enum {
 #define MOSS_MIX_POOLED 0x0u     /* lambda^(l)_i = K_l p^(l)_i / sum_l K_l p^(l)_i (default) */
 #define MOSS_MIX_PAPER 0x1u      /* lambda from the Theorem 7/9 variances evaluated at the
                                     pooled estimate (Eq. mixestimator, Eq. varianceMix) */
+/* estimate flag for k = 4: run MOSS-4 and MOSS-4Min on half the budget each and mix
+   their estimates of n_3, n_5, n_6 (Section 4.2, Theorem 1), with the pooled or the
+   paper's weights as for 5 nodes */
+#define MOSS_K4_MIN 0x2u
 
 /* table-build mask bits */
 #define MOSS_TABLES_K4 (1u << 4) /* ACC_Gamma, ACC_sigma, node guide */
 #define MOSS_TABLES_K5 (1u << 5) /* ACC_Gamma1, ACC_Gamma2, ACC_sigma, ACC_tau, guides */
+#define MOSS_TABLES_K4MIN (1u << 6) /* MOSS-4Min: rank tables, rows in descending order,
+                                       ACC_check, ACC_check-Gamma, guides */
 
 /* tables that moss_table_read can copy out */
 #define MOSS_TAB_ACC_GAMMA 5     /* u64[n]  inclusive prefix of Gamma_v     (Section 4.1.3) */
@@ -84,6 +91,13 @@ typedef enum {
                                     Section 4.1.3 = ACC_mu, Section 5.1.5) */
 #define MOSS_TAB_ACC_TAU 9       /* u64[nnz] row-local inclusive prefix of the tau weights
                                     (d_u - 1)(S_v - (d_u - 1)) (Section 5.1.2, step 2) */
+/* MOSS-4Min (Section 4.2.1) with the order of Section 3.2: a above b when d_a > d_b, or
+   d_a = d_b and a > b; N_{v,x} = {y in N_v : y above x}, d_{v,x} = |N_{v,x}| (Table 1) */
+#define MOSS_TAB_ACC_GAMMA_MIN 11 /* u64[n]   inclusive prefix of check-Gamma_v =
+                                     sum_{x in N_v} d_{v,x} d_{x,v} */
+#define MOSS_TAB_ACC_CHECK 12    /* u64[nnz] row-local inclusive prefix of d_{v,x} d_{x,v} */
+#define MOSS_TAB_RANK 13         /* u32 pairs, count nnz: per entry (v, x) d_{v,x}, d_{x,v} */
+#define MOSS_TAB_COL_RANK 15     /* i32[nnz] each row N_v in descending order */
 
 typedef struct moss_graph moss_graph;
 
@@ -101,6 +115,7 @@ typedef struct {
   uint64_t device_bytes;   /* device memory held by the graph's sampling tables (and CSR
                               copy); the per-graph block made at creation (edge hash
                               set and filter, work items, node records) is not counted */
+  uint64_t gamma_min;      /* check-Gamma (Table 1), valid once K4MIN tables are built */
 } moss_graph_info;
 
 typedef struct {
@@ -111,11 +126,16 @@ typedef struct {
   uint64_t n_samples;      /* requested budget */
   uint64_t K[2];           /* k=4: K[0] = n_samples, K[1] = 0; k=5: K[0] = K_1 = ceil(n/2)
                               T-5 samples, K[1] = K_2 = floor(n/2) Path-5 samples (Section
-                              5.1.4 sets K_1 = K_2) */
+                              5.1.4 sets K_1 = K_2); k=4 with MOSS_K4_MIN: K[0] = ceil(n/2)
+                              MOSS-4 and K[1] = floor(n/2) MOSS-4Min samples */
   uint64_t hits[2][22];    /* per sampler: [0] rejected samples, [i] samples of class i
-                              (m_i, Sections 4.1.2 and 5.1.1-5.1.2); sum = K[s], or all
-                              zero when the sampler's Gamma is 0 */
-  uint64_t gamma[2];       /* k=4: Gamma; k=5: Gamma^(1), Gamma^(2) */
+                              (m_i, Sections 4.1.2 and 5.1.1-5.1.2); the class counts sum
+                              to K[s], or are all zero when the sampler's Gamma is 0.
+                              MOSS-4Min also counts its diamonds (class 5) by the number c
+                              of ordered draws that reach them: [7] c = 2, [8] c = 4,
+                              [9] c = 6 (not part of that sum) */
+  uint64_t gamma[2];       /* k=4: Gamma (and check-Gamma with MOSS_K4_MIN);
+                              k=5: Gamma^(1), Gamma^(2) */
   uint64_t lambda;         /* k=4: Lambda_3; k=5: Lambda_4 */
   double estimate[21];     /* estimate[i-1] of n_i (k=4, i <= 6) or eta_i (k=5) */
   double variance[21];     /* Theorem 3 / Theorem 10 evaluated at the estimates */
@@ -170,6 +190,14 @@ moss_status moss_table_read(const moss_graph *g, int32_t which, void *host_out, 
  * k = 4: MOSS-4 (Algorithm 1) with K = n_samples >= 1 samples; estimates n_1..n_6 with
  *        n_i = m_i / (K p_i), p_i = 2 phi^(1)_i / Gamma (Theorem 2) for i in {1,3,4,5,6},
  *        n_2 = Lambda_3 - n_4 - 2 n_5 - 4 n_6 (Section 4.1.2) and Theorem 3's variances.
+ *        With MOSS_K4_MIN (n_samples >= 2), MOSS-4 on ceil(n/2) and MOSS-4Min (Algorithm 2)
+ *        on floor(n/2) samples; n_3, n_5, n_6 mix both (Theorem 1).  MOSS-4Min reaches a
+ *        4-cycle by 2 and a 4-clique by 6 ordered draws (Theorem 4), but a diamond by 2,
+ *        4 or 6 depending on its nodes' order, so each MOSS-4Min sample is weighted by
+ *        its own reach count c: n_i = (check-Gamma / K') sum_c m_{i,c} / c, with the
+ *        matching variance (Theorem 5 when c is fixed).  Mix weights: pooled (default)
+ *        K p_i / (K p_i + K' q_i), q = 2, 2, 6 / check-Gamma for i = 3, 5, 6; or the
+ *        paper's inverse-variance weights (MOSS_MIX_PAPER).
  * k = 5: T-5 (Algorithm 3) with K_1 = ceil(n/2) and Path-5 (Algorithm 4) with
  *        K_2 = floor(n/2) samples (n_samples >= 2), mixed per Section 5.1.3 (flags),
  *        eta_2 = Lambda_4 - sum_{Omega_3*} phi^(3)_i eta_i and Theorem 10's variances.
@@ -180,7 +208,8 @@ moss_status moss_estimate(moss_graph *g, int32_t k, uint64_t n_samples, uint64_t
                           uint32_t flags, moss_result *out);
 
 /* Raw hit counts of one sampler (MOSS_SAMPLER_*) over sample indices [k0, k1), accumulated
-   into hits[22] (host; [0] rejected, [i] class i; overwritten).  If d_class_out is not
+   into hits[22] (host; [0] rejected, [i] class i, MOSS-4Min's diamonds also by reach
+   count in [7..9]; overwritten).  If d_class_out is not
    NULL it receives one byte per sample, d_class_out[k - k0] = class of sample k (0 =
    rejected); it must hold k1 - k0 bytes on the device.  Splitting [k0, k1) into pieces
    gives exactly the same total. */
@@ -194,8 +223,8 @@ moss_status moss_sample_nodes(moss_graph *g, int32_t sampler, uint64_t seed, con
                               int64_t count, int32_t *d_nodes_out, uint8_t *d_class_out);
 
 /* The classification table a sampler's kernel uses (host only, no device needed): entry m
-   is the motif id of a sample whose probed pairs are the set bits of m.  MOSS-4 (len 8):
-   bit 0 = u~w, 1 = v~r, 2 = w~r.  T-5 (len 64): u~w, u~r, w~r, v~t, w~t, r~t.  Path-5
+   is the motif id of a sample whose probed pairs are the set bits of m.  MOSS-4 and
+   MOSS-4Min (len 8): bit 0 = u~w, 1 = v~r, 2 = w~r.  T-5 (len 64): u~w, u~r, w~r, v~t, w~t, r~t.  Path-5
    (len 64): v~r, v~t, u~w, u~t, w~r, r~t.  Ids follow the paper's motif numbering, which
    its printed constants fix (Section 4.1.2 for 4 nodes, Table 2 for 5 nodes). */
 moss_status moss_class_lut(int32_t sampler, uint8_t *out, int32_t len);
@@ -212,7 +241,7 @@ moss_status moss_finals(moss_result *out);
 typedef struct {
   moss_graph *g;
   int32_t k;               /* 4 or 5 */
-  uint32_t flags;          /* MOSS_MIX_* */
+  uint32_t flags;          /* MOSS_MIX_*, MOSS_K4_MIN */
   uint64_t n_samples;
   uint64_t seed;
 } moss_request;

@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "batch.h"
 #include "internal.h"
 
 namespace moss {
@@ -90,6 +91,10 @@ SamplerView sampler_view(const moss_graph* g, int sampler) {
   v.edge_bits = g->edge_bits;
   v.filter = g->filter;
   v.filter_bits = g->filter_bits;
+  v.rank = g->rank;
+  v.col_rank = g->col_rank;
+  v.acc_check = g->acc_check;
+  v.check_guide = g->check_guide;
   v.total = g->total[s];
   v.n = g->n;
   v.gbits = g->gbits;
@@ -127,6 +132,28 @@ bool grouped_schedule(const moss_graph* g, uint64_t nsamples) {
   if (sch == MOSS_SCHEDULE_XCD) return true;
   if (sch == MOSS_SCHEDULE_PLAIN) return false;
   return sampling_footprint(g) >= kGroupedMinFootprint && nsamples >= kGroupedMinSamples;
+}
+
+moss_status plan_estimate(int32_t k, uint64_t n_samples, uint32_t flags, EstimatePlan* p) {
+  *p = EstimatePlan{};
+  if (flags & ~(MOSS_MIX_PAPER | MOSS_K4_MIN)) return MOSS_E_ARG;
+  const bool with_min = (flags & MOSS_K4_MIN) != 0;
+  if (k == 4 && !with_min) {
+    if (n_samples < 1) return MOSS_E_ARG;
+    p->count = 1;
+    p->sampler[0] = kMoss4;
+    p->K[0] = n_samples;
+    p->tables = MOSS_TABLES_K4;
+    return MOSS_OK;
+  }
+  if ((k != 4 && k != 5) || (k == 5 && with_min) || n_samples < 2) return MOSS_E_ARG;
+  p->count = 2;
+  p->sampler[0] = k == 4 ? kMoss4 : kT5;
+  p->sampler[1] = k == 4 ? kMoss4Min : kPath5;
+  p->K[0] = (n_samples + 1) / 2;
+  p->K[1] = n_samples / 2;
+  p->tables = k == 4 ? (MOSS_TABLES_K4 | MOSS_TABLES_K4MIN) : MOSS_TABLES_K5;
+  return MOSS_OK;
 }
 
 void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int* grid, int* block) {
@@ -297,6 +324,26 @@ struct NodeLayout {
   size_t acc_tau, tau_guide, acc[2], guide[2], bytes;
 };
 
+// MOSS-4Min: rank pairs, rows in descending order, the row prefix of d_{v,x} d_{x,v}
+// (also the rank passes' key scratch) with its row guides, the node prefix and guide
+struct MinLayout {
+  size_t rank, col_rank, acc_check, check_guide, acc, guide, bytes;
+};
+
+MinLayout min_layout(const moss_graph* g) {
+  const size_t n = (size_t)g->n, nnz = (size_t)g->nnz, G = ((size_t)1 << g->gbits) + 1;
+  MinLayout L;
+  Carve c;
+  L.rank = c.take<uint2>(nnz);
+  L.col_rank = c.take<int32_t>(nnz);
+  L.acc_check = c.take<uint64_t>(nnz);
+  L.check_guide = c.take<uint32_t>((size_t)g->row_guide_len);
+  L.acc = c.take<uint64_t>(n);
+  L.guide = c.take<uint32_t>(G);
+  L.bytes = c.off;
+  return L;
+}
+
 // k5 = false: ACC_Gamma and its guide; true: ACC_tau, its row guides, ACC_Gamma1/2, guides
 NodeLayout node_layout(const moss_graph* g, bool k5) {
   const size_t n = (size_t)g->n, G = ((size_t)1 << g->gbits) + 1;
@@ -376,6 +423,16 @@ void free_tables(moss_graph* g, uint32_t mask) {
     g->guide[1] = g->guide[2] = nullptr;
     g->total[1] = g->total[2] = 0;
   }
+  if (mask & MOSS_TABLES_K4MIN) {
+    dev_free(g->stream, g->mem_min);
+    g->rank = nullptr;
+    g->col_rank = nullptr;
+    g->acc_check = nullptr;
+    g->check_guide = nullptr;
+    g->acc_node[3] = nullptr;
+    g->guide[3] = nullptr;
+    g->total[3] = 0;
+  }
   g->built &= ~mask;
   if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5))) {
     dev_free(g->stream, g->mem_sig);
@@ -389,7 +446,7 @@ void destroy_graph(moss_graph* g) {
   if (!g) return;
   DeviceScope scope(g->device);
   (void)hipStreamSynchronize(g->stream);
-  free_tables(g, MOSS_TABLES_K4 | MOSS_TABLES_K5);
+  free_tables(g, MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN);
   void* csr = g->owned_rp;
   dev_free(g->stream, csr);
   dev_free(g->stream, g->mem_graph);
@@ -604,6 +661,7 @@ moss_status moss_graph_get_info(const moss_graph* g, moss_graph_info* info) {
   r.lambda3 = g->lambda3;
   r.lambda4 = g->lambda4;
   r.device_bytes = g->table_bytes + (g->owned_rp ? g->csr_bytes : 0);
+  r.gamma_min = g->total[3];
   *info = r;
   return MOSS_OK;
 }
@@ -625,7 +683,7 @@ moss_status moss_table_read(const moss_graph* g, int32_t which, void* host_out, 
     }
     case MOSS_TAB_ACC_SIGMA:
       if (count != g->nnz) return MOSS_E_ARG;
-      if (!g->built) return MOSS_E_NOT_BUILT;
+      if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5))) return MOSS_E_NOT_BUILT;
       src = g->acc_sigma;
       bytes = (size_t)g->nnz * sizeof(uint32_t);
       break;
@@ -635,6 +693,20 @@ moss_status moss_table_read(const moss_graph* g, int32_t which, void* host_out, 
       src = g->acc_tau;
       bytes = (size_t)g->nnz * sizeof(uint64_t);
       break;
+    case MOSS_TAB_ACC_GAMMA_MIN:
+    case MOSS_TAB_ACC_CHECK:
+    case MOSS_TAB_RANK:
+    case MOSS_TAB_COL_RANK: {
+      const bool nodes = which == MOSS_TAB_ACC_GAMMA_MIN;
+      if (count != (nodes ? (int64_t)g->n : g->nnz)) return MOSS_E_ARG;
+      if (!(g->built & MOSS_TABLES_K4MIN)) return MOSS_E_NOT_BUILT;
+      src = nodes ? (const void*)g->acc_node[3]
+                  : which == MOSS_TAB_ACC_CHECK ? (const void*)g->acc_check
+                  : which == MOSS_TAB_RANK     ? (const void*)g->rank
+                                               : (const void*)g->col_rank;
+      bytes = (size_t)count * (which == MOSS_TAB_COL_RANK ? sizeof(int32_t) : sizeof(uint64_t));
+      break;
+    }
     default:
       return MOSS_E_ARG;
   }
@@ -648,15 +720,16 @@ moss_status moss_table_read(const moss_graph* g, int32_t which, void* host_out, 
 }  // extern "C"
 
 moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
-  if (k_mask & ~(MOSS_TABLES_K4 | MOSS_TABLES_K5)) return MOSS_E_ARG;
+  if (k_mask & ~(MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN)) return MOSS_E_ARG;
   const uint32_t need = k_mask & ~g->built;
   if (!need) return MOSS_OK;
   DeviceScope scope(g->device);
   if (!scope.ok()) return MOSS_E_DEVICE;
-  const bool want4 = need & MOSS_TABLES_K4, want5 = need & MOSS_TABLES_K5;
-  const bool sig_ready = g->built != 0;  // ACC_sigma and its companions come with the first set
+  const bool want4 = need & MOSS_TABLES_K4, want5 = need & MOSS_TABLES_K5, want_min = need & MOSS_TABLES_K4MIN;
+  // ACC_sigma and its companions come with the first MOSS-4 or 5-node set
+  const bool want_sig = (want4 || want5) && !g->mem_sig;
   moss_status st = MOSS_OK;
-  if (!sig_ready) {
+  if (want_sig) {
     const SigLayout L = sig_layout(g);
     st = dev_alloc_bytes(g->stream, &g->mem_sig, L.bytes);
     if (st == MOSS_OK) {
@@ -684,6 +757,18 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
       }
     }
   }
+  if (st == MOSS_OK && want_min) {
+    const MinLayout L = min_layout(g);
+    st = dev_alloc_bytes(g->stream, &g->mem_min, L.bytes);
+    if (st == MOSS_OK) {
+      g->rank = at<uint2>(g->mem_min, L.rank);
+      g->col_rank = at<int32_t>(g->mem_min, L.col_rank);
+      g->acc_check = at<uint64_t>(g->mem_min, L.acc_check);
+      g->check_guide = at<uint32_t>(g->mem_min, L.check_guide);
+      g->acc_node[3] = at<uint64_t>(g->mem_min, L.acc);
+      g->guide[3] = at<uint32_t>(g->mem_min, L.guide);
+    }
+  }
   if (st != MOSS_OK) {
     (void)hipStreamSynchronize(g->stream);  // the blocks it did get are idle before release
     free_tables(g, need);
@@ -696,7 +781,7 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   f.p[0] = g->small + kWErr;
   f.count[0] = kWLambda + 2;
   f.p[1] = g->small + kWTotal;
-  f.count[1] = 3;
+  f.count[1] = 4;
   hipError_t e = launch_fill_set(f, s);
   RowTables t{};
   t.items = g->items;
@@ -706,16 +791,16 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   t.item_sum = g->item_sum;
   t.rec = g->rec;
   t.n_items = g->n_items;
-  if (e == hipSuccess && !sig_ready) {
+  if (e == hipSuccess && want_sig) {
     t.guide = g->sig_guide;
-    e = launch_row_tables(false, t, err, s);
+    e = launch_row_tables(kRowSigma, t, err, s);
   }
   if (e == hipSuccess && want5) {
     t.acc_tau = g->acc_tau;
     t.guide = g->tau_guide;
-    e = launch_row_tables(true, t, err, s);
+    e = launch_row_tables(kRowTau, t, err, s);
   }
-  if (e == hipSuccess)
+  if (e == hipSuccess && (want4 || want5))
     e = launch_node_weights(g->n, g->rp, g->rec, want5 ? g->acc_tau : nullptr, want4 ? g->acc_node[0] : nullptr,
                             want5 ? g->acc_node[1] : nullptr, want5 ? g->acc_node[2] : nullptr, g->partials,
                             (unsigned long long*)(g->small + kWLambda), err, s);
@@ -734,6 +819,31 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   }
   if (e == hipSuccess) e = launch_scans(scans, g->n, err, s);
   if (e == hipSuccess) e = launch_guides(guides, g->n, g->gbits, s);
+  if (want_min) {
+    // ranks (the row prefix array serves as their key scratch), the prefix of
+    // d_{v,x} d_{x,v} with its row guides, check-Gamma_v, its scan and guide
+    if (e == hipSuccess)
+      e = launch_rank_tables(g->n_items, g->items, g->rp, g->col, g->rec, g->acc_check, g->rank, g->col_rank, s);
+    if (e == hipSuccess) {
+      t.rank = g->rank;
+      t.acc_check = g->acc_check;
+      t.guide = g->check_guide;
+      e = launch_row_tables(kRowCheck, t, err, s);
+    }
+    if (e == hipSuccess) e = launch_row_totals(g->n, g->rp, g->acc_check, g->acc_node[3], s);
+    ScanSet ms{};
+    ms.data[0] = g->acc_node[3];
+    ms.tmp[0] = g->scan_tmp[0];
+    ms.err_bit[0] = kErrOverflowMin;
+    ms.count = 1;
+    GuideSet mg{};
+    mg.acc[0] = g->acc_node[3];
+    mg.guide[0] = g->guide[3];
+    mg.total[0] = g->small + kWTotal + 3;
+    mg.count = 1;
+    if (e == hipSuccess) e = launch_scans(ms, g->n, err, s);
+    if (e == hipSuccess) e = launch_guides(mg, g->n, g->gbits, s);
+  }
   uint64_t* h = g->h_stage;
   if (e == hipSuccess) e = hipMemcpyAsync(h, g->small, kWHits * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   const hipError_t es = hipStreamSynchronize(s);  // also drains work queued before a failed launch
@@ -743,12 +853,13 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     return status_of(e);
   }
   const uint32_t bits = (uint32_t)(h[kWErr] & 0xFFFFFFFFu);
-  if ((bits & kErrOverflow) || (want4 && (bits & kErrOverflowK4)) || (want5 && (bits & kErrOverflowK5))) {
+  if ((want_sig && (bits & kErrOverflow)) || (want4 && (bits & kErrOverflowK4)) ||
+      (want5 && (bits & kErrOverflowK5)) || (want_min && (bits & kErrOverflowMin))) {
     free_tables(g, need);
     return MOSS_E_OVERFLOW;
   }
-  for (int slot = 0; slot < 3; ++slot)
-    if (slot == 0 ? want4 : want5) g->total[slot] = g->n > 0 ? h[kWTotal + slot] : 0;
+  for (int slot = 0; slot < 4; ++slot)
+    if (slot == 0 ? want4 : slot == 3 ? want_min : want5) g->total[slot] = g->n > 0 ? h[kWTotal + slot] : 0;
   if (want4) g->lambda3 = h[kWLambda];
   if (want5) g->lambda4 = h[kWLambda + 1];
   g->built |= need;
@@ -759,17 +870,19 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
 void moss::free_graph_tables(moss_graph* g, uint32_t mask) {
   DeviceScope scope(g->device);
   (void)hipStreamSynchronize(g->stream);
-  free_tables(g, mask & (MOSS_TABLES_K4 | MOSS_TABLES_K5));
+  free_tables(g, mask & (MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN));
 }
 
 // With mask = 0: the bytes held now.  Otherwise the bytes that building `mask` adds.
 uint64_t moss::table_bytes_needed(const moss_graph* g, uint32_t mask) {
   const uint64_t sig = sig_layout(g).bytes, k4 = node_layout(g, false).bytes, k5 = node_layout(g, true).bytes;
   const uint32_t have = g->built, add = mask == 0 ? have : (mask & ~have);
+  const uint32_t sig_sets = MOSS_TABLES_K4 | MOSS_TABLES_K5;  // ACC_sigma comes with either
   uint64_t b = 0;
-  if (add && (mask == 0 || !have)) b += sig;
+  if ((add & sig_sets) && (mask == 0 || !(have & sig_sets))) b += sig;
   if (add & MOSS_TABLES_K4) b += k4;
   if (add & MOSS_TABLES_K5) b += k5;
+  if (add & MOSS_TABLES_K4MIN) b += min_layout(g).bytes;
   return b;
 }
 
@@ -818,7 +931,7 @@ moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0,
   return MOSS_OK;
 }
 
-bool valid_sampler(int s) { return s == kMoss4 || s == kT5 || s == kPath5; }
+bool valid_sampler(int s) { return s == kMoss4 || s == kMoss4Min || s == kT5 || s == kPath5; }
 
 }  // namespace
 
@@ -826,41 +939,18 @@ extern "C" {
 
 moss_status moss_estimate(moss_graph* g, int32_t k, uint64_t n_samples, uint64_t seed, uint32_t flags,
                           moss_result* out) {
-  if (!g || !out || (k != 4 && k != 5) || (flags & ~MOSS_MIX_PAPER)) return MOSS_E_ARG;
-  if ((k == 4 && n_samples < 1) || (k == 5 && n_samples < 2)) return MOSS_E_ARG;
+  EstimatePlan plan;
+  if (!g || !out || plan_estimate(k, n_samples, flags, &plan) != MOSS_OK) return MOSS_E_ARG;
   GraphClaim claim(g);
   if (!claim.ok()) return MOSS_E_BUSY;
   DeviceScope scope(g->device);
   if (!scope.ok()) return MOSS_E_DEVICE;
-  moss_status st = build_tables(g, k == 4 ? MOSS_TABLES_K4 : MOSS_TABLES_K5);
+  moss_status st = build_tables(g, plan.tables);
   if (st != MOSS_OK) return st;
-  moss_result r{};
-  r.k = k;
-  r.flags = flags;
-  r.n_samples = n_samples;
-  int samplers[2];
-  uint64_t k0[2] = {0, 0}, k1[2];
-  int count;
-  if (k == 4) {
-    r.K[0] = n_samples;
-    r.gamma[0] = g->total[0];
-    r.lambda = g->lambda3;
-    samplers[0] = kMoss4;
-    k1[0] = n_samples;
-    count = 1;
-  } else {
-    r.K[0] = (n_samples + 1) / 2;
-    r.K[1] = n_samples / 2;
-    r.gamma[0] = g->total[1];
-    r.gamma[1] = g->total[2];
-    r.lambda = g->lambda4;
-    samplers[0] = kT5;
-    samplers[1] = kPath5;
-    k1[0] = r.K[0];
-    k1[1] = r.K[1];
-    count = 2;
-  }
-  st = run_samplers(g, samplers, k0, k1, count, seed, nullptr, r.hits, &r.device_ms);
+  moss_result r;
+  result_header(g, k, n_samples, flags, &r);
+  const uint64_t k0[2] = {0, 0};
+  st = run_samplers(g, plan.sampler, k0, plan.K, plan.count, seed, nullptr, r.hits, &r.device_ms);
   if (st != MOSS_OK) return st;
   st = moss_finals(&r);
   if (st != MOSS_OK) return st;
@@ -875,7 +965,7 @@ moss_status moss_sample_range(moss_graph* g, int32_t sampler, uint64_t seed, uin
   if (!claim.ok()) return MOSS_E_BUSY;
   DeviceScope scope(g->device);
   if (!scope.ok()) return MOSS_E_DEVICE;
-  moss_status st = build_tables(g, sampler == kMoss4 ? MOSS_TABLES_K4 : MOSS_TABLES_K5);
+  moss_status st = build_tables(g, sampler_tables(sampler));
   if (st != MOSS_OK) return st;
   uint64_t h[2][22];
   const int samplers[1] = {sampler};
@@ -897,7 +987,7 @@ moss_status moss_sample_nodes(moss_graph* g, int32_t sampler, uint64_t seed, con
   if (!claim.ok()) return MOSS_E_BUSY;
   DeviceScope scope(g->device);
   if (!scope.ok()) return MOSS_E_DEVICE;
-  moss_status st = build_tables(g, sampler == kMoss4 ? MOSS_TABLES_K4 : MOSS_TABLES_K5);
+  moss_status st = build_tables(g, sampler_tables(sampler));
   if (st != MOSS_OK) return st;
   if (g->total[sampler_slot(sampler)] == 0) return count == 0 ? MOSS_OK : MOSS_E_ARG;  // nothing can be drawn
   hipError_t e = launch_sample_nodes(sampler, sampler_view(g, sampler), seed, d_index, count, d_nodes_out,

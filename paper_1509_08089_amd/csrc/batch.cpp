@@ -41,15 +41,17 @@ void result_header(const moss_graph* g, int32_t k, uint64_t n_samples, uint32_t 
   r->k = k;
   r->flags = flags;
   r->n_samples = n_samples;
+  EstimatePlan plan;
+  (void)plan_estimate(k, n_samples, flags, &plan);  // callers checked the request
+  r->K[0] = plan.K[0];
+  r->K[1] = plan.K[1];
   if (k == 4) {
     r->n_motifs = 6;
-    r->K[0] = n_samples;
     r->gamma[0] = g->total[0];
+    r->gamma[1] = plan.count == 2 ? g->total[3] : 0;
     r->lambda = g->lambda3;
   } else {
     r->n_motifs = 21;
-    r->K[0] = (n_samples + 1) / 2;
-    r->K[1] = n_samples / 2;
     r->gamma[0] = g->total[1];
     r->gamma[1] = g->total[2];
     r->lambda = g->lambda4;
@@ -227,7 +229,7 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     } else {
       vi = it->second;
     }
-    const uint64_t weight = w.sampler == kMoss4 ? 2 : 3;
+    const uint64_t weight = (w.sampler == kMoss4 || w.sampler == kMoss4Min) ? 2 : 3;
     for (uint64_t a = w.k0; a < w.k1; a += T) {
       const uint64_t b = std::min<uint64_t>(w.k1, a + T);
       Tile t{};
@@ -302,13 +304,16 @@ moss_status batch_impl(const moss_request* reqs, int32_t n, moss_result* out, hi
   const int device = reqs[0].g ? reqs[0].g->device : -1;
   for (int32_t i = 0; i < n; ++i) {
     const moss_request& q = reqs[i];
-    if (!q.g || q.g->device != device || (q.k != 4 && q.k != 5) || (q.flags & ~MOSS_MIX_PAPER)) return MOSS_E_ARG;
-    if ((q.k == 4 && q.n_samples < 1) || (q.k == 5 && q.n_samples < 2)) return MOSS_E_ARG;
+    EstimatePlan plan;
+    if (!q.g || q.g->device != device || plan_estimate(q.k, q.n_samples, q.flags, &plan) != MOSS_OK)
+      return MOSS_E_ARG;
   }
   // build missing tables (each graph once)
   for (int32_t i = 0; i < n; ++i) {
     moss_graph* g = reqs[i].g;
-    const uint32_t mask = reqs[i].k == 4 ? MOSS_TABLES_K4 : MOSS_TABLES_K5;
+    EstimatePlan plan;
+    (void)plan_estimate(reqs[i].k, reqs[i].n_samples, reqs[i].flags, &plan);
+    const uint32_t mask = plan.tables;
     if ((g->built & mask) == mask) continue;
     GraphClaim claim(g);
     if (!claim.ok()) return MOSS_E_BUSY;
@@ -321,12 +326,10 @@ moss_status batch_impl(const moss_request* reqs, int32_t n, moss_result* out, hi
     const moss_request& q = reqs[i];
     moss_result& r = out[i];
     result_header(q.g, q.k, q.n_samples, q.flags, &r);
-    if (q.k == 4) {
-      work.push_back({q.g, kMoss4, q.seed, 0, r.K[0], (uint32_t)(2 * i)});
-    } else {
-      work.push_back({q.g, kT5, q.seed, 0, r.K[0], (uint32_t)(2 * i)});
-      work.push_back({q.g, kPath5, q.seed, 0, r.K[1], (uint32_t)(2 * i + 1)});
-    }
+    EstimatePlan plan;
+    (void)plan_estimate(q.k, q.n_samples, q.flags, &plan);
+    for (int s = 0; s < plan.count; ++s)
+      work.push_back({q.g, plan.sampler[s], q.seed, 0, plan.K[s], (uint32_t)(2 * i + s)});
   }
   std::vector<uint64_t> bins((size_t)n * 2 * 22);
   std::lock_guard<std::mutex> lk(g_batch_mu);

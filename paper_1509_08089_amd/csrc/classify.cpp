@@ -105,7 +105,7 @@ extern "C" moss_status moss_class_lut(int32_t sampler, uint8_t* out, int32_t len
   } catch (...) {
     return MOSS_E_ARG;
   }
-  if (sampler == MOSS_SAMPLER_MOSS4 && len == 8) std::memcpy(out, l4, 8);
+  if ((sampler == MOSS_SAMPLER_MOSS4 || sampler == MOSS_SAMPLER_MOSS4MIN) && len == 8) std::memcpy(out, l4, 8);
   else if (sampler == MOSS_SAMPLER_T5 && len == 64) std::memcpy(out, lt, 64);
   else if (sampler == MOSS_SAMPLER_PATH5 && len == 64) std::memcpy(out, lp, 64);
   else return MOSS_E_ARG;

@@ -14,6 +14,21 @@
 //   Cov(eta_i, eta_j) = -eta_i eta_j sum_l lambda^(l)_i lambda^(l)_j / K_l (i != j)
 //   eta_2 = Lambda_4 - sum_{i in Omega_3*} phi^(3)_i eta_i,
 //   Var(eta_2) = sum_{i,j in Omega_3*} phi^(3)_i phi^(3)_j Cov(eta_i, eta_j)
+// MOSS-4 with MOSS-4Min (k = 4, MOSS_K4_MIN; Section 4.2, Theorems 1, 4, 5):
+//   MOSS-4Min draws each ordered (w, v, u, r) with w above u and r above v with
+//   probability 1/check-Gamma, so a CIS s is drawn with probability c(s)/check-Gamma
+//   (c = 2 for the 4-cycle, 6 for the 4-clique, 2, 4 or 6 for a diamond, counted per
+//   sample in hits[1][7..9]).  Per-sample weights give
+//     n'_i = (check-Gamma / K') sum_c m_{i,c} / c,  Var = (A_i - n_i^2) / K',
+//     A_i = sum_{s in C_i} check-Gamma / c(s), for the diamond estimated by
+//     (check-Gamma^2 / K') sum_c m_{5,c} / c^2, for the others n_i / q_i,
+//   q_3 = 2 / check-Gamma, q_5 = 2 / check-Gamma (fixed weight only), q_6 = 6 / check-Gamma.
+//   n_3, n_5, n_6 mix MOSS-4 and MOSS-4Min with lambda_i = K p_i / (K p_i + K' q_i)
+//   (pooled; variances at the mixed value) or V'_i / (V_i + V'_i) (paper, variances
+//   at the pooled value); n_1, n_4 are MOSS-4's; n_2 = Lambda_3 - n_4 - 2 n_5 - 4 n_6
+//   with Var = MOSS-4's share (n_4/p_4 + 4 l5^2 n_5/p_5 + 16 l6^2 n_6/p_6
+//   - (n_4 + 2 l5 n_5 + 4 l6 n_6)^2) / K plus MOSS-4Min's share (4 (1-l5)^2 A_5
+//   + 16 (1-l6)^2 A_6 - (2 (1-l5) n_5 + 4 (1-l6) n_6)^2) / K', each at least 0.
 // The unknown counts inside the variance formulas are replaced by the estimates;
 // reported variances are clamped at zero.
 #include <cmath>
@@ -50,6 +65,70 @@ void finals4(moss_result* r) {
     const double s = n[4] + 2.0 * n[5] + 4.0 * n[6];
     r->variance[1] = nonneg((n[4] / p[4] + 4.0 * n[5] / p[5] + 16.0 * n[6] / p[6] - s * s) / K);
   }
+}
+
+void finals4_min(moss_result* r) {
+  const double K = (double)r->K[0], Kc = (double)r->K[1];
+  const uint64_t G = r->gamma[0], Gc = r->gamma[1];
+  const uint64_t* h = r->hits[0];
+  const uint64_t* hm = r->hits[1];
+  double p[7] = {}, q[7] = {}, a4[7] = {}, amin[7] = {}, lam[7] = {1, 1, 1, 1, 1, 1, 1};
+  if (G != 0)
+    for (int i = 1; i <= 6; ++i)
+      if (kPhi4[i] != 0) {
+        p[i] = 2.0 * kPhi4[i] / (double)G;
+        a4[i] = (double)h[i] / (K * p[i]);
+      }
+  double A5 = 0.0;
+  if (Gc != 0) {
+    const double gc = (double)Gc;
+    q[3] = 2.0 / gc;
+    q[5] = 2.0 / gc;
+    q[6] = 6.0 / gc;
+    amin[3] = (double)hm[3] * gc / (2.0 * Kc);
+    amin[6] = (double)hm[6] * gc / (6.0 * Kc);
+    amin[5] = gc / Kc * ((double)hm[7] / 2.0 + (double)hm[8] / 4.0 + (double)hm[9] / 6.0);
+    A5 = gc * gc / Kc * ((double)hm[7] / 4.0 + (double)hm[8] / 16.0 + (double)hm[9] / 36.0);
+  }
+  double n[7] = {};
+  for (int i : {1, 4}) {
+    if (p[i] == 0.0) continue;
+    n[i] = a4[i];
+    r->variance[i - 1] = nonneg(n[i] / K * (1.0 / p[i] - n[i]));
+  }
+  for (int i : {3, 5, 6}) {
+    const double w4 = K * p[i], wmin = Kc * q[i];
+    if (w4 + wmin == 0.0) continue;
+    double l = w4 / (w4 + wmin);
+    double est = l * a4[i] + (1.0 - l) * amin[i];
+    const double v1 = p[i] > 0.0 ? nonneg(est / K * (1.0 / p[i] - est)) : 0.0;
+    const double Ai = i == 5 ? A5 : (q[i] > 0.0 ? est / q[i] : 0.0);
+    const double v2 = q[i] > 0.0 ? nonneg((Ai - est * est) / Kc) : 0.0;
+    double var;
+    if ((r->flags & MOSS_MIX_PAPER) && p[i] > 0.0 && q[i] > 0.0 && v1 + v2 > 0.0) {
+      l = v2 / (v1 + v2);
+      est = l * a4[i] + (1.0 - l) * amin[i];
+      var = v1 * v2 / (v1 + v2);
+    } else {
+      var = l * l * v1 + (1.0 - l) * (1.0 - l) * v2;
+    }
+    lam[i] = l;
+    n[i] = est;
+    r->variance[i - 1] = nonneg(var);
+  }
+  for (int i = 1; i <= 6; ++i) r->estimate[i - 1] = n[i];
+  r->estimate[1] = (double)r->lambda - n[4] - 2.0 * n[5] - 4.0 * n[6];
+  double v4 = 0.0, vmin = 0.0;
+  if (p[4] > 0.0) {
+    const double s = n[4] + 2.0 * lam[5] * n[5] + 4.0 * lam[6] * n[6];
+    v4 = nonneg((n[4] / p[4] + 4.0 * lam[5] * lam[5] * n[5] / p[5] + 16.0 * lam[6] * lam[6] * n[6] / p[6] - s * s) / K);
+  }
+  if (q[6] > 0.0) {
+    const double m5 = 1.0 - lam[5], m6 = 1.0 - lam[6];
+    const double t = 2.0 * m5 * n[5] + 4.0 * m6 * n[6];
+    vmin = nonneg((4.0 * m5 * m5 * A5 + 16.0 * m6 * m6 * (n[6] / q[6]) - t * t) / Kc);
+  }
+  r->variance[1] = v4 + vmin;
 }
 
 void finals5(moss_result* r) {
@@ -105,14 +184,20 @@ extern "C" moss_status moss_finals(moss_result* r) {
   if (!r) return MOSS_E_ARG;
   std::memset(r->estimate, 0, sizeof(r->estimate));
   std::memset(r->variance, 0, sizeof(r->variance));
+  if (r->flags & ~(MOSS_MIX_PAPER | MOSS_K4_MIN)) return MOSS_E_ARG;
   if (r->k == 4) {
     if (r->K[0] == 0) return MOSS_E_ARG;
     r->n_motifs = 6;
-    finals4(r);
+    if (r->flags & MOSS_K4_MIN) {
+      if (r->K[1] == 0) return MOSS_E_ARG;
+      finals4_min(r);
+    } else {
+      finals4(r);
+    }
     return MOSS_OK;
   }
   if (r->k == 5) {
-    if (r->K[0] == 0 || r->K[1] == 0) return MOSS_E_ARG;
+    if (r->K[0] == 0 || r->K[1] == 0 || (r->flags & MOSS_K4_MIN)) return MOSS_E_ARG;
     r->n_motifs = 21;
     finals5(r);
     return MOSS_OK;

@@ -20,13 +20,15 @@ struct moss_graph {
   int32_t* owned_col = nullptr;
   uint32_t flags = 0;
 
-  // Device memory comes in four stream-ordered blocks: per graph (word block, work
-  // items, node records, scan scratch), and per table set (ACC_sigma with its row
-  // guides, the edge hash set and filter; the MOSS-4 node table; the 5-node tables).
+  // Device memory comes in stream-ordered blocks: per graph (word block, edge hash set
+  // and filter, work items, node records, scan scratch), and per table set (ACC_sigma
+  // with its row guides; the MOSS-4 node table; the 5-node tables; the MOSS-4Min
+  // tables).
   void* mem_graph = nullptr;
   void* mem_sig = nullptr;
   void* mem_k4 = nullptr;
   void* mem_k5 = nullptr;
+  void* mem_min = nullptr;
 
   // per graph (mem_graph)
   uint64_t* small = nullptr;             // kWords words shared with the kernels
@@ -48,10 +50,15 @@ struct moss_graph {
   int filter_bits = 1;
   uint64_t* acc_tau = nullptr;      // nnz
   uint32_t* tau_guide = nullptr;    // row guides over ACC_tau
-  uint64_t* acc_node[3] = {};       // n each: Gamma (MOSS-4), Gamma^(1) (T-5), Gamma^(2) (Path-5)
-  uint32_t* guide[3] = {};          // 2^gbits + 1 each
+  uint2* rank = nullptr;            // nnz: {d_{v,x}, d_{x,v}} (MOSS-4Min)
+  int32_t* col_rank = nullptr;      // nnz: rows in descending order (MOSS-4Min)
+  uint64_t* acc_check = nullptr;    // nnz: row prefix of d_{v,x} d_{x,v} (MOSS-4Min)
+  uint32_t* check_guide = nullptr;  // row guides over acc_check
+  // n each: Gamma (MOSS-4), Gamma^(1) (T-5), Gamma^(2) (Path-5), check-Gamma (MOSS-4Min)
+  uint64_t* acc_node[4] = {};
+  uint32_t* guide[4] = {};          // 2^gbits + 1 each
   int gbits = 1;
-  uint64_t total[3] = {};
+  uint64_t total[4] = {};
   uint64_t lambda3 = 0, lambda4 = 0;
   uint32_t built = 0;               // MOSS_TABLES_* bits
 
@@ -66,7 +73,26 @@ struct moss_graph {
 namespace moss {
 
 // index of a sampler's node distribution / tables
-inline int sampler_slot(int sampler) { return sampler == kMoss4 ? 0 : sampler == kT5 ? 1 : 2; }
+inline int sampler_slot(int sampler) {
+  return sampler == kMoss4 ? 0 : sampler == kT5 ? 1 : sampler == kPath5 ? 2 : 3;
+}
+
+// the table sets a sampler reads
+inline uint32_t sampler_tables(int sampler) {
+  return sampler == kMoss4 ? MOSS_TABLES_K4 : sampler == kMoss4Min ? MOSS_TABLES_K4MIN : MOSS_TABLES_K5;
+}
+
+// The samplers of one estimate: MOSS-4 alone, MOSS-4 with MOSS-4Min (k = 4 and
+// MOSS_K4_MIN) or T-5 with Path-5 (k = 5); two samplers split the budget as
+// ceil(n/2), floor(n/2).
+struct EstimatePlan {
+  int count = 0;
+  int sampler[2] = {0, 0};
+  uint64_t K[2] = {0, 0};
+  uint32_t tables = 0;
+};
+// MOSS_E_ARG for a bad k, flag or budget.
+moss_status plan_estimate(int32_t k, uint64_t n_samples, uint32_t flags, EstimatePlan* p);
 
 moss_status status_of(hipError_t e);
 

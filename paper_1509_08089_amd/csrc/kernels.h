@@ -7,6 +7,7 @@ namespace moss {
 
 // Sampler ids double as Philox key tags.
 constexpr int kMoss4 = 0x4;
+constexpr int kMoss4Min = 0x41;
 constexpr int kT5 = 0x51;
 constexpr int kPath5 = 0x52;
 
@@ -19,6 +20,7 @@ constexpr uint32_t kErrAsymmetric = 1u << 4;
 constexpr uint32_t kErrOverflow = 1u << 5;    // a row sum S_v needs more than 32 bits (all tables)
 constexpr uint32_t kErrOverflowK4 = 1u << 6;  // Gamma prefix or Lambda_3 exceeds 64 bits
 constexpr uint32_t kErrOverflowK5 = 1u << 7;  // a Gamma^(1)/Gamma^(2) value or prefix, or Lambda_4
+constexpr uint32_t kErrOverflowMin = 1u << 8; // a row or node prefix of the MOSS-4Min weights exceeds 64 bits
 
 // What one sampler needs of one graph.
 struct SamplerView {
@@ -33,6 +35,10 @@ struct SamplerView {
   const uint32_t* tau_guide;  // row guides over ACC_tau (Path-5)
   const uint64_t* edge_slots; // edge hash set: 2^edge_bits slots, key min << 32 | max
   const uint64_t* filter;     // edge filter: 2^filter_bits words of 64 bits
+  const uint2* rank;          // MOSS-4Min, per entry (v, x): {d_{v,x}, d_{x,v}}
+  const int32_t* col_rank;    // MOSS-4Min: each row in descending order (N_{v,x} = its first d_{v,x})
+  const uint64_t* acc_check;  // MOSS-4Min: row-local inclusive prefix of d_{v,x} d_{x,v}
+  const uint32_t* check_guide;  // row guides over acc_check
   uint64_t total;             // sum of the node weights
   int32_t n;
   int32_t gbits;
@@ -48,7 +54,7 @@ constexpr int kWItems = 4;     // number of work items
 constexpr int kWGuideLen = 5;  // entries of one row-guide array
 constexpr int kWUpper = 6;     // CSR entries (v, c) with c > v
 constexpr int kWMaxDeg = 7;    // largest degree
-constexpr int kWTotal = 8;     // totals of the Gamma, Gamma^(1), Gamma^(2) node weights
+constexpr int kWTotal = 8;     // totals of the Gamma, Gamma^(1), Gamma^(2), check-Gamma node weights
 constexpr int kWHits = 16;     // 2 x 22 hit counters of a plain estimate
 constexpr int kWords = 64;
 
@@ -116,20 +122,32 @@ hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, con
                               bool full, const uint64_t* slots, int hash_bits, uint64_t* small, hipStream_t s);
 
 // ---- table build ----
-// Row prefixes ACC_sigma (tau = false) or ACC_tau (tau = true, after ACC_sigma), their
-// row guides, and with ACC_sigma the node records' S_v.  item_sum holds n_items u64.
+// Row prefixes with their row guides: ACC_sigma (kRowSigma; also the node records'
+// S_v), ACC_tau (kRowTau, after ACC_sigma) or the MOSS-4Min prefix of d_{v,x} d_{x,v}
+// (kRowCheck, after the rank tables).  item_sum holds n_items u64.
+enum RowMode { kRowSigma = 0, kRowTau = 1, kRowCheck = 2 };
 struct RowTables {
   const uint64_t* items;
   const int32_t* rp;
   const int32_t* col;
   uint32_t* acc_sigma;
   uint64_t* acc_tau;
+  const uint2* rank;
+  uint64_t* acc_check;
   uint64_t* item_sum;
   uint4* rec;
   uint32_t* guide;
   int64_t n_items;
 };
-hipError_t launch_row_tables(bool tau, const RowTables& t, uint32_t* err, hipStream_t s);
+hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStream_t s);
+
+// MOSS-4Min rank tables (Section 4.2.1, order of Section 3.2): for every entry (v, x),
+// rank[e] = {d_{v,x}, d_{x,v}}, and col_rank holds each row in descending order.
+// `keys` (nnz u64) is scratch: each piece's keys, sorted.  Needs the node records.
+hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
+                              const uint4* rec, uint64_t* keys, uint2* rank, int32_t* col_rank, hipStream_t s);
+// w[v] = the last entry of v's row prefix `acc` (0 for an empty row).
+hipError_t launch_row_totals(int32_t n, const int32_t* rp, const uint64_t* acc, uint64_t* w, hipStream_t s);
 
 // Edge hash set size (2^bits u64 slots for m edges, load factor <= 0.4) and edge
 // filter size (2^bits 64-bit words, bits >= 1).
@@ -153,7 +171,8 @@ struct GuideSet {
 };
 hipError_t launch_guides(const GuideSet& set, int32_t n, int gbits, hipStream_t s);
 
-// Plain sampling launch: samples [k0, k1) of one sampler, hits[22] accumulated.
+// Plain sampling launch: samples [k0, k1) of one sampler, hits[22] accumulated.  For
+// MOSS-4Min hits[7..9] also count the diamonds reached by 2, 4 and 6 ordered draws.
 hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
                          unsigned long long* hits, uint8_t* class_out, int grid, int block, hipStream_t s);
 

@@ -208,6 +208,11 @@ static int item_grid(int64_t n_items) {
   return (int)g;
 }
 
+// row start and degree of a node (the first half of its record)
+__device__ __forceinline__ uint2 row_of(const uint4* __restrict__ rec, int32_t x) {
+  return *reinterpret_cast<const uint2*>(rec + x);
+}
+
 struct ItemRange {
   int32_t v, r0, r1, e0, e1, piece;
 };
@@ -377,13 +382,15 @@ hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, con
 
 // ---------------------------------------------------------------------------------
 // Row prefixes (Section 4.1.3 ACC_sigma = ACC_mu of Section 5.1.5; the tau prefix of
-// Section 5.1.2), in two steps per table:
+// Section 5.1.2; MOSS-4Min's prefix of d_{v,x} d_{x,v}, Section 4.2.1), in two steps
+// per table:
 //   local   each item scans its own entries and writes its total to item_sum
 //   finish  each item adds the totals of its row's earlier pieces (at most a few
 //           hundred, summed by the wave), then writes its share of the row guide;
 //           the ACC_sigma pass also records S_v
 // ACC_sigma entries are (d_x - 1) of the neighbours; ACC_tau entries are
-// (d_x - 1)(S_v - (d_x - 1)) with S_v the row total of ACC_sigma.
+// (d_x - 1)(S_v - (d_x - 1)) with S_v the row total of ACC_sigma; the MOSS-4Min
+// entries are d_{v,x} d_{x,v} from the rank tables.
 // ---------------------------------------------------------------------------------
 // Entry e of a row answers the guide buckets whose lower bound b * 2^sh lies in
 // [lo, hi) (lo, hi: the finished prefix before and through e); the row's last entry
@@ -396,17 +403,28 @@ __device__ __forceinline__ void guide_entries(uint32_t* gd, int g, int sh, uint6
   for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - r0);
 }
 
+// the u64 prefix a mode writes (ACC_sigma is u32)
+template <int M>
+__device__ __forceinline__ uint64_t* row_out64(const RowTables& t) {
+  return M == kRowTau ? t.acc_tau : t.acc_check;
+}
+
+template <int M>
+__device__ __forceinline__ uint32_t row_overflow_bit() {
+  return M == kRowSigma ? kErrOverflow : (M == kRowTau ? kErrOverflowK5 : kErrOverflowMin);
+}
+
 // Local prefix of every piece.  A row of one piece (d <= 256) is finished here: its
 // prefix is final, and its guide and (sigma) S_v are written from the values the wave
 // just computed; k_row_finish then only handles rows of several pieces.
-template <bool TAU>
+template <int M>
 __global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   bool wrapped = false, over = false;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
     const ItemRange it = item_range(t.items, t.rp, i);
-    const uint64_t S = TAU ? (uint64_t)t.rec[it.v].z : 0ull;
+    const uint64_t S = M == kRowTau ? (uint64_t)t.rec[it.v].z : 0ull;
     const bool single = it.e0 == it.r0 && it.e1 == it.r1;
     uint64_t carry = 0;
     uint64_t keep[kItem / 64];  // this lane's prefix values (single-piece rows)
@@ -417,9 +435,12 @@ __global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err
       if (it.e0 + c * 64 >= it.e1) continue;  // wave-uniform
       uint64_t x = 0;
       if (e < it.e1) {
-        if (TAU) {  // the sigma entry d_x - 1, from the finished ACC_sigma
+        if (M == kRowTau) {  // the sigma entry d_x - 1, from the finished ACC_sigma
           const uint64_t dx = (uint64_t)t.acc_sigma[e] - (e > it.r0 ? (uint64_t)t.acc_sigma[e - 1] : 0ull);
           x = dx * (S - dx);
+        } else if (M == kRowCheck) {
+          const uint2 rk = t.rank[e];
+          x = (uint64_t)rk.x * (uint64_t)rk.y;
         } else {
           const int32_t c2 = t.col[e];
           x = (uint64_t)(t.rp[c2 + 1] - t.rp[c2] - 1);
@@ -427,8 +448,8 @@ __global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err
       }
       const uint64_t sv = add_wrap(wave_inclusive_scan(x, wrapped), carry, wrapped);
       if (e < it.e1) {
-        if (TAU) t.acc_tau[e] = sv;
-        else t.acc_sigma[e] = (uint32_t)sv;
+        if (M == kRowSigma) t.acc_sigma[e] = (uint32_t)sv;
+        else row_out64<M>(t)[e] = sv;
       }
       keep[c] = sv;
       carry = __shfl(sv, 63, 64);
@@ -436,7 +457,7 @@ __global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err
     if (lane == 0) t.item_sum[i] = carry;
     if (!single) continue;
     const uint64_t total = carry;
-    if (!TAU && total > 0xFFFFFFFFull) over = true;
+    if (M == kRowSigma && total > 0xFFFFFFFFull) over = true;
     const int32_t d = it.r1 - it.r0;
     if (d >= kRowGuideMin) {
       const int g = row_guide_bits(d);
@@ -453,18 +474,18 @@ __global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err
         if (e < it.e1) guide_entries(gd, g, sh, lo, keep[c], e, it.r0, it.r1);
       }
     }
-    if (!TAU && lane == 0) t.rec[it.v].z = (uint32_t)total;
+    if (M == kRowSigma && lane == 0) t.rec[it.v].z = (uint32_t)total;
   }
-  // a wrap inside a tau row is a Gamma^(2)_v beyond 64 bits; a sigma row total beyond
-  // 32 bits does not fit ACC_sigma
-  if (TAU && __ballot(wrapped) != 0 && lane == 0) atomicOr(err, kErrOverflowK5);
-  if (!TAU && __ballot(over) != 0 && lane == 0) atomicOr(err, kErrOverflow);
+  // a wrap inside a tau row is a Gamma^(2)_v beyond 64 bits, inside a MOSS-4Min row a
+  // check-Gamma_v beyond 64 bits; a sigma row total beyond 32 bits does not fit ACC_sigma
+  if (M != kRowSigma && __ballot(wrapped) != 0 && lane == 0) atomicOr(err, row_overflow_bit<M>());
+  if (M == kRowSigma && __ballot(over) != 0 && lane == 0) atomicOr(err, kErrOverflow);
 }
 
 // Rows of several pieces: each piece adds the totals of its row's earlier pieces (at
 // most a few hundred, summed by the wave), then writes its share of the row guide;
 // the last piece records S_v (sigma).
-template <bool TAU>
+template <int M>
 __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -484,7 +505,7 @@ __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) 
     }
     before = wave_sum_wrap(before, wrapped);
     const uint64_t total = add_wrap(before, wave_sum_wrap(rest, wrapped), wrapped);
-    over |= TAU ? wrapped : total > 0xFFFFFFFFull;
+    over |= M != kRowSigma ? wrapped : total > 0xFFFFFFFFull;
     const bool guided = d >= kRowGuideMin;
     const int g = guided ? row_guide_bits(d) : 0;
     const int sh = guided ? row_guide_shift(total, g) : 0;
@@ -495,12 +516,13 @@ __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) 
       const bool in = e < it.e1;
       uint64_t hi = carry;
       if (in) {
-        if (TAU) {
-          hi = t.acc_tau[e] + before;
-          if (before) t.acc_tau[e] = hi;
-        } else {
+        if (M == kRowSigma) {
           hi = (uint64_t)t.acc_sigma[e] + before;
           if (before) t.acc_sigma[e] = (uint32_t)hi;
+        } else {
+          uint64_t* out = row_out64<M>(t);
+          hi = out[e] + before;
+          if (before) out[e] = hi;
         }
       }
       uint64_t lo = __shfl_up(hi, 1, 64);
@@ -508,20 +530,171 @@ __global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) 
       carry = __shfl(hi, 63, 64);
       if (in && guided) guide_entries(gd, g, sh, lo, hi, e, it.r0, it.r1);
     }
-    if (!TAU && it.e1 == it.r1 && lane == 0) t.rec[it.v].z = (uint32_t)total;
+    if (M == kRowSigma && it.e1 == it.r1 && lane == 0) t.rec[it.v].z = (uint32_t)total;
   }
-  if (__ballot(over) != 0 && lane == 0) atomicOr(err, TAU ? kErrOverflowK5 : kErrOverflow);
+  if (__ballot(over) != 0 && lane == 0) atomicOr(err, row_overflow_bit<M>());
 }
 
-hipError_t launch_row_tables(bool tau, const RowTables& t, uint32_t* err, hipStream_t s) {
-  if (t.n_items <= 0) return hipSuccess;
+template <int M>
+static hipError_t row_tables_mode(const RowTables& t, uint32_t* err, hipStream_t s) {
   const dim3 grid(item_grid(t.n_items)), block(256);
-  if (tau) hipLaunchKernelGGL(k_prefix_local<true>, grid, block, 0, s, t, err);
-  else hipLaunchKernelGGL(k_prefix_local<false>, grid, block, 0, s, t, err);
+  hipLaunchKernelGGL(k_prefix_local<M>, grid, block, 0, s, t, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (tau) hipLaunchKernelGGL(k_row_finish<true>, grid, block, 0, s, t, err);
-  else hipLaunchKernelGGL(k_row_finish<false>, grid, block, 0, s, t, err);
+  hipLaunchKernelGGL(k_row_finish<M>, grid, block, 0, s, t, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStream_t s) {
+  if (t.n_items <= 0) return hipSuccess;
+  switch (mode) {
+    case kRowSigma: return row_tables_mode<kRowSigma>(t, err, s);
+    case kRowTau: return row_tables_mode<kRowTau>(t, err, s);
+    case kRowCheck: return row_tables_mode<kRowCheck>(t, err, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// MOSS-4Min rank tables (Section 4.2.1).  The order of Section 3.2's example ranks a
+// node by degree, then id: with key(x) = d_x * 2^32 + x, x is above y exactly when
+// key(x) > key(y).  d_{v,x} = |{y in N_v : y above x}| is then x's place in row v
+// sorted by key, largest first, and col_rank lists the row in that order, so that
+// N_{v,x} is its first d_{v,x} entries.  Three passes over the work items:
+//   local   each piece ranks its entries among themselves: every lane compares its keys
+//           with each key of the piece, broadcast from the lane that holds it.  A row
+//           of one piece is finished here; a longer row's piece writes its keys in
+//           descending order (scratch) and its local ranks
+//   merge   each entry of a longer row adds the keys above it in the row's other
+//           pieces (a binary search of each piece's sorted keys)
+//   mirror  d_{x,v} is read at the entry (x, v), found by a binary search of row x
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t order_key(const uint4* __restrict__ rec, int32_t x) {
+  return ((uint64_t)row_of(rec, x).y << 32) | (uint64_t)(uint32_t)x;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(256) void k_rank_local(int64_t n_items, const uint64_t* __restrict__ items,
+                                                    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                    const uint4* __restrict__ rec, uint64_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
+  const int lane = lane_id();
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    const int32_t len = it.e1 - it.e0;  // 1 .. kItem
+    const bool single = it.e0 == it.r0 && it.e1 == it.r1;
+    uint64_t k[kItem / 64];
+    int32_t x[kItem / 64];
+    uint32_t above[kItem / 64];
+#pragma unroll
+    for (int c = 0; c < kItem / 64; ++c) {
+      const int32_t e = it.e0 + c * 64 + lane;
+      x[c] = e < it.e1 ? col[e] : 0;
+      k[c] = e < it.e1 ? order_key(rec, x[c]) : 0ull;
+      above[c] = 0;
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < kItem / 64; ++c2) {
+      if (c2 * 64 >= len) break;  // wave-uniform
+      const int lim = min(64, len - c2 * 64);
+      for (int j = 0; j < lim; ++j) {
+        const uint64_t kj = readlane64(k[c2], j);
+#pragma unroll
+        for (int c = 0; c < kItem / 64; ++c) above[c] += kj > k[c] ? 1u : 0u;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kItem / 64; ++c) {
+      const int32_t e = it.e0 + c * 64 + lane;
+      if (e >= it.e1) continue;
+      rank32[2 * (int64_t)e] = above[c];
+      if (single) col_rank[it.r0 + (int32_t)above[c]] = x[c];
+      else keys[it.e0 + (int32_t)above[c]] = k[c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rank_merge(int64_t n_items, const uint64_t* __restrict__ items,
+                                                    const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                    const uint4* __restrict__ rec, const uint64_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
+  const int lane = lane_id();
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    if (it.e0 == it.r0 && it.e1 == it.r1) continue;  // finished by k_rank_local
+    const int32_t pieces = (it.r1 - it.r0 + kItem - 1) / kItem;
+    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
+      const int32_t x = col[e];
+      const uint64_t key = order_key(rec, x);
+      uint32_t r = rank32[2 * (int64_t)e];
+      for (int32_t p = 0; p < pieces; ++p) {
+        if (p == it.piece) continue;
+        const int32_t q0 = it.r0 + p * kItem, q1 = min(it.r1, q0 + kItem);
+        int32_t lo = q0, hi = q1;  // first place whose key is not above `key`
+        while (lo < hi) {
+          const int32_t mid = lo + ((hi - lo) >> 1);
+          if (keys[mid] > key) lo = mid + 1;
+          else hi = mid;
+        }
+        r += (uint32_t)(lo - q0);
+      }
+      rank32[2 * (int64_t)e] = r;
+      col_rank[it.r0 + (int32_t)r] = x;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rank_mirror(int64_t n_items, const uint64_t* __restrict__ items,
+                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                     const uint4* __restrict__ rec, uint32_t* __restrict__ rank32) {
+  const int lane = lane_id();
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+    const ItemRange it = item_range(items, rp, i);
+    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
+      const uint2 X = row_of(rec, col[e]);
+      int32_t lo = (int32_t)X.x, hi = (int32_t)(X.x + X.y);
+      while (lo < hi) {  // first entry of row x not below v
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (col[mid] < it.v) lo = mid + 1;
+        else hi = mid;
+      }
+      // a symmetric CSR always holds (x, v); without it (unchecked input) the weight is 0
+      const bool found = lo < (int32_t)(X.x + X.y) && col[lo] == it.v;
+      rank32[2 * (int64_t)e + 1] = found ? rank32[2 * (int64_t)lo] : 0u;
+    }
+  }
+}
+
+hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
+                              const uint4* rec, uint64_t* keys, uint2* rank, int32_t* col_rank, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const dim3 grid(item_grid(n_items)), block(256);
+  uint32_t* rank32 = reinterpret_cast<uint32_t*>(rank);
+  hipLaunchKernelGGL(k_rank_local, grid, block, 0, s, n_items, items, rp, col, rec, keys, rank32, col_rank);
+  hipLaunchKernelGGL(k_rank_merge, grid, block, 0, s, n_items, items, rp, col, rec, keys, rank32, col_rank);
+  hipLaunchKernelGGL(k_rank_mirror, grid, block, 0, s, n_items, items, rp, col, rec, rank32);
+  return hipGetLastError();
+}
+
+__global__ void k_row_totals(int32_t n, const int32_t* __restrict__ rp, const uint64_t* __restrict__ acc,
+                             uint64_t* __restrict__ w) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r1 = rp[v + 1];
+    w[v] = r1 > rp[v] ? acc[r1 - 1] : 0ull;
+  }
+}
+
+hipError_t launch_row_totals(int32_t n, const int32_t* rp, const uint64_t* acc, uint64_t* w, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_totals, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, acc, w);
   return hipGetLastError();
 }
 
@@ -810,11 +983,6 @@ struct PrefixOf64 {
   __device__ uint64_t operator()(int32_t i) const { return acc[i]; }
 };
 
-// row start and degree of a node (the first half of its record)
-__device__ __forceinline__ uint2 row_of(const uint4* __restrict__ rec, int32_t x) {
-  return *reinterpret_cast<const uint2*>(rec + x);
-}
-
 // ---------------------------------------------------------------------------------
 // The samplers.  Each returns the motif class of sample k (0 = rejected) and, when
 // `nodes` is not null, writes the sampled nodes v, u, w, r, t.
@@ -881,6 +1049,68 @@ __device__ __forceinline__ int draw_moss4(const SamplerView& a, const uint8_t* l
   if (r == w) return 0;
   const int32_t px[3] = {u, v, w}, py[3] = {w, r, r};
   return lut[probe_edges<3>(a, px, py)];
+}
+
+// Reach count of a MOSS-4Min sample (Section 4.2.1): the ordered draws (w, v, u, r) of
+// its four nodes with edges w-v, v-u, u-r, w above u and r above v.  Nodes 0..3 are
+// v, u, w, r; bit 4a + b of adj is set when nodes a and b are adjacent; k0..k3 are
+// their order keys.  Each such draw has probability 1/check-Gamma, so the sample's
+// set was drawn with probability (reach count)/check-Gamma.
+__device__ int reach_count(uint32_t adj, uint64_t k0, uint64_t k1, uint64_t k2, uint64_t k3) {
+  const uint64_t key[4] = {k0, k1, k2, k3};
+  int c = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (w == v || u == w || u == v) continue;
+        const int r = 6 - w - v - u;  // the fourth node
+        const bool path = (adj >> (4 * w + v) & 1) && (adj >> (4 * v + u) & 1) && (adj >> (4 * u + r) & 1);
+        if (path && key[w] > key[u] && key[r] > key[v]) ++c;
+      }
+  return c;
+}
+
+// MOSS-4Min (Algorithm 2): v ~ check-Gamma_v, u ~ d_{u,v} d_{v,u} over N_v (row prefix
+// acc_check), w uniform in N_{v,u} and r uniform in N_{u,v} (the first d_{v,u} and
+// d_{u,v} entries of the rows in descending order); rejected when r = w.  Known edges
+// vu, vw, ur; probe bits as MOSS-4 (b0 = u~w, b1 = v~r, b2 = w~r).  A diamond (class 5)
+// is reached by 2, 4 or 6 ordered draws; its count c goes out as the extra bin
+// 6 + c/2 in bits 8 and up of the result.
+__device__ __forceinline__ int draw_moss4min(const SamplerView& a, const uint8_t* lut, uint64_t seed, uint64_t k,
+                                             int32_t* nodes) {
+  uint64_t W[4];
+  philox_block(k, 0, seed, kMoss4Min, W);
+  const int32_t v = pick_node(a, W[0]);
+  const uint4 R = a.rec[v];
+  const int32_t rv = (int32_t)R.x, dv = (int32_t)R.y;
+  const uint64_t* __restrict__ chk = a.acc_check + rv;
+  const uint64_t T = chk[dv - 1];
+  const int32_t iu = row_pick(PrefixOf64{chk}, dv, T, bounded(W[1], T), a.check_guide, R.w);
+  const int32_t u = a.col[rv + iu];
+  const uint2 rk = a.rank[rv + iu];  // d_{v,u}, d_{u,v}: both >= 1 for a drawn entry
+  const int32_t w = a.col_rank[rv + (int32_t)bounded(W[2], (uint64_t)rk.x)];
+  const uint2 U = row_of(a.rec, u);
+  const int32_t r = a.col_rank[(int32_t)U.x + (int32_t)bounded(W[3], (uint64_t)rk.y)];
+  if (nodes) {
+    nodes[0] = v; nodes[1] = u; nodes[2] = w; nodes[3] = r; nodes[4] = -1;
+  }
+  if (r == w) return 0;
+  const int32_t px[3] = {u, v, w}, py[3] = {w, r, r};
+  const int m = probe_edges<3>(a, px, py);
+  const int c = lut[m];
+  if (c != 5) return c;
+  // known v-u (0,1), v-w (0,2), u-r (1,3); probed u-w (1,2), v-r (0,3), w-r (2,3)
+  uint32_t adj = (1u << 1) | (1u << 4) | (1u << 2) | (1u << 8) | (1u << 7) | (1u << 13);
+  if (m & 1) adj |= (1u << 6) | (1u << 9);
+  if (m & 2) adj |= (1u << 3) | (1u << 12);
+  if (m & 4) adj |= (1u << 11) | (1u << 14);
+  const uint64_t kv = ((uint64_t)R.y << 32) | (uint32_t)v, ku = ((uint64_t)U.y << 32) | (uint32_t)u;
+  const uint64_t kw = ((uint64_t)row_of(a.rec, w).y << 32) | (uint32_t)w;
+  const uint64_t kr = ((uint64_t)row_of(a.rec, r).y << 32) | (uint32_t)r;
+  return c | ((6 + reach_count(adj, kv, ku, kw, kr) / 2) << 8);
 }
 
 // T-5 (Algorithm 3): v ~ Gamma^(1)_v, u ~ d_u - 1 over N_v, w then r uniform over
@@ -967,6 +1197,7 @@ template <int S>
 __device__ __forceinline__ int draw(const SamplerView& a, const uint8_t* lut, uint64_t seed, uint64_t k,
                                     int32_t* nodes) {
   if constexpr (S == kMoss4) return draw_moss4(a, lut, seed, k, nodes);
+  else if constexpr (S == kMoss4Min) return draw_moss4min(a, lut, seed, k, nodes);
   else if constexpr (S == kT5) return draw_t5(a, lut, seed, k, nodes);
   else return draw_path5(a, lut, seed, k, nodes);
 }
@@ -975,7 +1206,7 @@ template <int S>
 __device__ __forceinline__ void load_lut(uint8_t* lut) {
   const int tid = threadIdx.x;
   if (tid < 64) {
-    if constexpr (S == kMoss4) lut[tid] = tid < 8 ? c_lut4[tid] : 0;
+    if constexpr (S == kMoss4 || S == kMoss4Min) lut[tid] = tid < 8 ? c_lut4[tid] : 0;
     else if constexpr (S == kT5) lut[tid] = c_lut5t[tid];
     else lut[tid] = c_lut5p[tid];
   }
@@ -983,6 +1214,13 @@ __device__ __forceinline__ void load_lut(uint8_t* lut) {
 
 constexpr int kMaxWaves = 16;  // 1024 threads per block at most
 constexpr int kBins = 22;
+
+// One sample into a wave's LDS counters: its class, and for a MOSS-4Min diamond the
+// reach-count bin too.
+__device__ __forceinline__ void count_sample(uint32_t* bins, int c) {
+  atomicAdd(&bins[c & 0xff], 1u);
+  if (c >> 8) atomicAdd(&bins[c >> 8], 1u);
+}
 
 template <int S>
 __global__ __launch_bounds__(256, 8) void k_sample(SamplerView a, uint64_t seed, uint64_t k0, uint64_t k1,
@@ -996,7 +1234,7 @@ __global__ __launch_bounds__(256, 8) void k_sample(SamplerView a, uint64_t seed,
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t k = k0 + (uint64_t)blockIdx.x * blockDim.x + tid; k < k1; k += stride) {
     const int c = draw<S>(a, lut, seed, k, nullptr);
-    atomicAdd(&bins[wave][c], 1u);
+    count_sample(bins[wave], c);
     if (class_out) class_out[k - k0] = (uint8_t)c;
   }
   __syncthreads();
@@ -1016,6 +1254,9 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
     uint8_t* co = class_out ? class_out + (a - k0) : nullptr;
     switch (sampler) {
       case kMoss4: hipLaunchKernelGGL(k_sample<kMoss4>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co); break;
+      case kMoss4Min:
+        hipLaunchKernelGGL(k_sample<kMoss4Min>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co);
+        break;
       case kT5: hipLaunchKernelGGL(k_sample<kT5>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co); break;
       case kPath5: hipLaunchKernelGGL(k_sample<kPath5>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co); break;
       default: return hipErrorInvalidValue;
@@ -1180,7 +1421,7 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
       for (uint64_t j = p + tid; j < q; j += blockDim.x) {
         const uint64_t i = t.order[j];
         const int c = draw<S>(a, lut, seed, k0 + i, nullptr);
-        atomicAdd(&bins[wave][c], 1u);
+        count_sample(bins[wave], c);
         if (class_out) class_out[i] = (uint8_t)c;
       }
     }
@@ -1208,6 +1449,7 @@ hipError_t launch_sample_grouped(int sampler, const SamplerView& v, uint64_t see
     uint8_t* co = class_out ? class_out + (a - k0) : nullptr;
     switch (sampler) {
       case kMoss4: hipLaunchKernelGGL(k_sort_count<kMoss4>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
+      case kMoss4Min: hipLaunchKernelGGL(k_sort_count<kMoss4Min>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
       case kT5: hipLaunchKernelGGL(k_sort_count<kT5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
       case kPath5: hipLaunchKernelGGL(k_sort_count<kPath5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
       default: return hipErrorInvalidValue;
@@ -1227,6 +1469,9 @@ hipError_t launch_sample_grouped(int sampler, const SamplerView& v, uint64_t see
     switch (sampler) {
       case kMoss4:
         hipLaunchKernelGGL(k_sample_sorted<kMoss4>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
+        break;
+      case kMoss4Min:
+        hipLaunchKernelGGL(k_sample_sorted<kMoss4Min>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
         break;
       case kT5:
         hipLaunchKernelGGL(k_sample_sorted<kT5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
@@ -1262,6 +1507,9 @@ hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed,
   const dim3 grid((unsigned)((count + 255) / 256)), block(256);
   switch (sampler) {
     case kMoss4: hipLaunchKernelGGL(k_sample_nodes<kMoss4>, grid, block, 0, s, v, seed, index, count, nodes_out, class_out); break;
+    case kMoss4Min:
+      hipLaunchKernelGGL(k_sample_nodes<kMoss4Min>, grid, block, 0, s, v, seed, index, count, nodes_out, class_out);
+      break;
     case kT5: hipLaunchKernelGGL(k_sample_nodes<kT5>, grid, block, 0, s, v, seed, index, count, nodes_out, class_out); break;
     case kPath5: hipLaunchKernelGGL(k_sample_nodes<kPath5>, grid, block, 0, s, v, seed, index, count, nodes_out, class_out); break;
     default: return hipErrorInvalidValue;
@@ -1299,6 +1547,9 @@ __global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict_
     if (tile.sampler == kMoss4) {
       for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
         atomicAdd(&lb[wave][draw_moss4(v, lut4, tile.seed, k, nullptr)], 1u);
+    } else if (tile.sampler == kMoss4Min) {
+      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
+        count_sample(lb[wave], draw_moss4min(v, lut4, tile.seed, k, nullptr));
     } else if (tile.sampler == kT5) {
       for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
         atomicAdd(&lb[wave][draw_t5(v, lut5t, tile.seed, k, nullptr)], 1u);
@@ -1327,6 +1578,7 @@ int sample_kernel_blocks_per_cu(int sampler, int block) {
   hipError_t e = hipSuccess;
   switch (sampler) {
     case kMoss4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<kMoss4>, block, 0); break;
+    case kMoss4Min: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<kMoss4Min>, block, 0); break;
     case kT5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<kT5>, block, 0); break;
     case kPath5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sample<kPath5>, block, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, block, 0); break;

@@ -99,7 +99,7 @@ struct moss_server {
       if (!victim) return false;
       moss::GraphClaim claim(victim->g);
       if (!claim.ok()) return false;
-      moss::free_graph_tables(victim->g, MOSS_TABLES_K4 | MOSS_TABLES_K5);
+      moss::free_graph_tables(victim->g, MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN);
       ++evictions;
     }
     return true;
@@ -129,7 +129,9 @@ void moss_server::loop() {
         continue;
       }
       GraphEntry& ge = graphs[(size_t)r->graph_id];
-      const uint32_t mask = r->k == 4 ? MOSS_TABLES_K4 : MOSS_TABLES_K5;
+      moss::EstimatePlan plan;
+      (void)moss::plan_estimate(r->k, r->n, r->flags, &plan);  // checked at submission
+      const uint32_t mask = plan.tables;
       if ((ge.g->built & mask) != mask) {
         const uint64_t need = moss::table_bytes_needed(ge.g, mask);
         if (cfg.mem_budget_bytes && need > cfg.mem_budget_bytes) {
@@ -171,11 +173,12 @@ void moss_server::loop() {
     for (size_t i = 0; i < batch.size(); ++i) {
       Req& r = *batch[i];
       moss_graph* g = graphs[(size_t)r.graph_id].g;
-      const int samplers[2] = {r.k == 4 ? moss::kMoss4 : moss::kT5, moss::kPath5};
-      for (int s = 0; s < (r.k == 4 ? 1 : 2); ++s) {
-        const uint64_t b = std::min(r.K[s], r.next[s] + chunk);
+      moss::EstimatePlan plan;
+      (void)moss::plan_estimate(r.k, r.n, r.flags, &plan);
+      for (int s = 0; s < 2; ++s) {
+        const uint64_t b = s < plan.count ? std::min(r.K[s], r.next[s] + chunk) : r.next[s];
         upto[2 * i + s] = b;
-        if (b > r.next[s]) work.push_back({g, samplers[s], r.seed, r.next[s], b, (uint32_t)(2 * i + s)});
+        if (b > r.next[s]) work.push_back({g, plan.sampler[s], r.seed, r.next[s], b, (uint32_t)(2 * i + s)});
       }
     }
     lk.unlock();
@@ -197,7 +200,7 @@ void moss_server::loop() {
       } else {
         for (int s = 0; s < 2; ++s) {
           for (int c = 0; c < 22; ++c) r->hits[s][c] += bins[(2 * i + s) * 22 + c];
-          if (s == 0 || r->k == 5) r->next[s] = upto[2 * i + s];
+          r->next[s] = upto[2 * i + s];
         }
         if (r->cancelled) {
           finish(r, MOSS_E_CANCELLED);
@@ -259,8 +262,8 @@ moss_status moss_server_add_graph(moss_server* s, moss_graph* g, int32_t* graph_
 
 moss_status moss_server_submit(moss_server* s, int32_t graph_id, int32_t k, uint64_t n_samples, uint64_t seed,
                                uint32_t flags, uint64_t* ticket) {
-  if (!s || !ticket || (k != 4 && k != 5) || (flags & ~MOSS_MIX_PAPER)) return MOSS_E_ARG;
-  if ((k == 4 && n_samples < 1) || (k == 5 && n_samples < 2)) return MOSS_E_ARG;
+  moss::EstimatePlan plan;
+  if (!s || !ticket || moss::plan_estimate(k, n_samples, flags, &plan) != MOSS_OK) return MOSS_E_ARG;
   auto r = std::make_shared<Req>();
   r->graph_id = graph_id;
   r->k = k;

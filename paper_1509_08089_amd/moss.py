@@ -25,12 +25,13 @@ STATUS = {
 }
 globals().update({v: k for k, v in STATUS.items()})
 
-MOSS_SAMPLER_MOSS4, MOSS_SAMPLER_T5, MOSS_SAMPLER_PATH5 = 0x4, 0x51, 0x52
+MOSS_SAMPLER_MOSS4, MOSS_SAMPLER_MOSS4MIN, MOSS_SAMPLER_T5, MOSS_SAMPLER_PATH5 = 0x4, 0x41, 0x51, 0x52
 MOSS_SCHEDULE_AUTO, MOSS_SCHEDULE_PLAIN, MOSS_SCHEDULE_XCD = 0, 1, 2
 MOSS_TRUST_CSR = 0x1
-MOSS_MIX_POOLED, MOSS_MIX_PAPER = 0x0, 0x1
-MOSS_TABLES_K4, MOSS_TABLES_K5 = 1 << 4, 1 << 5
+MOSS_MIX_POOLED, MOSS_MIX_PAPER, MOSS_K4_MIN = 0x0, 0x1, 0x2
+MOSS_TABLES_K4, MOSS_TABLES_K5, MOSS_TABLES_K4MIN = 1 << 4, 1 << 5, 1 << 6
 MOSS_TAB_ACC_GAMMA, MOSS_TAB_ACC_GAMMA1, MOSS_TAB_ACC_GAMMA2, MOSS_TAB_ACC_SIGMA, MOSS_TAB_ACC_TAU = 5, 6, 7, 8, 9
+MOSS_TAB_ACC_GAMMA_MIN, MOSS_TAB_ACC_CHECK, MOSS_TAB_RANK, MOSS_TAB_COL_RANK = 11, 12, 13, 15
 
 # every symbol include/moss.h declares
 EXPORTED = [
@@ -52,7 +53,7 @@ class moss_graph_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("max_degree", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("built_mask", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("gamma", ctypes.c_uint64),
                 ("gamma1", ctypes.c_uint64), ("gamma2", ctypes.c_uint64), ("lambda3", ctypes.c_uint64),
-                ("lambda4", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64)]
+                ("lambda4", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("gamma_min", ctypes.c_uint64)]
 
 
 class moss_result(ctypes.Structure):
@@ -204,8 +205,12 @@ def moss_graph_get_info(g) -> moss_graph_info:
 
 
 def moss_table_read(g, which: int, count: int) -> np.ndarray:
-    dtype = np.uint32 if which == MOSS_TAB_ACC_SIGMA else np.uint64
-    out = np.zeros(count, dtype)
+    """One table as a numpy array (MOSS_TAB_RANK: count x 2 u32 pairs)."""
+    if which == MOSS_TAB_RANK:
+        out = np.zeros((count, 2), np.uint32)
+    else:
+        dtype = {MOSS_TAB_ACC_SIGMA: np.uint32, MOSS_TAB_COL_RANK: np.int32}.get(which, np.uint64)
+        out = np.zeros(count, dtype)
     _check(lib().moss_table_read(g, which, _hptr(out), count), "moss_table_read")
     return out
 
@@ -228,7 +233,7 @@ def moss_sample_nodes(g, sampler: int, seed: int, d_index, d_nodes_out, d_class_
 
 
 def moss_class_lut(sampler: int) -> np.ndarray:
-    n = 8 if sampler == MOSS_SAMPLER_MOSS4 else 64
+    n = 8 if sampler in (MOSS_SAMPLER_MOSS4, MOSS_SAMPLER_MOSS4MIN) else 64
     out = np.zeros(n, np.uint8)
     _check(lib().moss_class_lut(sampler, _hptr(out), n), "moss_class_lut")
     return out
@@ -365,7 +370,8 @@ class Graph:
         return moss_graph_get_info(self.h)
 
     def table(self, which: int) -> np.ndarray:
-        count = self.nnz if which in (MOSS_TAB_ACC_SIGMA, MOSS_TAB_ACC_TAU) else self.n
+        per_entry = (MOSS_TAB_ACC_SIGMA, MOSS_TAB_ACC_TAU, MOSS_TAB_ACC_CHECK, MOSS_TAB_RANK, MOSS_TAB_COL_RANK)
+        count = self.nnz if which in per_entry else self.n
         return moss_table_read(self.h, which, count)
 
     def estimate(self, k: int, n_samples: int, seed: int, flags: int = 0) -> moss_result:

@@ -98,9 +98,9 @@ def test_per_sample_classes_and_ranges(c1, sampler):
 @pytest.mark.parametrize("sampler", SAMPLERS)
 def test_sampled_nodes_match_oracle(c1, sampler):
     G, og = moss.Graph(c1), oracle.Graph(c1)
-    idx = np.concatenate([np.arange(0, 300), np.array([2**40 + 5, 2**63 - 1, 2**64 - 1], dtype=np.uint64),
+    idx = np.concatenate([np.arange(0, 300, dtype=np.uint64),
+                          np.array([2**40 + 5, 2**63 - 1, 2**64 - 1], dtype=np.uint64),
                           np.random.Generator(np.random.PCG64(1)).integers(0, 2**62, 500, dtype=np.uint64)])
-    idx = idx.astype(np.uint64)
     nodes, cls = G.sample_nodes(sampler, 11, idx)
     osid = ORACLE_SAMPLER[sampler]
     for i, k in enumerate(idx):

@@ -35,6 +35,7 @@ def test_status_strings():
 # node order v, u, w, r, t; pairs fixed by each sampler, then the probed pairs in bit order
 STRUCTURE = {
     moss.MOSS_SAMPLER_MOSS4: (4, [(0, 1), (0, 2), (1, 3)], [(1, 2), (0, 3), (2, 3)]),
+    moss.MOSS_SAMPLER_MOSS4MIN: (4, [(0, 1), (0, 2), (1, 3)], [(1, 2), (0, 3), (2, 3)]),
     moss.MOSS_SAMPLER_T5: (5, [(0, 1), (0, 2), (0, 3), (1, 4)], [(1, 2), (1, 3), (2, 3), (0, 4), (2, 4), (3, 4)]),
     moss.MOSS_SAMPLER_PATH5: (5, [(0, 1), (0, 2), (1, 3), (2, 4)], [(0, 3), (0, 4), (1, 2), (1, 4), (2, 3), (3, 4)]),
 }
@@ -105,11 +106,45 @@ def test_finals5_match_oracle(seed, mix):
         assert _rel_close(r.variance[i], var[i], 0.0, 1e-11), (i, r.variance[i], var[i])
 
 
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("mix", [moss.MOSS_MIX_POOLED, moss.MOSS_MIX_PAPER])
+def test_finals4_min_match_oracle(seed, mix):
+    """MOSS-4 mixed with MOSS-4Min (reach-count bins in hits[1][7..9])."""
+    rng = np.random.Generator(np.random.PCG64(300 + seed))
+    K = int(rng.integers(1, 10**8))
+    Kc = K - int(rng.integers(0, 2)) or 1
+    h4 = rng.multinomial(K, rng.dirichlet(np.ones(7))).astype(np.uint64)
+    hm = np.zeros(22, np.uint64)
+    hm[:7] = rng.multinomial(Kc, rng.dirichlet(np.ones(7)))
+    hm[7:10] = rng.multinomial(int(hm[5]), rng.dirichlet(np.ones(3)))
+    gamma = int(rng.integers(1, 2**60)) if seed % 5 else 0
+    gmin = int(rng.integers(0, gamma + 1)) if seed % 3 else 0
+    lam = int(rng.integers(0, 2**60))
+    r = moss.moss_result()
+    r.k, r.flags, r.K[0], r.K[1], r.lambda_ = 4, mix | moss.MOSS_K4_MIN, K, Kc, lam
+    r.gamma[0], r.gamma[1] = gamma, gmin
+    for i in range(22):
+        r.hits[0][i] = int(h4[i]) if i < 7 else 0
+        r.hits[1][i] = int(hm[i])
+    moss.moss_finals(r)
+    est, var = oracle.finals4min(K, h4, gamma, lam, Kc, hm[:10], gmin, mix)
+    for i in range(6):
+        scale = float(lam) if i == 1 else 0.0
+        assert _rel_close(r.estimate[i], est[i], scale), (i, r.estimate[i], est[i])
+        assert _rel_close(r.variance[i], var[i], 0.0, 1e-11), (i, r.variance[i], var[i])
+
+
 def test_finals_reject_bad_arguments():
     r = moss.moss_result()
     r.k = 3
     with pytest.raises(moss.MossError):
         moss.moss_finals(r)
     r.k, r.K[0] = 4, 0
+    with pytest.raises(moss.MossError):
+        moss.moss_finals(r)
+    r.k, r.K[0], r.K[1], r.flags = 4, 10, 0, moss.MOSS_K4_MIN  # no MOSS-4Min samples
+    with pytest.raises(moss.MossError):
+        moss.moss_finals(r)
+    r.k, r.K[0], r.K[1], r.flags = 5, 10, 10, moss.MOSS_K4_MIN  # the flag is for k = 4
     with pytest.raises(moss.MossError):
         moss.moss_finals(r)
