@@ -6,6 +6,8 @@ sampling tables (Section 4.1.3 initialization), draw and classify every sample
 (Algorithm 1, or Algorithms 3 and 4), reduce the histograms and compute the FP64
 finals.  The default workload is the plain 4-node configuration (Chung-Lu n=1e5,
 m=1e6, 1e7 samples, seed 1).  value = samples drawn per second of wall time.
+C2MIN is the same graph and budget with MOSS-4 and MOSS-4Min (Section 4.2) on half the
+samples each, their rank tables built in the step, and the 4-node mix.
 
 Also reported on the same JSON line:
   roofline      algorithmic bytes of the sampling kernel per launch (64 B per line
@@ -17,7 +19,7 @@ Also reported on the same JSON line:
                 vs one launch per request
   serving       (--serve) Poisson arrivals over many resident graphs: p50/p99 latency
 
-Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--workload C2|C3]
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--workload C2|C3|C2MIN]
 """
 from __future__ import annotations
 
@@ -39,6 +41,8 @@ WORKLOAD_TEXT = {
     "C1": "plain 4-node MOSS-4, Chung-Lu n=2e3 m=1e4 beta=2.5 dmax=200, 1e5 samples, seed 1",
     "C2": "plain 4-node MOSS-4, Chung-Lu n=1e5 m=1e6 beta=2.2 dmax=3e3, 1e7 samples, seed 1",
     "C3": "plain 5-node MOSS-5 (T-5 + Path-5), Chung-Lu n=1e6 m=1e7 beta=2.1 dmax=2e4, 1e8 samples, seed 1",
+    "C2MIN": "4-node MOSS-4 + MOSS-4Min mix (5e6 + 5e6 samples), Chung-Lu n=1e5 m=1e6 beta=2.2 dmax=3e3, "
+             "seed 1",
 }
 
 
@@ -51,7 +55,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3"])
+    ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C2MIN"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", action="store_true")
@@ -122,6 +126,7 @@ def cpu_baseline(csr, cfg, seconds: float):
     og = oracle.Graph(csr)
     build_s = time.time() - t
     sid = oracle.MOSS4 if cfg["k"] == 4 else oracle.T5
+    pair = (oracle.MOSS4, oracle.MOSS4MIN) if cfg.get("min") else (oracle.T5, oracle.PATH5)
     # calibrate, then run a bounded prefix of the sample stream
     n = 20_000 * cores
     t = time.time()
@@ -129,12 +134,12 @@ def cpu_baseline(csr, cfg, seconds: float):
     dt = max(time.time() - t, 1e-6)
     n = int(min(cfg["samples"], max(n, n * seconds / dt)))
     t = time.time()
-    if cfg["k"] == 4:
+    if cfg["k"] == 4 and not cfg.get("min"):
         og.run(oracle.MOSS4, cfg["seed"], 0, n, cores)
         done = n
-    else:
-        og.run(oracle.T5, cfg["seed"], 0, (n + 1) // 2, cores)
-        og.run(oracle.PATH5, cfg["seed"], 0, n // 2, cores)
+    else:  # two samplers on half the samples each
+        og.run(pair[0], cfg["seed"], 0, (n + 1) // 2, cores)
+        og.run(pair[1], cfg["seed"], 0, n // 2, cores)
         done = n
     dt = time.time() - t
     return {"value": done / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
@@ -162,11 +167,14 @@ def main():
     from paper_1509_08089_amd import moss
 
     torch.cuda.init()
-    cfg = gg.CONFIGS[args.workload]
+    with_min = args.workload == "C2MIN"
+    base = "C2" if with_min else args.workload  # graph, line counts and exact counts
+    cfg = dict(gg.CONFIGS[base], min=with_min)
     log(f"[bench] generating {args.workload} graph")
     csr = cfg["graph"].build()
     k, K, seed = cfg["k"], cfg["samples"], cfg["seed"]
-    mask = moss.MOSS_TABLES_K4 if k == 4 else moss.MOSS_TABLES_K5
+    flags = moss.MOSS_K4_MIN if with_min else 0
+    mask = (moss.MOSS_TABLES_K4 | (moss.MOSS_TABLES_K4MIN if with_min else 0)) if k == 4 else moss.MOSS_TABLES_K5
     d_rp = torch.from_numpy(csr.row_ptr).cuda()
     d_col = torch.from_numpy(csr.col).cuda()
     torch.cuda.synchronize()
@@ -176,7 +184,7 @@ def main():
         h = moss.moss_graph_create_device(csr.n, csr.nnz, d_rp, d_col, 0, stream)
         try:
             moss.moss_build_tables(h, mask)
-            return moss.moss_estimate(h, k, K, seed, 0)
+            return moss.moss_estimate(h, k, K, seed, flags)
         finally:
             moss.moss_graph_destroy(h)
 
@@ -197,9 +205,12 @@ def main():
         assert np.array_equal(r.hits_np, results[0].hits_np)
 
     # roofline of the sampling kernel(s): algorithmic bytes per launch / average duration
-    lc = json.load(open(os.path.join(ROOT, "tests", "golden", "line_counts.json")))[args.workload]
+    lc = json.load(open(os.path.join(ROOT, "tests", "golden", "line_counts.json")))[base]
     r0 = results[0]
-    if k == 4:
+    if with_min:
+        alg_bytes = 64.0 * (r0.K[0] * lc["moss4"] + r0.K[1] * lc["moss4min"])
+        kernel = "k_sample_moss4_moss4min"
+    elif k == 4:
         alg_bytes = K * 64.0 * lc["moss4"]
         kernel = "k_sample_moss4"
     else:
@@ -222,12 +233,12 @@ def main():
                      "kernel": kernel, "kernel_ms": kern_ms,
                      "traffic_gbs": traffic_gbs, "traffic_frac": traffic_gbs / PEAK_HBM_GBS if traffic_gbs else None,
                      "alg_bytes_per_launch": alg_bytes,
-                     "lines_per_sample": {kk: lc[kk] for kk in ("moss4", "t5", "path5") if kk in lc},
+                     "lines_per_sample": {kk: lc[kk] for kk in ("moss4", "moss4min", "t5", "path5") if kk in lc},
                      "kernel_samples_per_s": K / (kern_ms / 1e3)},
         "estimates": [float(x) for x in r0.estimate_np],
         "stderr_rel": [float(math.sqrt(v) / e) if e > 0 else None for v, e in zip(r0.variance_np, r0.estimate_np)],
     }
-    exact = exact_counts(args.workload, csr.sha256(), k)
+    exact = exact_counts(base, csr.sha256(), k)
     if exact is not None:
         line["exact"] = exact
         line["rel_error"] = [abs(e - x) / x if x else None for e, x in zip(line["estimates"], exact)]

@@ -77,6 +77,14 @@ def lib():
             L.orc_finals4min.argtypes = [u64, P, u64, u64, u64, P, u64, ctypes.c_int, P, P]
             L.orc_ways_of.argtypes = [P, P]
             L.orc_estimate4min.argtypes = [P, u64, u64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Result)]
+            L.orc_normal_two_sided.argtypes = [ctypes.c_double]
+            L.orc_normal_two_sided.restype = ctypes.c_double
+            L.orc_plan_budget.argtypes = [ctypes.POINTER(_Result), ctypes.c_double, ctypes.c_double, ctypes.c_uint32,
+                                          P, ctypes.POINTER(u64)]
+            L.orc_concentrations.argtypes = [ctypes.POINTER(_Result), P]
+            L.orc_estimate_to_precision.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_uint32, u64, u64, u64, u64, ctypes.c_int, ctypes.c_int,
+                                                    ctypes.POINTER(_Result), ctypes.POINTER(u64)]
             L.orc_estimate.argtypes = [P, ctypes.c_int, u64, u64, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(_Result)]
             L.orc_count_cis.argtypes = [P, ctypes.c_int, P]
@@ -120,6 +128,7 @@ def classify(k: int, adj) -> int:
 
 class Result:
     def __init__(self, r: _Result):
+        self.raw = r
         self.k = r.k
         self.n_motifs = r.n_motifs
         self.K = [int(r.K[0]), int(r.K[1])]
@@ -199,6 +208,18 @@ class Graph:
             raise OracleError(st, "orc_estimate4min")
         return Result(r)
 
+    def estimate_to_precision(self, k: int, eps: float, delta: float, motif_mask: int, pilot_samples: int,
+                              pilot_seed: int, max_samples: int, seed: int, with_min: bool = False,
+                              mix: int = MIX_POOLED, threads: int = 1):
+        r = _Result()
+        K = ctypes.c_uint64()
+        st = lib().orc_estimate_to_precision(self._h, k, int(with_min), eps, delta, motif_mask, pilot_samples,
+                                             pilot_seed, max_samples, seed, mix, threads, ctypes.byref(r),
+                                             ctypes.byref(K))
+        if st != OK:
+            raise OracleError(st, "orc_estimate_to_precision")
+        return Result(r), int(K.value)
+
     def count_cis(self, k: int) -> np.ndarray:
         out = np.zeros(22, np.uint64)
         st = lib().orc_count_cis(self._h, k, _ptr(out))
@@ -260,3 +281,25 @@ def ways_of(adj, keys) -> int:
     a = np.ascontiguousarray(np.asarray(adj, dtype=np.uint8).reshape(16))
     k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64).reshape(4))
     return int(lib().orc_ways_of(_ptr(a), _ptr(k)))
+
+
+def normal_two_sided(delta: float) -> float:
+    return float(lib().orc_normal_two_sided(delta))
+
+
+def plan_budget(pilot: Result, eps: float, delta: float, motif_mask: int = 0):
+    """(per-motif budgets, largest over the mask) from a pilot result."""
+    b = np.zeros(21, np.uint64)
+    mx = ctypes.c_uint64()
+    st = lib().orc_plan_budget(ctypes.byref(pilot.raw), eps, delta, motif_mask, _ptr(b), ctypes.byref(mx))
+    if st != OK:
+        raise OracleError(st, "orc_plan_budget")
+    return b[: pilot.n_motifs], int(mx.value)
+
+
+def concentrations(r: Result) -> np.ndarray:
+    out = np.zeros(21)
+    st = lib().orc_concentrations(ctypes.byref(r.raw), _ptr(out))
+    if st != OK:
+        raise OracleError(st, "orc_concentrations")
+    return out[: r.n_motifs]

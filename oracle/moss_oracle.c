@@ -17,6 +17,7 @@
  */
 #include "moss_oracle.h"
 
+#include <math.h>
 #include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
@@ -941,6 +942,71 @@ int orc_estimate4min(const orc_graph *g, uint64_t n_samples, uint64_t seed, int 
   if (st) return st;
   return orc_finals4min(K, res->hits[0], g->tot.gamma, g->tot.lambda3, Kc, res->hits[1], g->tot.gamma_min, mix,
                         res->estimate, res->variance);
+}
+
+/* Theorem 1: an estimate is asymptotically normal around the count, so
+   P(|est - n| >= z sqrt(Var)) -> P(|Z| >= z) = erfc(z / sqrt 2).  (The theorem prints
+   the one-sided tail; the two-sided event needs both.) */
+double orc_normal_two_sided(double delta) {
+  double lo = 0.0, hi = 40.0;
+  for (int it = 0; it < 200; ++it) {
+    double mid = lo + (hi - lo) / 2.0;
+    if (erfc(mid / sqrt(2.0)) > delta) lo = mid; else hi = mid;
+  }
+  return (lo + hi) / 2.0;
+}
+
+int orc_plan_budget(const orc_result *pilot, double eps, double delta, uint32_t motif_mask, uint64_t budget[21],
+                    uint64_t *max_budget) {
+  if (!pilot || !budget || !max_budget || !(eps > 0.0) || !(delta > 0.0) || !(delta < 1.0)) return ORC_E_ARG;
+  if (pilot->n_motifs != 6 && pilot->n_motifs != 21) return ORC_E_ARG;
+  double z = orc_normal_two_sided(delta);
+  double Kp = (double)(pilot->K[0] + pilot->K[1]);
+  *max_budget = 0;
+  for (int i = 0; i < 21; ++i) {
+    budget[i] = 0;
+    if (i >= pilot->n_motifs) continue;
+    double e = pilot->estimate[i];
+    if (!(e > 0.0)) continue;
+    double num = z * z * pilot->variance[i] * Kp;
+    double den = eps * eps * e * e;
+    double kk = num / den;
+    uint64_t Ki;
+    if (!(kk > 1.0)) Ki = 1;
+    else if (kk >= 18446744073709549568.0) Ki = UINT64_MAX;
+    else Ki = (uint64_t)ceil(kk);
+    budget[i] = Ki;
+    if ((motif_mask == 0 || (motif_mask >> i & 1)) && Ki > *max_budget) *max_budget = Ki;
+  }
+  return ORC_OK;
+}
+
+int orc_concentrations(const orc_result *r, double omega[21]) {
+  if (!r || !omega || (r->n_motifs != 6 && r->n_motifs != 21)) return ORC_E_ARG;
+  double sum = 0.0;
+  for (int i = 0; i < r->n_motifs; ++i) sum += r->estimate[i];
+  for (int i = 0; i < 21; ++i) omega[i] = (i < r->n_motifs && sum != 0.0) ? r->estimate[i] / sum : 0.0;
+  return ORC_OK;
+}
+
+int orc_estimate_to_precision(const orc_graph *g, int k, int with_min, double eps, double delta, uint32_t motif_mask,
+                              uint64_t pilot_samples, uint64_t pilot_seed, uint64_t max_samples, uint64_t seed,
+                              int mix, int nthreads, orc_result *res, uint64_t *final_samples) {
+  if (!g || !res || !final_samples || (k != 4 && k != 5) || (with_min && k != 4)) return ORC_E_ARG;
+  uint64_t least = (k == 4 && !with_min) ? 1 : 2;
+  if (pilot_samples < least || max_samples < least) return ORC_E_ARG;
+  orc_result pilot;
+  int st = with_min ? orc_estimate4min(g, pilot_samples, pilot_seed, mix, nthreads, &pilot)
+                    : orc_estimate(g, k, pilot_samples, pilot_seed, mix, nthreads, &pilot);
+  if (st) return st;
+  uint64_t budget[21], K;
+  st = orc_plan_budget(&pilot, eps, delta, motif_mask, budget, &K);
+  if (st) return st;
+  if (K == 0) K = pilot_samples;
+  if (K < least) K = least;
+  if (K > max_samples) K = max_samples;
+  *final_samples = K;
+  return with_min ? orc_estimate4min(g, K, seed, mix, nthreads, res) : orc_estimate(g, k, K, seed, mix, nthreads, res);
 }
 
 int orc_estimate(const orc_graph *g, int k, uint64_t n_samples, uint64_t seed, int mix, int nthreads,

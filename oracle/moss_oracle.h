@@ -129,6 +129,27 @@ int orc_estimate(const orc_graph *g, int k, uint64_t n_samples, uint64_t seed, i
 int orc_estimate4min(const orc_graph *g, uint64_t n_samples, uint64_t seed, int mix, int nthreads,
                      orc_result *res);
 
+/* Sampling budget (the closing remark of Section 4.1.2 with Theorem 1's normal limit).
+   z: the two-sided normal quantile, erfc(z / sqrt 2) = delta, found by 200 halvings of
+   [0, 40] (the midpoint of the last interval).  Every variance of Theorems 3, 5 and 10
+   scales as 1/K, so the budget that makes z sqrt(Var_i) <= eps est_i is
+     K_i = max(1, ceil(z^2 var_i K_p / (eps est_i)^2)),   K_p = K[0] + K[1] of the pilot,
+   for each motif with a positive pilot estimate (0 for the others); *max_budget is the
+   largest K_i over the motifs in motif_mask (bit i-1 = motif i; 0 = every motif). */
+double orc_normal_two_sided(double delta);
+int orc_plan_budget(const orc_result *pilot, double eps, double delta, uint32_t motif_mask, uint64_t budget[21],
+                    uint64_t *max_budget);
+
+/* Concentrations omega_i = est_i / sum_j est_j (Section 6.2), 0 when the sum is 0. */
+int orc_concentrations(const orc_result *r, double omega[21]);
+
+/* A pilot estimate (pilot_samples, pilot_seed), the planned budget clamped to
+   [smallest valid, max_samples] (the pilot's size when no motif can be planned), then
+   the estimate with that budget and `seed`.  with_min: k = 4 with MOSS-4Min. */
+int orc_estimate_to_precision(const orc_graph *g, int k, int with_min, double eps, double delta, uint32_t motif_mask,
+                              uint64_t pilot_samples, uint64_t pilot_seed, uint64_t max_samples, uint64_t seed,
+                              int mix, int nthreads, orc_result *res, uint64_t *final_samples);
+
 /* exact counts of k-node connected induced subgraphs per class (ESU enumeration) */
 int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]);
 

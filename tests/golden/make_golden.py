@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 import graphgen as gg  # noqa: E402
 import oracle  # noqa: E402
 
-SAMPLERS = {"moss4": oracle.MOSS4, "t5": oracle.T5, "path5": oracle.PATH5}
+SAMPLERS = {"moss4": oracle.MOSS4, "moss4min": oracle.MOSS4MIN, "t5": oracle.T5, "path5": oracle.PATH5}
 
 
 def line_counts(samples: int) -> dict:
@@ -37,7 +37,7 @@ def line_counts(samples: int) -> dict:
         og = oracle.Graph(g)
         entry = {"graph_sha256": g.sha256(), "n": g.n, "m": g.m, "seed": cfg["seed"], "samples": samples}
         for sname, sid in SAMPLERS.items():
-            if (cfg["k"] == 4) != (sname == "moss4"):
+            if (cfg["k"] == 4) != (sname in ("moss4", "moss4min")):
                 continue
             entry[sname] = og.line_count(sid, cfg["seed"], 0, samples)
         out[name] = entry

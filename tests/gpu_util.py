@@ -6,7 +6,7 @@ from paper_1509_08089_amd import moss
 
 SAMPLERS = (moss.MOSS_SAMPLER_MOSS4, moss.MOSS_SAMPLER_T5, moss.MOSS_SAMPLER_PATH5)
 ORACLE_SAMPLER = {moss.MOSS_SAMPLER_MOSS4: oracle.MOSS4, moss.MOSS_SAMPLER_T5: oracle.T5,
-                  moss.MOSS_SAMPLER_PATH5: oracle.PATH5}
+                  moss.MOSS_SAMPLER_PATH5: oracle.PATH5, moss.MOSS_SAMPLER_MOSS4MIN: oracle.MOSS4MIN}
 
 
 def rel_close(a, b, scale=0.0, tol=1e-12):

@@ -29,7 +29,11 @@ def _sampled_classes(G, og, sampler, seed, K, n_check, rng):
     cls = torch.zeros(K, dtype=torch.uint8, device="cuda")
     hits = G.sample_range(sampler, seed, 0, K, cls)
     counts = torch.bincount(cls.to(torch.int64), minlength=22).cpu().numpy()[:22]
-    np.testing.assert_array_equal(counts, hits)
+    if sampler == moss.MOSS_SAMPLER_MOSS4MIN:  # [7..9]: the diamonds again, by reach count
+        np.testing.assert_array_equal(counts[:7], hits[:7])
+        assert int(hits[7:10].sum()) == int(hits[5])
+    else:
+        np.testing.assert_array_equal(counts, hits)
     idx = np.unique(np.concatenate([np.arange(2000), K - 1 - np.arange(2000),
                                     rng.integers(0, K, size=n_check)]))
     got = cls[torch.from_numpy(idx).cuda()].cpu().numpy()
@@ -51,6 +55,23 @@ def test_c2_full_size():
     assert int(r.hits_np[0].sum()) == K
     hits = _sampled_classes(G, og, moss.MOSS_SAMPLER_MOSS4, seed, K, 20_000, np.random.Generator(np.random.PCG64(2)))
     np.testing.assert_array_equal(hits, r.hits_np[0])
+
+
+@pytest.mark.timeout(600)
+def test_c2_moss4min_mix_full_size():
+    """The C2 graph and budget with MOSS-4 and MOSS-4Min on half the samples each."""
+    cfg = gg.CONFIGS["C2"]
+    g = cfg["graph"].build()
+    G, og = moss.Graph(g), oracle.Graph(g)
+    K, seed = cfg["samples"], cfg["seed"]
+    for mix in (moss.MOSS_MIX_POOLED, moss.MOSS_MIX_PAPER):
+        r = G.estimate(4, K, seed, mix | moss.MOSS_K4_MIN)
+        o = og.estimate4min(K, seed, mix, threads=threads())
+        assert_result_matches(r, o, float(og.totals()["lambda3"]))
+    assert int(r.hits_np[1][:7].sum()) == r.K[1]
+    hits = _sampled_classes(G, og, moss.MOSS_SAMPLER_MOSS4MIN, seed, int(r.K[1]), 20_000,
+                            np.random.Generator(np.random.PCG64(3)))
+    np.testing.assert_array_equal(hits, r.hits_np[1])
 
 
 @pytest.mark.timeout(900)
