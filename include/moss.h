@@ -233,6 +233,31 @@ moss_status moss_class_lut(int32_t sampler, uint8_t *out, int32_t len);
    flags (Theorems 2, 3, 6-10).  Used by the estimate calls; exposed for re-scaling. */
 moss_status moss_finals(moss_result *out);
 
+/* ---- sampling budget and concentrations ------------------------------------------------
+ * The budget that keeps each motif's relative error below eps with probability about
+ * 1 - delta (the closing remark of Section 4.1.2, with Theorem 1's normal limit).  Every
+ * variance of Theorems 3, 5 and 10 scales as 1/K, so from a pilot result
+ *   K_i = max(1, ceil(z^2 variance[i] K_p / (eps estimate[i])^2)),  K_p = K[0] + K[1],
+ * with z the two-sided normal quantile: erfc(z / sqrt 2) = delta, found by 200 halvings
+ * of [0, 40] (the midpoint of the last interval).  budget[i] = K_i for the motifs with a
+ * positive estimate, 0 for the others; *max_budget = the largest K_i over motif_mask
+ * (bit i - 1 = motif i; 0 = every motif), 0 if none.  Needs eps > 0 and 0 < delta < 1.
+ * Host only. */
+moss_status moss_plan_budget(const moss_result *pilot, double eps, double delta, uint32_t motif_mask,
+                             uint64_t budget[21], uint64_t *max_budget);
+
+/* A pilot estimate (pilot_samples, pilot_seed), the planned budget (the pilot's size when
+   no motif of the mask can be planned) clamped to [the least valid budget, max_samples],
+   then the estimate with that budget and `seed` into *out (out->n_samples is the budget
+   used).  Both runs are moss_estimate calls with `flags`. */
+moss_status moss_estimate_to_precision(moss_graph *g, int32_t k, double eps, double delta, uint32_t motif_mask,
+                                       uint64_t pilot_samples, uint64_t pilot_seed, uint64_t max_samples,
+                                       uint64_t seed, uint32_t flags, moss_result *out);
+
+/* Motif concentrations omega_i = estimate_i / sum_j estimate_j (Section 6.2) into
+   omega[0 .. n_motifs - 1] (the rest 0); all 0 when the sum is 0.  Host only. */
+moss_status moss_concentrations(const moss_result *r, double omega[21]);
+
 /* ---- batching: many requests in one persistent launch --------------------------------
  * Every request's samples are cut into tiles of consecutive sample indices; one
  * persistent kernel (replayed from a captured hipGraph) drains the whole tile list and

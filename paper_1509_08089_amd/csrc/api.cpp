@@ -958,6 +958,25 @@ moss_status moss_estimate(moss_graph* g, int32_t k, uint64_t n_samples, uint64_t
   return MOSS_OK;
 }
 
+moss_status moss_estimate_to_precision(moss_graph* g, int32_t k, double eps, double delta, uint32_t motif_mask,
+                                       uint64_t pilot_samples, uint64_t pilot_seed, uint64_t max_samples,
+                                       uint64_t seed, uint32_t flags, moss_result* out) {
+  EstimatePlan plan;
+  if (!g || !out || plan_estimate(k, 2, flags, &plan) != MOSS_OK) return MOSS_E_ARG;
+  const uint64_t least = plan_estimate(k, 1, flags, &plan) == MOSS_OK ? 1 : 2;
+  if (pilot_samples < least || max_samples < least || !(eps > 0.0) || !(delta > 0.0) || !(delta < 1.0))
+    return MOSS_E_ARG;
+  moss_result pilot;
+  moss_status st = moss_estimate(g, k, pilot_samples, pilot_seed, flags, &pilot);
+  if (st != MOSS_OK) return st;
+  uint64_t budget[21], K = 0;
+  st = moss_plan_budget(&pilot, eps, delta, motif_mask, budget, &K);
+  if (st != MOSS_OK) return st;
+  if (K == 0) K = pilot_samples;
+  K = std::min(std::max(K, least), max_samples);
+  return moss_estimate(g, k, K, seed, flags, out);
+}
+
 moss_status moss_sample_range(moss_graph* g, int32_t sampler, uint64_t seed, uint64_t k0, uint64_t k1,
                               uint8_t* d_class_out, uint64_t hits[22]) {
   if (!g || !hits || !valid_sampler(sampler) || k1 < k0) return MOSS_E_ARG;

@@ -32,6 +32,7 @@
 // The unknown counts inside the variance formulas are replaced by the estimates;
 // reported variances are clamped at zero.
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 #include "internal.h"
@@ -203,4 +204,54 @@ extern "C" moss_status moss_finals(moss_result* r) {
     return MOSS_OK;
   }
   return MOSS_E_ARG;
+}
+
+namespace {
+
+// Two-sided normal quantile (Theorem 1's limit): the z with erfc(z / sqrt 2) = delta,
+// by halving [0, 40] 200 times; erfc falls monotonically, so the root stays inside.
+double two_sided_quantile(double delta) {
+  double lo = 0.0, hi = 40.0;
+  const double r2 = std::sqrt(2.0);
+  for (int it = 0; it < 200; ++it) {
+    const double mid = lo + (hi - lo) / 2.0;
+    if (std::erfc(mid / r2) > delta) lo = mid;
+    else hi = mid;
+  }
+  return (lo + hi) / 2.0;
+}
+
+}  // namespace
+
+extern "C" moss_status moss_plan_budget(const moss_result* pilot, double eps, double delta, uint32_t motif_mask,
+                                        uint64_t budget[21], uint64_t* max_budget) {
+  if (!pilot || !budget || !max_budget || !(eps > 0.0) || !(delta > 0.0) || !(delta < 1.0)) return MOSS_E_ARG;
+  if (pilot->n_motifs != 6 && pilot->n_motifs != 21) return MOSS_E_ARG;
+  const double z = two_sided_quantile(delta);
+  const double Kp = (double)(pilot->K[0] + pilot->K[1]);
+  uint64_t best = 0;
+  for (int i = 0; i < 21; ++i) {
+    budget[i] = 0;
+    const double e = pilot->estimate[i];
+    if (i >= pilot->n_motifs || !(e > 0.0)) continue;
+    // K_i from Var_i(K) = Var_i(K_p) K_p / K and z sqrt(Var_i(K)) <= eps e
+    const double num = z * z * pilot->variance[i] * Kp;
+    const double den = eps * eps * e * e;
+    const double x = num / den;
+    uint64_t Ki = 1;
+    if (x >= 18446744073709549568.0) Ki = UINT64_MAX;  // largest double below 2^64
+    else if (x > 1.0) Ki = (uint64_t)std::ceil(x);
+    budget[i] = Ki;
+    if ((motif_mask == 0 || ((motif_mask >> i) & 1u)) && Ki > best) best = Ki;
+  }
+  *max_budget = best;
+  return MOSS_OK;
+}
+
+extern "C" moss_status moss_concentrations(const moss_result* r, double omega[21]) {
+  if (!r || !omega || (r->n_motifs != 6 && r->n_motifs != 21)) return MOSS_E_ARG;
+  double sum = 0.0;
+  for (int i = 0; i < r->n_motifs; ++i) sum += r->estimate[i];
+  for (int i = 0; i < 21; ++i) omega[i] = (i < r->n_motifs && sum != 0.0) ? r->estimate[i] / sum : 0.0;
+  return MOSS_OK;
 }

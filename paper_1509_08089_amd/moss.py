@@ -40,6 +40,7 @@ EXPORTED = [
     "moss_sample_nodes", "moss_class_lut", "moss_finals", "moss_estimate_batch", "moss_set_tuning",
     "moss_get_tuning", "moss_autotune", "moss_server_create", "moss_server_add_graph", "moss_server_submit",
     "moss_server_wait", "moss_server_cancel", "moss_server_stats_get", "moss_server_destroy",
+    "moss_plan_budget", "moss_estimate_to_precision", "moss_concentrations",
 ]
 
 
@@ -127,6 +128,11 @@ def lib():
             "moss_sample_nodes": ([P, i32, u64, P, i64, P, P], ctypes.c_int),
             "moss_class_lut": ([i32, P, i32], ctypes.c_int),
             "moss_finals": ([ctypes.POINTER(moss_result)], ctypes.c_int),
+            "moss_plan_budget": ([ctypes.POINTER(moss_result), ctypes.c_double, ctypes.c_double, u32, P,
+                                  ctypes.POINTER(u64)], ctypes.c_int),
+            "moss_estimate_to_precision": ([P, i32, ctypes.c_double, ctypes.c_double, u32, u64, u64, u64, u64, u32,
+                                            ctypes.POINTER(moss_result)], ctypes.c_int),
+            "moss_concentrations": ([ctypes.POINTER(moss_result), P], ctypes.c_int),
             "moss_estimate_batch": ([P, i32, P, P], ctypes.c_int),
             "moss_set_tuning": ([ctypes.POINTER(moss_tuning)], ctypes.c_int),
             "moss_get_tuning": ([ctypes.POINTER(moss_tuning)], ctypes.c_int),
@@ -242,6 +248,29 @@ def moss_class_lut(sampler: int) -> np.ndarray:
 def moss_finals(r: moss_result) -> moss_result:
     _check(lib().moss_finals(ctypes.byref(r)), "moss_finals")
     return r
+
+
+def moss_plan_budget(pilot: moss_result, eps: float, delta: float, motif_mask: int = 0):
+    """(per-motif budgets, largest over the mask)."""
+    b = np.zeros(21, np.uint64)
+    mx = ctypes.c_uint64()
+    _check(lib().moss_plan_budget(ctypes.byref(pilot), eps, delta, motif_mask, _hptr(b), ctypes.byref(mx)),
+           "moss_plan_budget")
+    return b[: pilot.n_motifs], int(mx.value)
+
+
+def moss_estimate_to_precision(g, k: int, eps: float, delta: float, motif_mask: int, pilot_samples: int,
+                               pilot_seed: int, max_samples: int, seed: int, flags: int = 0) -> moss_result:
+    r = moss_result()
+    _check(lib().moss_estimate_to_precision(g, k, eps, delta, motif_mask, pilot_samples, pilot_seed, max_samples,
+                                            seed, flags, ctypes.byref(r)), "moss_estimate_to_precision")
+    return r
+
+
+def moss_concentrations(r: moss_result) -> np.ndarray:
+    out = np.zeros(21)
+    _check(lib().moss_concentrations(ctypes.byref(r), _hptr(out)), "moss_concentrations")
+    return out[: r.n_motifs]
 
 
 def moss_estimate_batch(requests, stream=None):
@@ -376,6 +405,11 @@ class Graph:
 
     def estimate(self, k: int, n_samples: int, seed: int, flags: int = 0) -> moss_result:
         return moss_estimate(self.h, k, n_samples, seed, flags)
+
+    def estimate_to_precision(self, k: int, eps: float, delta: float, motif_mask: int, pilot_samples: int,
+                              pilot_seed: int, max_samples: int, seed: int, flags: int = 0) -> moss_result:
+        return moss_estimate_to_precision(self.h, k, eps, delta, motif_mask, pilot_samples, pilot_seed, max_samples,
+                                          seed, flags)
 
     def sample_range(self, sampler: int, seed: int, k0: int, k1: int, class_out=None) -> np.ndarray:
         return moss_sample_range(self.h, sampler, seed, k0, k1, class_out)

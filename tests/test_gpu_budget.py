@@ -1,0 +1,39 @@
+"""Pilot-then-final estimates on the GPU against the oracle's (calls through the C ABI):
+the planned budget is identical, the final hits bit-exact, finals and concentrations
+within 1e-12."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import assert_result_matches
+from paper_1509_08089_amd import moss
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(4, 0), (5, 0), (4, moss.MOSS_K4_MIN), (4, moss.MOSS_K4_MIN | moss.MOSS_MIX_PAPER), (5, moss.MOSS_MIX_PAPER)]
+
+
+@pytest.mark.parametrize("k,flags", CASES)
+@pytest.mark.parametrize("eps,delta,mask,cap", [(0.02, 0.05, 0b101, 10**12), (0.01, 0.01, 0, 300_001),
+                                                (0.05, 0.2, 1 << 20, 10**9)])
+def test_estimate_to_precision_matches_oracle(k, flags, eps, delta, mask, cap):
+    g = gg.config_graph("C1")
+    G, og = moss.Graph(g), oracle.Graph(g)
+    with_min = bool(flags & moss.MOSS_K4_MIN)
+    mix = flags & moss.MOSS_MIX_PAPER
+    r = G.estimate_to_precision(k, eps, delta, mask, 40_000, 9, cap, 4, flags)
+    o, K = og.estimate_to_precision(k, eps, delta, mask, 40_000, 9, cap, 4, with_min, mix, threads=8)
+    assert r.n_samples == K
+    lam = og.totals()["lambda3" if k == 4 else "lambda4"]
+    assert_result_matches(r, o, float(lam))
+    np.testing.assert_allclose(moss.moss_concentrations(r), oracle.concentrations(o), rtol=1e-11, atol=1e-15)
+
+
+def test_estimate_to_precision_rejects_bad_arguments():
+    G = moss.Graph(gg.gnp(12, 0.4, 1))
+    for args in ((4, 0.0, 0.1, 0, 100, 1, 1000, 2, 0), (4, 0.1, 1.0, 0, 100, 1, 1000, 2, 0),
+                 (5, 0.1, 0.1, 0, 1, 1, 1000, 2, 0), (5, 0.1, 0.1, 0, 100, 1, 1000, 2, moss.MOSS_K4_MIN),
+                 (4, 0.1, 0.1, 0, 100, 1, 1, 2, moss.MOSS_K4_MIN)):
+        with pytest.raises(moss.MossError):
+            G.estimate_to_precision(*args)

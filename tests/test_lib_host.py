@@ -134,6 +134,43 @@ def test_finals4_min_match_oracle(seed, mix):
         assert _rel_close(r.variance[i], var[i], 0.0, 1e-11), (i, r.variance[i], var[i])
 
 
+def _pilot_pair(rng, n_motifs):
+    """The same pilot result as the library's struct and the oracle's."""
+    est = rng.lognormal(8, 3, n_motifs) * (rng.random(n_motifs) < 0.8)
+    est[rng.random(n_motifs) < 0.1] *= -1
+    var = rng.lognormal(10, 4, n_motifs) * (rng.random(n_motifs) < 0.9)
+    K = [int(rng.integers(1, 10**9)), int(rng.integers(0, 10**9)) if n_motifs == 21 else 0]
+    r = moss.moss_result()
+    o = oracle._Result()
+    for x in (r, o):
+        x.k, x.n_motifs = (4, 6) if n_motifs == 6 else (5, 21)
+        x.K[0], x.K[1] = K
+        for i in range(n_motifs):
+            x.estimate[i], x.variance[i] = float(est[i]), float(var[i])
+    return r, oracle.Result(o)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_plan_budget_matches_oracle(seed):
+    rng = np.random.Generator(np.random.PCG64(500 + seed))
+    r, o = _pilot_pair(rng, 6 if seed % 2 else 21)
+    eps = float(10 ** rng.uniform(-3, -0.5))
+    delta = float(10 ** rng.uniform(-8, -0.1))
+    mask = int(rng.integers(0, 1 << 21)) if seed % 3 else 0
+    b, mx = moss.moss_plan_budget(r, eps, delta, mask)
+    ob, omx = oracle.plan_budget(o, eps, delta, mask)
+    np.testing.assert_array_equal(b, ob)
+    assert mx == omx
+    np.testing.assert_allclose(moss.moss_concentrations(r), oracle.concentrations(o), rtol=1e-14, atol=0)
+
+
+def test_plan_budget_rejects_bad_arguments():
+    r, _ = _pilot_pair(np.random.Generator(np.random.PCG64(1)), 6)
+    for eps, delta in ((0.0, 0.1), (-1.0, 0.1), (0.1, 0.0), (0.1, 1.0), (float("nan"), 0.1)):
+        with pytest.raises(moss.MossError):
+            moss.moss_plan_budget(r, eps, delta)
+
+
 def test_finals_reject_bad_arguments():
     r = moss.moss_result()
     r.k = 3
