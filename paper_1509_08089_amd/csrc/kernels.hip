@@ -560,14 +560,26 @@ hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStr
 // node by degree, then id: with key(x) = d_x * 2^32 + x, x is above y exactly when
 // key(x) > key(y).  d_{v,x} = |{y in N_v : y above x}| is then x's place in row v
 // sorted by key, largest first, and col_rank lists the row in that order, so that
-// N_{v,x} is its first d_{v,x} entries.  Three passes over the work items:
-//   local   each piece ranks its entries among themselves: every lane compares its keys
-//           with each key of the piece, broadcast from the lane that holds it.  A row
-//           of one piece is finished here; a longer row's piece writes its keys in
-//           descending order (scratch) and its local ranks
-//   merge   each entry of a longer row adds the keys above it in the row's other
-//           pieces (a binary search of each piece's sorted keys)
-//   mirror  d_{x,v} is read at the entry (x, v), found by a binary search of row x
+// N_{v,x} is its first d_{v,x} entries.  The passes over the work items:
+//   local    each piece ranks its entries among themselves, one wave per piece: every
+//            lane compares its keys with each key of the piece, broadcast from the lane
+//            that holds it (a bitonic sort of the piece in LDS by a block of 256 threads
+//            measured slower: it spends more instructions in all, 0.87 against 0.78 ms
+//            at n = 1e6, m = 1e7).  A row of one piece is finished here; a longer row's
+//            piece writes its keys in descending order (scratch) and its local ranks
+//   merge    one block per piece of a longer row: the row's other pieces' sorted keys
+//            go through LDS, eight pieces at a time, and each thread adds the keys
+//            above its entry (a binary search in LDS)
+//   mirror   d_{x,v} is read at the entry (x, v), found by a binary search of row x
+//            (the upper levels of the searches in a hub row are shared and stay cached;
+//            exchanging the ranks through the edge hash set's slots measured only 15%
+//            faster at n = 1e6, m = 1e7, for a scratch block the size of the set, and
+//            running a lane's four searches side by side 14% slower: the pass is bound
+//            by the L2's request rate, not by latency)
+// Equal keys (a repeated neighbour, possible only in an unchecked CSR) are ranked by
+// their place in the row, so the ranks of a row are always a permutation of 0..d-1 and
+// every place of col_rank is written exactly once.  A missing mirror (also only in an
+// unchecked CSR) reads as rank 0, so the entry gets weight 0.
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t order_key(const uint4* __restrict__ rec, int32_t x) {
   return ((uint64_t)row_of(rec, x).y << 32) | (uint64_t)(uint32_t)x;
@@ -605,8 +617,10 @@ __global__ __launch_bounds__(256) void k_rank_local(int64_t n_items, const uint6
       const int lim = min(64, len - c2 * 64);
       for (int j = 0; j < lim; ++j) {
         const uint64_t kj = readlane64(k[c2], j);
+        const int pj = c2 * 64 + j;  // its place in the piece
 #pragma unroll
-        for (int c = 0; c < kItem / 64; ++c) above[c] += kj > k[c] ? 1u : 0u;
+        for (int c = 0; c < kItem / 64; ++c)
+          above[c] += (kj > k[c] || (kj == k[c] && pj < c * 64 + lane)) ? 1u : 0u;
       }
     }
 #pragma unroll
@@ -620,31 +634,49 @@ __global__ __launch_bounds__(256) void k_rank_local(int64_t n_items, const uint6
   }
 }
 
+constexpr int kMergeBatch = 8;  // pieces staged in LDS at a time
+
 __global__ __launch_bounds__(256) void k_rank_merge(int64_t n_items, const uint64_t* __restrict__ items,
                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                     const uint4* __restrict__ rec, const uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
-  const int lane = lane_id();
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
+  __shared__ uint64_t sk[kMergeBatch][kItem];
+  const int tid = threadIdx.x;  // blockDim.x == kItem: one thread per entry of the piece
+  for (int64_t i = blockIdx.x; i < n_items; i += gridDim.x) {  // block-uniform
     const ItemRange it = item_range(items, rp, i);
     if (it.e0 == it.r0 && it.e1 == it.r1) continue;  // finished by k_rank_local
     const int32_t pieces = (it.r1 - it.r0 + kItem - 1) / kItem;
-    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
-      const int32_t x = col[e];
-      const uint64_t key = order_key(rec, x);
-      uint32_t r = rank32[2 * (int64_t)e];
-      for (int32_t p = 0; p < pieces; ++p) {
-        if (p == it.piece) continue;
-        const int32_t q0 = it.r0 + p * kItem, q1 = min(it.r1, q0 + kItem);
-        int32_t lo = q0, hi = q1;  // first place whose key is not above `key`
+    const int32_t e = it.e0 + tid;
+    const bool in = e < it.e1;
+    const int32_t x = in ? col[e] : 0;
+    const uint64_t key = in ? order_key(rec, x) : 0ull;
+    uint32_t r = in ? rank32[2 * (int64_t)e] : 0u;
+    for (int32_t p0 = 0; p0 < pieces; p0 += kMergeBatch) {
+      __syncthreads();  // the previous batch's searches are done
+#pragma unroll
+      for (int j = 0; j < kMergeBatch; ++j) {
+        const int32_t q0 = it.r0 + (p0 + j) * kItem;
+        if (p0 + j < pieces && q0 + tid < it.r1) sk[j][tid] = keys[q0 + tid];
+      }
+      __syncthreads();
+      if (!in) continue;
+#pragma unroll
+      for (int j = 0; j < kMergeBatch; ++j) {
+        const int32_t p = p0 + j;
+        if (p >= pieces || p == it.piece) continue;
+        const int32_t len = min(it.r1 - (it.r0 + p * kItem), kItem);
+        const bool earlier = p < it.piece;  // its equal keys come first
+        int32_t lo = 0, hi = len;  // first place whose key does not come before `key`
         while (lo < hi) {
-          const int32_t mid = lo + ((hi - lo) >> 1);
-          if (keys[mid] > key) lo = mid + 1;
+          const int32_t mid = (lo + hi) >> 1;
+          const uint64_t km = sk[j][mid];
+          if (km > key || (earlier && km == key)) lo = mid + 1;
           else hi = mid;
         }
-        r += (uint32_t)(lo - q0);
+        r += (uint32_t)lo;
       }
+    }
+    if (in) {
       rank32[2 * (int64_t)e] = r;
       col_rank[it.r0 + (int32_t)r] = x;
     }
@@ -679,7 +711,9 @@ hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, const int3
   const dim3 grid(item_grid(n_items)), block(256);
   uint32_t* rank32 = reinterpret_cast<uint32_t*>(rank);
   hipLaunchKernelGGL(k_rank_local, grid, block, 0, s, n_items, items, rp, col, rec, keys, rank32, col_rank);
-  hipLaunchKernelGGL(k_rank_merge, grid, block, 0, s, n_items, items, rp, col, rec, keys, rank32, col_rank);
+  const int merge_grid = (int)std::min<int64_t>(n_items, 65536);
+  hipLaunchKernelGGL(k_rank_merge, dim3(merge_grid), dim3(kItem), 0, s, n_items, items, rp, col, rec, keys, rank32,
+                     col_rank);
   hipLaunchKernelGGL(k_rank_mirror, grid, block, 0, s, n_items, items, rp, col, rec, rank32);
   return hipGetLastError();
 }
