@@ -21,6 +21,7 @@
 // All counting is integer; a sample's outcome depends only on (graph, seed, sampler,
 // sample index), never on which lane, block or launch draws it.
 #include <algorithm>
+#include <type_traits>
 
 #include "device.h"
 #include "kernels.h"
@@ -1320,11 +1321,13 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
 constexpr int kXcds = 8;
 constexpr int kSortBits = 8;
 constexpr int kSortGroups = 1 << kSortBits;
+using SortGroup = std::conditional_t<(kSortBits <= 8), uint8_t, uint16_t>;  // a sample's group
+static_assert(kSortGroups % 256 == 0 && kSortBits <= 16, "whole groups per scatter thread");
 constexpr uint32_t kSortSpan = 8192;   // samples per block of the counting passes
 constexpr uint32_t kSortWindow = 2048; // sorted entries a block takes per cursor step
 
 struct SortScratch {
-  uint8_t* group;     // n: group of each sample
+  SortGroup* group;   // n: group of each sample
   uint32_t* order;    // n: sample offsets sorted by group
   uint64_t* counts;   // kSortGroups * nblk: per (group, block) counts, then inclusive prefix
   uint64_t* tmp;      // scan block sums
@@ -1343,7 +1346,7 @@ static SortScratch sort_scratch(void* base, uint64_t max_n) {
   };
   t.nblk = (uint32_t)((max_n + kSortSpan - 1) / kSortSpan);
   if (t.nblk == 0) t.nblk = 1;
-  t.group = reinterpret_cast<uint8_t*>(take(max_n));
+  t.group = reinterpret_cast<SortGroup*>(take(max_n * sizeof(SortGroup)));
   t.order = reinterpret_cast<uint32_t*>(take(max_n * 4));
   t.counts = reinterpret_cast<uint64_t*>(take((size_t)kSortGroups * t.nblk * 8));
   t.tmp = reinterpret_cast<uint64_t*>(take((size_t)scan_tmp_elems((int64_t)kSortGroups * t.nblk) * 8));
@@ -1355,7 +1358,7 @@ static SortScratch sort_scratch(void* base, uint64_t max_n) {
 int64_t grouped_scratch_bytes(uint64_t max_n) {
   const uint64_t nblk = std::max<uint64_t>(1, (max_n + kSortSpan - 1) / kSortSpan);
   auto r = [](uint64_t b) { return (b + 255) / 256 * 256; };
-  return (int64_t)(r(max_n) + r(max_n * 4) + r(kSortGroups * nblk * 8) +
+  return (int64_t)(r(max_n * sizeof(SortGroup)) + r(max_n * 4) + r(kSortGroups * nblk * 8) +
                    r((uint64_t)scan_tmp_elems((int64_t)(kSortGroups * nblk)) * 8) + r(kXcds * 4) + r(4) + 256);
 }
 
@@ -1374,7 +1377,7 @@ __global__ __launch_bounds__(256) void k_sort_count(uint64_t seed, uint64_t k0, 
     uint64_t W[4];
     philox_block(k0 + i, 0, seed, S, W);
     const uint32_t g = (uint32_t)(W[0] >> (64 - kSortBits));
-    t.group[i] = (uint8_t)g;
+    t.group[i] = (SortGroup)g;
     atomicAdd(&hist[g], 1u);
   }
   __syncthreads();
@@ -1386,43 +1389,51 @@ __global__ __launch_bounds__(256) void k_sort_count(uint64_t seed, uint64_t k0, 
 // the block's share of g in the sorted order: consecutive threads write consecutive
 // slots, so the stores coalesce (slot order within a share is immaterial).
 __global__ __launch_bounds__(256) void k_sort_scatter(uint64_t n, SortScratch t) {
-  __shared__ uint64_t base[kSortGroups];   // per group: the block's share in the sorted order
+  constexpr int kPerThread = kSortGroups / 256;  // thread tid owns groups tid * kPerThread ..
+  __shared__ uint32_t base[kSortGroups];   // per group: the block's share in the sorted order
   __shared__ uint32_t start[kSortGroups];  // per group: the run's start in the local order
   __shared__ uint32_t next[kSortGroups];   // per group: the run's fill cursor
-  __shared__ uint32_t wsum[kSortGroups / 64];
+  __shared__ uint32_t wsum[4];
   __shared__ uint32_t local[kSortSpan];    // span offsets sorted by group
-  __shared__ uint8_t grp[kSortSpan];
-  static_assert(kSortGroups == 256, "one thread per group");
-  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+  __shared__ SortGroup grp[kSortSpan];
+  const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;  // blockDim.x == 256
   const uint64_t lo = (uint64_t)blockIdx.x * kSortSpan;
   const uint32_t len = (uint32_t)(n < lo + kSortSpan ? n - lo : kSortSpan);
-  // the block's share of group tid: [inclusive count before it, its inclusive count)
-  uint32_t size = 0;
-  if (tid < kSortGroups) {
-    const uint64_t idx = (uint64_t)tid * t.nblk + blockIdx.x;
+  // the block's share of each of this thread's groups: [inclusive count before it, its
+  // inclusive count) (a chunk has at most 2^31 samples, so the places fit 32 bits)
+  uint32_t size[kPerThread];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    const uint32_t g = (uint32_t)tid * kPerThread + j;
+    const uint64_t idx = (uint64_t)g * t.nblk + blockIdx.x;
     const uint64_t before = idx ? t.counts[idx - 1] : 0;
-    base[tid] = before;
-    size = (uint32_t)(t.counts[idx] - before);
+    base[g] = (uint32_t)before;
+    size[j] = (uint32_t)(t.counts[idx] - before);
+    mine += size[j];
   }
   for (uint32_t j = tid; j < len; j += blockDim.x) grp[j] = t.group[lo + j];
-  // exclusive prefix of the 256 share sizes: local run starts
+  // exclusive prefix of the share sizes in group order: local run starts
   bool unused = false;
-  const uint32_t incl = (uint32_t)wave_inclusive_scan((uint64_t)size, unused);
+  const uint32_t incl = (uint32_t)wave_inclusive_scan((uint64_t)mine, unused);
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  if (tid < kSortGroups) {
-    uint32_t off = 0;
-    for (int w = 0; w < wave; ++w) off += wsum[w];
-    start[tid] = off + incl - size;
-    next[tid] = off + incl - size;
+  uint32_t off = incl - mine;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+#pragma unroll
+  for (int j = 0; j < kPerThread; ++j) {
+    const uint32_t g = (uint32_t)tid * kPerThread + j;
+    start[g] = off;
+    next[g] = off;
+    off += size[j];
   }
   __syncthreads();
   for (uint32_t j = tid; j < len; j += blockDim.x) local[atomicAdd(&next[grp[j]], 1u)] = j;
   __syncthreads();
   for (uint32_t j = tid; j < len; j += blockDim.x) {
-    const uint32_t off = local[j];
-    const uint32_t g = grp[off];
-    t.order[base[g] + (j - start[g])] = (uint32_t)(lo + off);
+    const uint32_t o = local[j];
+    const uint32_t g = grp[o];
+    t.order[(uint64_t)base[g] + (j - start[g])] = (uint32_t)(lo + o);
   }
 }
 
