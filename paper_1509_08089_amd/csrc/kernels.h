@@ -176,13 +176,18 @@ hipError_t launch_guides(const GuideSet& set, int32_t n, int gbits, hipStream_t 
 hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
                          unsigned long long* hits, uint8_t* class_out, int grid, int block, hipStream_t s);
 
-// The same samples drawn XCD-grouped: `scratch` holds grouped_scratch_bytes(max_n)
-// bytes (per sample a group byte and a sorted offset, per-block group counts, cursors);
-// chunks of at most max_n <= 2^31 samples.  block must be 64, 128, 192 or 256 threads.
+// The same samples drawn XCD-grouped, one chunk [a, a + n) at a time (n <= max_n <=
+// 2^31): the grouping passes (group of each sample, per-block group counts, their scan,
+// the sorted order) into `scratch`, which holds grouped_scratch_bytes(max_n) bytes, then
+// the sampling launch that reads them.  The two may run on different streams, ordered by
+// events; a scratch block serves one chunk at a time.  block must be 64, 128, 192 or 256
+// threads; class_out (may be null) receives the chunk's classes at [0, n).
 int64_t grouped_scratch_bytes(uint64_t max_n);
-hipError_t launch_sample_grouped(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
-                                 unsigned long long* hits, uint8_t* class_out, void* scratch, uint64_t max_n,
-                                 int grid, int block, hipStream_t s);
+hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n, void* scratch, uint64_t max_n,
+                              hipStream_t s);
+hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed, uint64_t a, uint64_t n,
+                               void* scratch, uint64_t max_n, unsigned long long* hits, uint8_t* class_out, int grid,
+                               int block, hipStream_t s);
 
 hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed, const uint64_t* index,
                                int64_t count, int32_t* nodes_out, uint8_t* class_out, hipStream_t s);

@@ -1479,57 +1479,57 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
   }
 }
 
-hipError_t launch_sample_grouped(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
-                                 unsigned long long* hits, uint8_t* class_out, void* scratch, uint64_t max_n,
-                                 int grid, int block, hipStream_t s) {
-  if (block != 64 * (block / 64) || block > 256 || block < 64 || max_n == 0 || max_n > (1ull << 31))
-    return hipErrorInvalidValue;
-  const SortScratch t = sort_scratch(scratch, max_n);
-  for (uint64_t a = k0; a < k1;) {
-    const uint64_t b = k1 - a > max_n ? a + max_n : k1;
-    const uint64_t n = b - a;
-    const uint32_t nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
-    SortScratch tc = t;
-    tc.nblk = nblk;
-    uint8_t* co = class_out ? class_out + (a - k0) : nullptr;
-    switch (sampler) {
-      case kMoss4: hipLaunchKernelGGL(k_sort_count<kMoss4>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
-      case kMoss4Min: hipLaunchKernelGGL(k_sort_count<kMoss4Min>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
-      case kT5: hipLaunchKernelGGL(k_sort_count<kT5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
-      case kPath5: hipLaunchKernelGGL(k_sort_count<kPath5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
-      default: return hipErrorInvalidValue;
-    }
-    ScanSet set{};
-    set.data[0] = tc.counts;
-    set.tmp[0] = tc.tmp;
-    set.err_bit[0] = 0;
-    set.count = 1;
-    hipError_t e = launch_scans(set, (int64_t)kSortGroups * nblk, tc.err, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(256), 0, s, n, tc);
-    // no more blocks than windows (each block visits every cursor once at least), a
-    // multiple of the XCD count so that every XCD gets its share of blocks
-    const uint64_t wins = (n + kSortWindow - 1) / kSortWindow;
-    const int g = (int)std::min<uint64_t>((uint64_t)grid, std::max<uint64_t>(kXcds, (wins + kXcds - 1) / kXcds * kXcds));
-    switch (sampler) {
-      case kMoss4:
-        hipLaunchKernelGGL(k_sample_sorted<kMoss4>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
-        break;
-      case kMoss4Min:
-        hipLaunchKernelGGL(k_sample_sorted<kMoss4Min>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
-        break;
-      case kT5:
-        hipLaunchKernelGGL(k_sample_sorted<kT5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
-        break;
-      default:
-        hipLaunchKernelGGL(k_sample_sorted<kPath5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, co);
-        break;
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    a = b;
+hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n, void* scratch, uint64_t max_n,
+                              hipStream_t s) {
+  if (n == 0 || n > max_n || max_n > (1ull << 31)) return hipErrorInvalidValue;
+  SortScratch tc = sort_scratch(scratch, max_n);
+  tc.nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
+  const uint32_t nblk = tc.nblk;
+  switch (sampler) {
+    case kMoss4: hipLaunchKernelGGL(k_sort_count<kMoss4>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
+    case kMoss4Min: hipLaunchKernelGGL(k_sort_count<kMoss4Min>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
+    case kT5: hipLaunchKernelGGL(k_sort_count<kT5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
+    case kPath5: hipLaunchKernelGGL(k_sort_count<kPath5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
+    default: return hipErrorInvalidValue;
   }
-  return hipSuccess;
+  ScanSet set{};
+  set.data[0] = tc.counts;
+  set.tmp[0] = tc.tmp;
+  set.err_bit[0] = 0;
+  set.count = 1;
+  hipError_t e = launch_scans(set, (int64_t)kSortGroups * nblk, tc.err, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(256), 0, s, n, tc);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed, uint64_t a, uint64_t n,
+                               void* scratch, uint64_t max_n, unsigned long long* hits, uint8_t* class_out, int grid,
+                               int block, hipStream_t s) {
+  if (block != 64 * (block / 64) || block > 256 || block < 64 || n == 0 || n > max_n || max_n > (1ull << 31))
+    return hipErrorInvalidValue;
+  SortScratch tc = sort_scratch(scratch, max_n);
+  tc.nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
+  // no more blocks than windows (each block visits every cursor once at least), a
+  // multiple of the XCD count so that every XCD gets its share of blocks
+  const uint64_t wins = (n + kSortWindow - 1) / kSortWindow;
+  const int g = (int)std::min<uint64_t>((uint64_t)grid, std::max<uint64_t>(kXcds, (wins + kXcds - 1) / kXcds * kXcds));
+  switch (sampler) {
+    case kMoss4:
+      hipLaunchKernelGGL(k_sample_sorted<kMoss4>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      break;
+    case kMoss4Min:
+      hipLaunchKernelGGL(k_sample_sorted<kMoss4Min>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      break;
+    case kT5:
+      hipLaunchKernelGGL(k_sample_sorted<kT5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      break;
+    case kPath5:
+      hipLaunchKernelGGL(k_sample_sorted<kPath5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int S>
