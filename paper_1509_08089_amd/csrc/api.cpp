@@ -908,6 +908,7 @@ moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0,
       return MOSS_E_NOMEM;
   }
   // (with a scratch block, every launch below runs grouped; chunks of at most max_n)
+  const uint32_t window = sort_window(sampling_footprint(g));
   hipError_t e = launch_fill_u64(g->small + kWHits, 0, 2 * 22, s);
   if (e == hipSuccess) e = hipEventRecord(g->ev0, s);
   for (int i = 0; i < count && e == hipSuccess; ++i) {
@@ -924,7 +925,7 @@ moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0,
       const uint64_t n = std::min<uint64_t>(max_n, k1[i] - a);
       e = launch_group_chunk(samplers[i], seed, a, n, scratch, max_n, s);
       if (e == hipSuccess)
-        e = launch_sample_chunk(samplers[i], view, seed, a, n, scratch, max_n, d_hits + 22 * i,
+        e = launch_sample_chunk(samplers[i], view, seed, a, n, scratch, max_n, window, d_hits + 22 * i,
                                 class_out ? class_out + (a - k0[i]) : nullptr, grid, block, s);
     }
   }

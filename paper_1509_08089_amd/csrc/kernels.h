@@ -182,12 +182,15 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
 // the sampling launch that reads them.  The two may run on different streams, ordered by
 // events; a scratch block serves one chunk at a time.  block must be 64, 128, 192 or 256
 // threads; class_out (may be null) receives the chunk's classes at [0, n).
+// `window`: sorted entries a block takes at a time (sort_window of the bytes the
+// samples read at random).
 int64_t grouped_scratch_bytes(uint64_t max_n);
+uint32_t sort_window(uint64_t footprint_bytes);
 hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n, void* scratch, uint64_t max_n,
                               hipStream_t s);
 hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed, uint64_t a, uint64_t n,
-                               void* scratch, uint64_t max_n, unsigned long long* hits, uint8_t* class_out, int grid,
-                               int block, hipStream_t s);
+                               void* scratch, uint64_t max_n, uint32_t window, unsigned long long* hits,
+                               uint8_t* class_out, int grid, int block, hipStream_t s);
 
 hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed, const uint64_t* index,
                                int64_t count, int32_t* nodes_out, uint8_t* class_out, hipStream_t s);

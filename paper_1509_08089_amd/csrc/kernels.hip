@@ -1324,7 +1324,14 @@ constexpr int kSortGroups = 1 << kSortBits;
 using SortGroup = std::conditional_t<(kSortBits <= 8), uint8_t, uint16_t>;  // a sample's group
 static_assert(kSortGroups % 256 == 0 && kSortBits <= 16, "whole groups per scatter thread");
 constexpr uint32_t kSortSpan = 8192;   // samples per block of the counting passes
-constexpr uint32_t kSortWindow = 2048; // sorted entries a block takes per cursor step
+// Sorted entries a block takes per cursor step: 2048 while the sampled tables fit the
+// MALL, 512 beyond it.  Smaller windows keep the blocks of an XCD closer together in
+// the sorted order, so that they share more of their tables' lines in the L2; past the
+// MALL that matters most (n = 1e6, m = 1e7: T-5 / Path-5 for 5e7 samples each 6.18 /
+// 9.38 ms at 2048, 5.94 / 8.48 ms at 512, 5.94 / 8.37 at 256, 7.58 / 10.6 at 128),
+// while within it the extra cursor steps cost a little (n = 1e5, m = 1e6, MOSS-4
+// for 1e7 samples: 0.673 ms at 2048, 0.684 at 512, 0.725 at 256).
+uint32_t sort_window(uint64_t footprint_bytes) { return footprint_bytes > (256ull << 20) ? 512u : 2048u; }
 
 struct SortScratch {
   SortGroup* group;   // n: group of each sample
@@ -1439,7 +1446,8 @@ __global__ __launch_bounds__(256) void k_sort_scatter(uint64_t n, SortScratch t)
 
 template <int S>
 __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_t seed, uint64_t k0, uint64_t n,
-                                                       SortScratch t, unsigned long long* __restrict__ hits,
+                                                       SortScratch t, uint32_t window,
+                                                       unsigned long long* __restrict__ hits,
                                                        uint8_t* __restrict__ class_out) {
   __shared__ uint32_t bins[kMaxWaves][kBins + 2];
   __shared__ uint8_t lut[64];
@@ -1459,10 +1467,10 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
     for (;;) {
       if (tid == 0) s_win = atomicAdd(&t.cursors[x], 1u);
       __syncthreads();
-      const uint64_t p = lo + (uint64_t)s_win * kSortWindow;
+      const uint64_t p = lo + (uint64_t)s_win * window;
       __syncthreads();
       if (p >= hi) break;
-      const uint64_t q = hi < p + kSortWindow ? hi : p + kSortWindow;
+      const uint64_t q = hi < p + window ? hi : p + window;
       for (uint64_t j = p + tid; j < q; j += blockDim.x) {
         const uint64_t i = t.order[j];
         const int c = draw<S>(a, lut, seed, k0 + i, nullptr);
@@ -1504,28 +1512,33 @@ hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n
 }
 
 hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed, uint64_t a, uint64_t n,
-                               void* scratch, uint64_t max_n, unsigned long long* hits, uint8_t* class_out, int grid,
-                               int block, hipStream_t s) {
-  if (block != 64 * (block / 64) || block > 256 || block < 64 || n == 0 || n > max_n || max_n > (1ull << 31))
+                               void* scratch, uint64_t max_n, uint32_t window, unsigned long long* hits,
+                               uint8_t* class_out, int grid, int block, hipStream_t s) {
+  if (block != 64 * (block / 64) || block > 256 || block < 64 || n == 0 || n > max_n || max_n > (1ull << 31) ||
+      window == 0)
     return hipErrorInvalidValue;
   SortScratch tc = sort_scratch(scratch, max_n);
   tc.nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
   // no more blocks than windows (each block visits every cursor once at least), a
   // multiple of the XCD count so that every XCD gets its share of blocks
-  const uint64_t wins = (n + kSortWindow - 1) / kSortWindow;
+  const uint64_t wins = (n + window - 1) / window;
   const int g = (int)std::min<uint64_t>((uint64_t)grid, std::max<uint64_t>(kXcds, (wins + kXcds - 1) / kXcds * kXcds));
   switch (sampler) {
     case kMoss4:
-      hipLaunchKernelGGL(k_sample_sorted<kMoss4>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      hipLaunchKernelGGL(k_sample_sorted<kMoss4>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, window, hits,
+                         class_out);
       break;
     case kMoss4Min:
-      hipLaunchKernelGGL(k_sample_sorted<kMoss4Min>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      hipLaunchKernelGGL(k_sample_sorted<kMoss4Min>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, window, hits,
+                         class_out);
       break;
     case kT5:
-      hipLaunchKernelGGL(k_sample_sorted<kT5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      hipLaunchKernelGGL(k_sample_sorted<kT5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, window, hits,
+                         class_out);
       break;
     case kPath5:
-      hipLaunchKernelGGL(k_sample_sorted<kPath5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, hits, class_out);
+      hipLaunchKernelGGL(k_sample_sorted<kPath5>, dim3(g), dim3(block), 0, s, v, seed, a, n, tc, window, hits,
+                         class_out);
       break;
     default: return hipErrorInvalidValue;
   }
