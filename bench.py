@@ -15,6 +15,10 @@ Also reported on the same JSON line:
                 duration from HIP events on the stream it runs on, against 8 TB/s
   cpu_baseline  the oracle's sampling loop timed on the host cores on a bounded
                 prefix of the same sample stream
+  gather        the dependent random-gather ceiling over a buffer of the samplers'
+                footprint (libmoss_probe.so, best of several occupancies), and the
+                kernel's vector-L1 line accesses per second (L1 accesses per sample from
+                the committed counter summary) as a fraction of it
   batched       (--batched) 256 mixed requests over 32 graphs: one persistent launch
                 vs one launch per request
   serving       (--serve) Poisson arrivals over many resident graphs: p50/p99 latency
@@ -58,6 +62,9 @@ def parse():
     ap.add_argument("--workload", default="C2", choices=["C1", "C2", "C3", "C2MIN"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gather-probe", action="store_true")
+    ap.add_argument("--probe-only", type=int, default=0, metavar="BYTES",
+                    help="only run the gather probe over a buffer of BYTES (for its counters)")
     ap.add_argument("--batched", action="store_true")
     ap.add_argument("--serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=5000)
@@ -106,6 +113,47 @@ def measured_traffic(kernel: str, workload: str):
     if not m or not b or m.group(1) != kernel_source_sha():
         return None
     return float(b.group(1))
+
+
+def measured_l1_per_sample(kernel: str, workload: str):
+    """Vector-L1 line accesses per sample of the sampling kernel, from the committed
+    counter summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(p):
+        return None
+    text = open(p).read()
+    m = re.search(r"kernel_source_sha:\s*([0-9a-f]+)", text)
+    b = re.search(r"l1_line_accesses_per_sample:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_source_sha():
+        return None
+    return float(b.group(1))
+
+
+def gather_ceiling(footprint_bytes: int, waves_per_cu=(8, 16, 20, 32), loads=1 << 27):
+    """Dependent random gathers over a buffer of the sampling kernels' footprint
+    (libmoss_probe.so): loads per second at several occupancies, and the best."""
+    import torch
+    from paper_1509_08089_amd import probe
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    buf = torch.empty(max(1, footprint_bytes // 8), dtype=torch.int64, device="cuda")
+    probe.moss_probe_fill(buf, 1)
+    sweep = {}
+    for w in waves_per_cu:
+        blocks = cus * w // 4  # 256-lane blocks of four waves
+        out = torch.empty(blocks * 256, dtype=torch.int64, device="cuda")
+        steps = max(16, loads // (blocks * 256))
+        probe.moss_probe_gather(buf, blocks, steps, out)  # warm-up (and brings the buffer into the caches)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            probe.moss_probe_gather(buf, blocks, steps, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        sweep[w] = blocks * 256 * steps / (ms / 1e3)
+    best = max(sweep, key=sweep.get)
+    return {"footprint_bytes": int(buf.numel() * 8), "probe_loads_per_s": sweep[best], "probe_waves_per_cu": best,
+            "sweep_loads_per_s": {str(w): v for w, v in sweep.items()}}
 
 
 def exact_counts(workload: str, sha: str, k: int):
@@ -159,6 +207,9 @@ def main():
 
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.probe_only:
+        print(json.dumps({"gather_probe": gather_ceiling(args.probe_only, waves_per_cu=(16,))}), flush=True)
+        return 0
 
     import numpy as np
     import torch
@@ -242,6 +293,20 @@ def main():
     if exact is not None:
         line["exact"] = exact
         line["rel_error"] = [abs(e - x) / x if x else None for e, x in zip(line["estimates"], exact)]
+    if not args.no_gather_probe:
+        log("[bench] gather probe")
+        h = moss.moss_graph_create_device(csr.n, csr.nnz, d_rp, d_col, 0, stream)
+        try:
+            moss.moss_build_tables(h, mask)
+            fp = moss.moss_graph_get_info(h).sampling_bytes
+        finally:
+            moss.moss_graph_destroy(h)
+        gc = gather_ceiling(fp)
+        l1 = measured_l1_per_sample(kernel, args.workload)
+        gc["kernel_l1_lines_per_sample"] = l1
+        gc["kernel_l1_lines_per_s"] = l1 * K / (kern_ms / 1e3) if l1 else None
+        gc["frac"] = gc["kernel_l1_lines_per_s"] / gc["probe_loads_per_s"] if l1 else None
+        line["gather"] = gc
     if args.batched:
         line["batched"] = run_batched(moss, gg)
     if args.serve:

@@ -116,6 +116,8 @@ typedef struct {
                               copy); the per-graph block made at creation (edge hash
                               set and filter, work items, node records) is not counted */
   uint64_t gamma_min;      /* check-Gamma (Table 1), valid once K4MIN tables are built */
+  uint64_t sampling_bytes; /* device bytes the samplers read from: the built tables, the
+                              CSR (owned or borrowed) and the edge hash set and filter */
 } moss_graph_info;
 
 typedef struct {

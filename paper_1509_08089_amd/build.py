@@ -10,6 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmoss.so")
+PROBE_LIB = os.path.join(HERE, "libmoss_probe.so")  # gather probe used by the benchmark
 
 SOURCES = ["kernels.hip", "api.cpp", "classify.cpp", "finals.cpp", "batch.cpp", "server.cpp"]
 HEADERS = ["device.h", "kernels.h", "internal.h", "batch.h"]
@@ -33,14 +34,19 @@ def needs_build() -> bool:
     return any(os.path.getmtime(p) > t for p in deps)
 
 
-def build(verbose: bool = False) -> str:
+def _compile(srcs, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", *sources(), "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    _compile(sources(), LIB, verbose)
+    _compile([os.path.join(CSRC, "probe.hip")], PROBE_LIB, verbose)
     return LIB
 
 

@@ -287,7 +287,7 @@ T* at(void* base, size_t off) {
 // per graph: word block, edge hash set and filter, items, item sums, row-guide lengths,
 // scan scratch, partials, records
 struct GraphLayout {
-  size_t small, slots, filter, items, item_sum, guide_len, tmp[3], partials, rec, bytes;
+  size_t small, slots, filter, items, item_sum, guide_len, tmp[3], partials, rec, span_row, check_part, bytes;
 };
 
 GraphLayout graph_layout(int32_t n, int64_t nnz) {
@@ -303,6 +303,8 @@ GraphLayout graph_layout(int32_t n, int64_t nnz) {
   for (int j = 0; j < 3; ++j) L.tmp[j] = c.take<uint64_t>((size_t)scan_tmp_elems(n));
   L.partials = c.take<uint64_t>(2 * (size_t)node_weight_blocks(n));
   L.rec = c.take<uint4>((size_t)n);
+  L.span_row = c.take<int32_t>((size_t)std::max<int64_t>(1, span_count(nnz)));
+  L.check_part = c.take<uint64_t>((size_t)check_part_words());
   L.bytes = c.off;
   return L;
 }
@@ -487,6 +489,8 @@ moss_status finish_create(moss_graph* g) {
   for (int j = 0; j < 3; ++j) g->scan_tmp[j] = at<uint64_t>(m, L.tmp[j]);
   g->partials = at<uint64_t>(m, L.partials);
   g->rec = at<uint4>(m, L.rec);
+  g->span_row = at<int32_t>(m, L.span_row);
+  g->check_part = at<uint64_t>(m, L.check_part);
   if (!(g->h_stage = pinned_chunk())) return MOSS_E_NOMEM;
   if (!(g->ev0 = pooled_event(g->device)) || !(g->ev1 = pooled_event(g->device))) return MOSS_E_DEVICE;
   hipStream_t s = g->stream;
@@ -516,13 +520,14 @@ moss_status finish_create(moss_graph* g) {
     e = launch_scans(set, g->n, err, s);
   }
   if (e == hipSuccess)
-    e = launch_items_records(g->n, g->rp, g->item_sum, g->guide_len, cap, g->items, g->rec, g->small, s);
+    e = launch_items_records(g->n, g->rp, g->item_sum, g->guide_len, cap, g->items, g->rec, g->span_row, g->small,
+                             s);
   if (e == hipSuccess)
-    e = launch_edge_insert(cap, g->items, g->rp, g->col, g->n, g->edge_slots, g->edge_bits, g->filter, g->filter_bits,
-                           g->small, s);
+    e = launch_edge_insert(g->nnz, g->span_row, g->rp, g->col, g->n, g->edge_slots, g->edge_bits, g->filter,
+                           g->filter_bits, g->small, s);
   if (e == hipSuccess)
-    e = launch_check_items(cap, g->items, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->edge_slots,
-                           g->edge_bits, g->small, s);
+    e = launch_check_items(g->nnz, g->span_row, g->n, g->rp, g->col, !(g->flags & MOSS_TRUST_CSR), g->edge_slots,
+                           g->edge_bits, g->check_part, g->small, s);
   if (e == hipSuccess) e = hipMemcpyAsync(g->h_stage, g->small, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return status_of(e);
@@ -662,6 +667,7 @@ moss_status moss_graph_get_info(const moss_graph* g, moss_graph_info* info) {
   r.lambda4 = g->lambda4;
   r.device_bytes = g->table_bytes + (g->owned_rp ? g->csr_bytes : 0);
   r.gamma_min = g->total[3];
+  r.sampling_bytes = sampling_footprint(g);
   *info = r;
   return MOSS_OK;
 }

@@ -38,6 +38,8 @@ struct moss_graph {
   uint64_t* scan_tmp[3] = {};            // block sums of up to three scans
   uint64_t* partials = nullptr;          // per-block Lambda partial sums
   uint4* rec = nullptr;                  // per node: row start, degree, S_v, row-guide offset
+  int32_t* span_row = nullptr;           // per span of 256 entries: the row of its first entry
+  uint64_t* check_part = nullptr;        // per-block counts of the creation check
   int64_t n_items = 0;
   int64_t row_guide_len = 0;             // entries of one row-guide array
 

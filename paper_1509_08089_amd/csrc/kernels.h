@@ -105,21 +105,28 @@ int64_t items_cap(int32_t n, int64_t nnz);
 // (small[kWMaxDeg]), piece count into item_cnt and row-guide length into guide_len.
 hipError_t launch_node_prep(int32_t n, int64_t nnz, const int32_t* rp, uint64_t* item_cnt, uint64_t* guide_len,
                             uint64_t* small, hipStream_t s);
+// Spans of CSR entries walked by the creation checks and the hash-set build (span s
+// starts at entry 256 s); span_row holds span_count(nnz) rows.
+int64_t span_count(int64_t nnz);
 // After item_end (scanned piece counts) and goff_end (scanned guide lengths): the packed
-// (row, piece) items and the node records {row start, degree, 0, row-guide offset}.
-// Both do nothing once row_ptr has been rejected.
+// (row, piece) items, the node records {row start, degree, 0, row-guide offset} and
+// span_row[s], the row holding the span's first entry.  All do nothing once row_ptr
+// has been rejected.
 hipError_t launch_items_records(int32_t n, const int32_t* rp, const uint64_t* item_end, const uint64_t* goff_end,
-                                int64_t cap, uint64_t* items, uint4* rec, uint64_t* small, hipStream_t s);
+                                int64_t cap, uint64_t* items, uint4* rec, int32_t* span_row, uint64_t* small,
+                                hipStream_t s);
 // The edge hash set (filled with empty keys beforehand) and the edge filter (zeroed)
 // from the entries (v, c) with v < c < n; nothing once row_ptr has been rejected.
-hipError_t launch_edge_insert(int64_t cap, const uint64_t* items, const int32_t* rp, const int32_t* col, int32_t n,
+hipError_t launch_edge_insert(int64_t nnz, const int32_t* span_row, const int32_t* rp, const int32_t* col, int32_t n,
                               uint64_t* slots, int hash_bits, uint64_t* filter, int filter_bits, uint64_t* small,
                               hipStream_t s);
 // Column range; with `full` also self-loops, strict ascent and, through the hash set,
 // the mirror of every entry (v, c) with c < v; counts the entries with c > v into
-// small[kWUpper].
-hipError_t launch_check_items(int64_t cap, const uint64_t* items, int32_t n, const int32_t* rp, const int32_t* col,
-                              bool full, const uint64_t* slots, int hash_bits, uint64_t* small, hipStream_t s);
+// small[kWUpper] (through part: check_part_words() u64 of per-block counts).
+int check_part_words();
+hipError_t launch_check_items(int64_t nnz, const int32_t* span_row, int32_t n, const int32_t* rp, const int32_t* col,
+                              bool full, const uint64_t* slots, int hash_bits, uint64_t* part, uint64_t* small,
+                              hipStream_t s);
 
 // ---- table build ----
 // Row prefixes with their row guides: ACC_sigma (kRowSigma; also the node records'

@@ -54,7 +54,8 @@ class moss_graph_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("max_degree", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("built_mask", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("gamma", ctypes.c_uint64),
                 ("gamma1", ctypes.c_uint64), ("gamma2", ctypes.c_uint64), ("lambda3", ctypes.c_uint64),
-                ("lambda4", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("gamma_min", ctypes.c_uint64)]
+                ("lambda4", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64), ("gamma_min", ctypes.c_uint64),
+                ("sampling_bytes", ctypes.c_uint64)]
 
 
 class moss_result(ctypes.Structure):

@@ -185,3 +185,25 @@ def test_finals_reject_bad_arguments():
     r.k, r.K[0], r.K[1], r.flags = 5, 10, 10, moss.MOSS_K4_MIN  # the flag is for k = 4
     with pytest.raises(moss.MossError):
         moss.moss_finals(r)
+
+
+def test_probe_library_exports_and_rejects_bad_arguments():
+    """libmoss_probe.so (the benchmark's gather probe) exports what moss_probe.h declares
+    and rejects bad arguments before any launch."""
+    import ctypes
+    from paper_1509_08089_amd import probe
+    text = open(os.path.join(ROOT, "include", "moss_probe.h")).read()
+    decl = sorted(set(re.findall(r"^int\s+(moss_probe_\w+)\(", text, re.M)))
+    assert decl == sorted(probe.EXPORTED)
+    L = probe.lib()
+    P = ctypes.c_void_p
+    fake = P(4096)  # never dereferenced: every call below fails its argument checks first
+    assert L.moss_probe_fill(None, 10, 1, None) == -1
+    assert L.moss_probe_fill(fake, 0, 1, None) == -1
+    assert L.moss_probe_gather(None, 10, 1, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 1, 1, None, None) == -1
+    assert L.moss_probe_gather(fake, 0, 1, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 0, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, (1 << 20) + 1, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 1, 0, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 1, (1 << 20) + 1, fake, None) == -1
