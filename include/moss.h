@@ -98,6 +98,14 @@ typedef enum {
 #define MOSS_TAB_ACC_CHECK 12    /* u64[nnz] row-local inclusive prefix of d_{v,x} d_{x,v} */
 #define MOSS_TAB_RANK 13         /* u32 pairs, count nnz: per entry (v, x) d_{v,x}, d_{x,v} */
 #define MOSS_TAB_COL_RANK 15     /* i32[nnz] each row N_v in descending order */
+/* Row guides (an implementation aid, not from the paper): the search windows of the
+   weighted picks inside a row.  Rows with d_v >= 64, in node order, each hold 2^g + 1
+   u32 entries, g = floor(log2 d_v) - 1; with A the row's prefix, T its last value and
+   s = max(0, bitlength(T) - g), entry b is the first i with A[i] > b * 2^s, or d_v - 1
+   when there is none.  count = the sum of those lengths over the rows. */
+#define MOSS_TAB_SIGMA_GUIDE 16  /* over ACC_sigma (built with K4 or K5) */
+#define MOSS_TAB_TAU_GUIDE 17    /* over ACC_tau (K5) */
+#define MOSS_TAB_CHECK_GUIDE 18  /* over ACC_check (K4MIN) */
 
 typedef struct moss_graph moss_graph;
 

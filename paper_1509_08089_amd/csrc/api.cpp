@@ -287,7 +287,8 @@ T* at(void* base, size_t off) {
 // per graph: word block, edge hash set and filter, items, item sums, row-guide lengths,
 // scan scratch, partials, records
 struct GraphLayout {
-  size_t small, slots, filter, items, item_sum, guide_len, tmp[3], partials, rec, span_row, check_part, bytes;
+  size_t small, slots, filter, items, item_sum, guide_len, tmp[3], partials, rec, span_row, check_part, span_sums,
+      bytes;
 };
 
 GraphLayout graph_layout(int32_t n, int64_t nnz) {
@@ -298,13 +299,14 @@ GraphLayout graph_layout(int32_t n, int64_t nnz) {
   L.slots = c.take<uint64_t>((size_t)1 << edge_hash_bits(nnz / 2));
   L.filter = c.take<uint64_t>((size_t)1 << edge_filter_bits(nnz / 2));
   L.items = c.take<uint64_t>((size_t)cap);
-  L.item_sum = c.take<uint64_t>((size_t)std::max<int64_t>(cap, (int64_t)n));
+  L.item_sum = c.take<uint64_t>((size_t)std::max<int32_t>(1, n));
   L.guide_len = c.take<uint64_t>((size_t)n);
   for (int j = 0; j < 3; ++j) L.tmp[j] = c.take<uint64_t>((size_t)scan_tmp_elems(n));
   L.partials = c.take<uint64_t>(2 * (size_t)node_weight_blocks(n));
   L.rec = c.take<uint4>((size_t)n);
   L.span_row = c.take<int32_t>((size_t)std::max<int64_t>(1, span_count(nnz)));
   L.check_part = c.take<uint64_t>((size_t)check_part_words());
+  L.span_sums = c.take<uint64_t>(2 * (size_t)std::max<int64_t>(1, span_count(nnz)));
   L.bytes = c.off;
   return L;
 }
@@ -491,6 +493,7 @@ moss_status finish_create(moss_graph* g) {
   g->rec = at<uint4>(m, L.rec);
   g->span_row = at<int32_t>(m, L.span_row);
   g->check_part = at<uint64_t>(m, L.check_part);
+  g->span_sums = at<uint64_t>(m, L.span_sums);
   if (!(g->h_stage = pinned_chunk())) return MOSS_E_NOMEM;
   if (!(g->ev0 = pooled_event(g->device)) || !(g->ev1 = pooled_event(g->device))) return MOSS_E_DEVICE;
   hipStream_t s = g->stream;
@@ -713,6 +716,20 @@ moss_status moss_table_read(const moss_graph* g, int32_t which, void* host_out, 
       bytes = (size_t)count * (which == MOSS_TAB_COL_RANK ? sizeof(int32_t) : sizeof(uint64_t));
       break;
     }
+    case MOSS_TAB_SIGMA_GUIDE:
+    case MOSS_TAB_TAU_GUIDE:
+    case MOSS_TAB_CHECK_GUIDE: {
+      if (count != g->row_guide_len) return MOSS_E_ARG;
+      const uint32_t need = which == MOSS_TAB_SIGMA_GUIDE ? (MOSS_TABLES_K4 | MOSS_TABLES_K5)
+                            : which == MOSS_TAB_TAU_GUIDE ? MOSS_TABLES_K5
+                                                          : MOSS_TABLES_K4MIN;
+      if (!(g->built & need)) return MOSS_E_NOT_BUILT;
+      src = which == MOSS_TAB_SIGMA_GUIDE ? (const void*)g->sig_guide
+            : which == MOSS_TAB_TAU_GUIDE ? (const void*)g->tau_guide
+                                          : (const void*)g->check_guide;
+      bytes = (size_t)count * sizeof(uint32_t);
+      break;
+    }
     default:
       return MOSS_E_ARG;
   }
@@ -790,13 +807,14 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   f.count[1] = 4;
   hipError_t e = launch_fill_set(f, s);
   RowTables t{};
-  t.items = g->items;
   t.rp = g->rp;
   t.col = g->col;
+  t.span_row = g->span_row;
   t.acc_sigma = g->acc_sigma;
-  t.item_sum = g->item_sum;
+  t.span_sums = g->span_sums;
   t.rec = g->rec;
-  t.n_items = g->n_items;
+  t.nnz = g->nnz;
+  t.n = g->n;
   if (e == hipSuccess && want_sig) {
     t.guide = g->sig_guide;
     e = launch_row_tables(kRowSigma, t, err, s);

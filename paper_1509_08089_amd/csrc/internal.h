@@ -33,13 +33,14 @@ struct moss_graph {
   // per graph (mem_graph)
   uint64_t* small = nullptr;             // kWords words shared with the kernels
   uint64_t* items = nullptr;             // work items: rows cut into pieces of <= 256 entries
-  uint64_t* item_sum = nullptr;          // per-piece totals (at creation: piece counts)
+  uint64_t* item_sum = nullptr;          // n: piece counts, scanned into each row's item end (creation)
   uint64_t* guide_len = nullptr;         // n, row-guide lengths (creation only)
   uint64_t* scan_tmp[3] = {};            // block sums of up to three scans
   uint64_t* partials = nullptr;          // per-block Lambda partial sums
   uint4* rec = nullptr;                  // per node: row start, degree, S_v, row-guide offset
   int32_t* span_row = nullptr;           // per span of 256 entries: the row of its first entry
   uint64_t* check_part = nullptr;        // per-block counts of the creation check
+  uint64_t* span_sums = nullptr;         // 2 per span: the row-prefix passes' span sums
   int64_t n_items = 0;
   int64_t row_guide_len = 0;             // entries of one row-guide array
 

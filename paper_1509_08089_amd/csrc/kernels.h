@@ -134,17 +134,19 @@ hipError_t launch_check_items(int64_t nnz, const int32_t* span_row, int32_t n, c
 // (kRowCheck, after the rank tables).  item_sum holds n_items u64.
 enum RowMode { kRowSigma = 0, kRowTau = 1, kRowCheck = 2 };
 struct RowTables {
-  const uint64_t* items;
   const int32_t* rp;
   const int32_t* col;
+  const int32_t* span_row;  // row of each 256-entry span's first entry (from creation)
   uint32_t* acc_sigma;
   uint64_t* acc_tau;
   const uint2* rank;
   uint64_t* acc_check;
-  uint64_t* item_sum;
+  uint64_t* span_sums;      // 2 * span_count(nnz): per span, the open row's sum at its end,
+                            // then the sum of its first row's entries in it
   uint4* rec;
   uint32_t* guide;
-  int64_t n_items;
+  int64_t nnz;
+  int32_t n;
 };
 hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStream_t s);
 

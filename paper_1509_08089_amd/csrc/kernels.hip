@@ -6,8 +6,10 @@
 //   k_edge_insert      the edge hash set (then k_filter_build: the edge filter)
 //   k_check_items      column range, self-loops, strict ascent, symmetry
 // Table build (Section 4.1.3 "Initialization", O(|E|)):
-//   k_prefix_local     each piece's local prefix of ACC_sigma or ACC_tau
-//   k_row_finish       stitches the pieces of a row, writes its row guide and S_v
+//   k_span_prefix      each 256-entry span's prefix of ACC_sigma, ACC_tau or the
+//                      MOSS-4Min row weights, restarted at every row start
+//   k_span_finish      adds the earlier spans' sums to rows that began before the
+//                      span, writes the row guides and S_v
 //   k_node_weights     Gamma_v, Gamma^(1)_v, Gamma^(2)_v, Lambda_3, Lambda_4
 //   k_scan_*           node-level inclusive prefixes ACC_Gamma*
 //   k_guides           search windows for the node draws
@@ -521,25 +523,38 @@ int check_part_words() { return kCheckBlocks; }
 
 // ---------------------------------------------------------------------------------
 // Row prefixes (Section 4.1.3 ACC_sigma = ACC_mu of Section 5.1.5; the tau prefix of
-// Section 5.1.2; MOSS-4Min's prefix of d_{v,x} d_{x,v}, Section 4.2.1), in two steps
-// per table:
-//   local   each item scans its own entries and writes its total to item_sum
-//   finish  each item adds the totals of its row's earlier pieces (at most a few
-//           hundred, summed by the wave), then writes its share of the row guide;
-//           the ACC_sigma pass also records S_v
-// ACC_sigma entries are (d_x - 1) of the neighbours; ACC_tau entries are
-// (d_x - 1)(S_v - (d_x - 1)) with S_v the row total of ACC_sigma; the MOSS-4Min
-// entries are d_{v,x} d_{x,v} from the rank tables.
+// Section 5.1.2; MOSS-4Min's prefix of d_{v,x} d_{x,v}, Section 4.2.1), in two passes
+// over 256-entry spans (k_span_prefix, k_span_finish below).  ACC_sigma entries are
+// (d_x - 1) of the neighbours; ACC_tau entries are (d_x - 1)(S_v - (d_x - 1)) with S_v
+// the row total of ACC_sigma; the MOSS-4Min entries are d_{v,x} d_{x,v} from the rank
+// tables.
 // ---------------------------------------------------------------------------------
-// Entry e of a row answers the guide buckets whose lower bound b * 2^sh lies in
-// [lo, hi) (lo, hi: the finished prefix before and through e); the row's last entry
-// also those at or above the total.
-__device__ __forceinline__ void guide_entries(uint32_t* gd, int g, int sh, uint64_t lo, uint64_t hi, int32_t e,
-                                              int32_t r0, int32_t r1) {
-  const uint64_t b0 = lo ? ((lo - 1) >> sh) + 1 : 0ull;
-  uint64_t b1 = hi ? ((hi - 1) >> sh) + 1 : 0ull;
-  if (e == r1 - 1) b1 = (1ull << g) + 1;
-  for (uint64_t b = b0; b < b1; ++b) gd[b] = (uint32_t)(e - r0);
+// Each lane owns nb guide entries guide[goff + b0 ..) to set to val; the wave shares the
+// stores out evenly (one entry of a row can own thousands of buckets while its
+// neighbours own none), consecutive lanes writing consecutive entries of one owner.
+// Uniform control flow.
+__device__ __forceinline__ void wave_fill_guides(uint32_t* __restrict__ guide, uint32_t goff, uint32_t b0,
+                                                 uint32_t nb, uint32_t val) {
+  if (__ballot(nb != 0) == 0) return;  // wave-uniform
+  const int lane = lane_id();
+  uint32_t incl = nb;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  const uint32_t start = goff + b0 - (incl - nb);  // owner's bucket of store index t: start + t
+  for (uint32_t base = 0; base < total; base += 64) {
+    const uint32_t t = base + lane;
+    int j = 0;  // the owner: the first lane whose inclusive count exceeds t
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+      if (__shfl(incl, j + step - 1, 64) <= t) j += step;
+    const uint32_t at = __shfl(start, j & 63, 64) + t;
+    const uint32_t v = __shfl(val, j & 63, 64);
+    if (t < total) guide[at] = v;
+  }
 }
 
 // the u64 prefix a mode writes (ACC_sigma is u32)
@@ -553,139 +568,222 @@ __device__ __forceinline__ uint32_t row_overflow_bit() {
   return M == kRowSigma ? kErrOverflow : (M == kRowTau ? kErrOverflowK5 : kErrOverflowMin);
 }
 
-// Local prefix of every piece.  A row of one piece (d <= 256) is finished here: its
-// prefix is final, and its guide and (sigma) S_v are written from the values the wave
-// just computed; k_row_finish then only handles rows of several pieces.
-template <int M>
-__global__ __launch_bounds__(256) void k_prefix_local(RowTables t, uint32_t* err) {
+// Inclusive scan over the lanes of a wave, restarted at every lane whose `head` is set;
+// on return `head` tells whether a restart lies at or before the lane.  `wrapped` is
+// set on any 64-bit wrap.
+__device__ __forceinline__ uint64_t wave_segmented_scan(uint64_t x, bool& head, bool& wrapped) {
   const int lane = lane_id();
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  bool wrapped = false, over = false;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
-    const ItemRange it = item_range(t.items, t.rp, i);
-    const uint64_t S = M == kRowTau ? (uint64_t)t.rec[it.v].z : 0ull;
-    const bool single = it.e0 == it.r0 && it.e1 == it.r1;
-    uint64_t carry = 0;
-    uint64_t keep[kItem / 64];  // this lane's prefix values (single-piece rows)
+  uint32_t f = head ? 1u : 0u;
 #pragma unroll
-    for (int c = 0; c < kItem / 64; ++c) {
-      const int32_t e = it.e0 + c * 64 + lane;
-      keep[c] = 0;
-      if (it.e0 + c * 64 >= it.e1) continue;  // wave-uniform
-      uint64_t x = 0;
-      if (e < it.e1) {
-        if (M == kRowTau) {  // the sigma entry d_x - 1, from the finished ACC_sigma
-          const uint64_t dx = (uint64_t)t.acc_sigma[e] - (e > it.r0 ? (uint64_t)t.acc_sigma[e - 1] : 0ull);
-          x = dx * (S - dx);
-        } else if (M == kRowCheck) {
-          const uint2 rk = t.rank[e];
-          x = (uint64_t)rk.x * (uint64_t)rk.y;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(x, off, 64);
+    const uint32_t g = __shfl_up(f, off, 64);
+    if (lane >= off) {
+      if (!f) x = add_wrap(y, x, wrapped);
+      f |= g;
+    }
+  }
+  head = f != 0;
+  return x;
+}
+
+// Row prefixes go over the entries in 256-entry spans, one wave per span, in two passes.
+// k_span_prefix: each span's entries are scanned with a restart at every row start, so
+// the prefix of a row lying inside the span is final; the span records the sum of its
+// last row's entries in it (span_sums[s], the row's running sum at the span's end if it
+// started in the span) and the sum of its first row's entries in it
+// (span_sums[spans + s]).
+template <int M>
+__global__ __launch_bounds__(256) void k_span_prefix(RowTables t, uint32_t* err) {
+  __shared__ __align__(16) uint32_t hist[4][kSpan];
+  constexpr int kPer = kSpanPer;
+  const int lane = lane_id();
+  uint32_t* wh = hist[threadIdx.x >> 6];
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t spans = (t.nnz + kSpan - 1) / kSpan;
+  bool wrapped = false, over = false;
+  for (int64_t sp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; sp < spans; sp += nwaves) {
+    const int64_t S = sp * kSpan;
+    const int32_t v0 = t.span_row[sp];
+    uint64_t raw[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t e = S + lane + 64 * k;
+      raw[k] = 0;
+      if (e >= t.nnz) continue;
+      if (M == kRowSigma) {
+        raw[k] = (uint64_t)(uint32_t)t.col[e];
+      } else if (M == kRowTau) {
+        raw[k] = t.acc_sigma[e];
+      } else {
+        const uint2 rk = t.rank[e];
+        raw[k] = (uint64_t)rk.x * (uint64_t)rk.y;
+      }
+    }
+    const uint64_t before_span = (M == kRowTau && lane == 0 && S > 0) ? (uint64_t)t.acc_sigma[S - 1] : 0ull;
+    int32_t row[kPer];
+    bool head[kPer];
+    span_rows(t.rp, S, v0, sp + 1 < spans ? t.span_row[sp + 1] : t.n - 1, wh, row, head);
+    uint64_t x[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const bool valid = S + lane + 64 * k < t.nnz;
+      if (M == kRowSigma) {  // d_x - 1 of the neighbour x
+        x[k] = valid ? (uint64_t)row_of(t.rec, (int32_t)raw[k]).y - 1 : 0ull;
+      } else if (M == kRowTau) {  // (d_x - 1)(S_v - (d_x - 1)), d_x - 1 from the sigma prefix
+        const uint64_t p = __shfl(raw[k], (lane + 63) & 63, 64);
+        const uint64_t wrap = k ? __shfl(raw[k > 0 ? k - 1 : 0], 63, 64) : before_span;
+        const uint64_t dx = head[k] ? raw[k] : raw[k] - (lane ? p : wrap);
+        x[k] = valid ? dx * ((uint64_t)t.rec[row[k]].z - dx) : 0ull;
+      } else {
+        x[k] = valid ? raw[k] : 0ull;
+      }
+    }
+    uint64_t carry = 0, first = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t e = S + lane + 64 * k;
+      const bool valid = e < t.nnz;
+      bool f = head[k];
+      uint64_t v = wave_segmented_scan(x[k], f, wrapped);
+      if (!f) v = add_wrap(v, carry, wrapped);
+      if (valid) {
+        if (M == kRowSigma) {
+          over |= v > 0xFFFFFFFFull;
+          t.acc_sigma[e] = (uint32_t)v;
         } else {
-          const int32_t c2 = t.col[e];
-          x = (uint64_t)(t.rp[c2 + 1] - t.rp[c2] - 1);
+          row_out64<M>(t)[e] = v;
         }
       }
-      const uint64_t sv = add_wrap(wave_inclusive_scan(x, wrapped), carry, wrapped);
-      if (e < it.e1) {
-        if (M == kRowSigma) t.acc_sigma[e] = (uint32_t)sv;
-        else row_out64<M>(t)[e] = sv;
-      }
-      keep[c] = sv;
-      carry = __shfl(sv, 63, 64);
+      carry = __shfl(v, 63, 64);
+      const uint64_t in_first = __ballot(valid && row[k] == v0);
+      if (in_first) first = __shfl(v, 63 - __clzll((long long)in_first), 64);
     }
-    if (lane == 0) t.item_sum[i] = carry;
-    if (!single) continue;
-    const uint64_t total = carry;
-    if (M == kRowSigma && total > 0xFFFFFFFFull) over = true;
-    const int32_t d = it.r1 - it.r0;
-    if (d >= kRowGuideMin) {
-      const int g = row_guide_bits(d);
-      const int sh = row_guide_shift(total, g);
-      uint32_t* gd = t.guide + t.rec[it.v].w;
-      uint64_t before = 0;
-#pragma unroll
-      for (int c = 0; c < kItem / 64; ++c) {
-        if (it.e0 + c * 64 >= it.e1) continue;
-        const int32_t e = it.e0 + c * 64 + lane;
-        uint64_t lo = __shfl_up(keep[c], 1, 64);
-        if (lane == 0) lo = before;
-        before = __shfl(keep[c], 63, 64);
-        if (e < it.e1) guide_entries(gd, g, sh, lo, keep[c], e, it.r0, it.r1);
-      }
+    if (lane == 0) {
+      t.span_sums[sp] = carry;
+      t.span_sums[spans + sp] = first;
     }
-    if (M == kRowSigma && lane == 0) t.rec[it.v].z = (uint32_t)total;
   }
   // a wrap inside a tau row is a Gamma^(2)_v beyond 64 bits, inside a MOSS-4Min row a
-  // check-Gamma_v beyond 64 bits; a sigma row total beyond 32 bits does not fit ACC_sigma
+  // check-Gamma_v beyond 64 bits; a sigma prefix beyond 32 bits does not fit ACC_sigma
   if (M != kRowSigma && __ballot(wrapped) != 0 && lane == 0) atomicOr(err, row_overflow_bit<M>());
   if (M == kRowSigma && __ballot(over) != 0 && lane == 0) atomicOr(err, kErrOverflow);
 }
 
-// Rows of several pieces: each piece adds the totals of its row's earlier pieces (at
-// most a few hundred, summed by the wave), then writes its share of the row guide;
-// the last piece records S_v (sigma).
+// k_span_finish: a span whose first row started in an earlier span adds that row's
+// sum over those spans to its first row's entries; then every entry writes its share
+// of its row's guide (the row total: from this span if the row ends here, else this
+// span's end plus the row's later spans) and, for ACC_sigma, the row's last entry
+// records S_v.
 template <int M>
-__global__ __launch_bounds__(256) void k_row_finish(RowTables t, uint32_t* err) {
+__global__ __launch_bounds__(256) void k_span_finish(RowTables t, uint32_t* err) {
+  __shared__ __align__(16) uint32_t hist[4][kSpan];
+  __shared__ uint64_t fin[4][kSpan];
+  constexpr int kPer = kSpanPer;
   const int lane = lane_id();
+  uint32_t* wh = hist[threadIdx.x >> 6];
+  uint64_t* fh = fin[threadIdx.x >> 6];
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  bool over = false;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < t.n_items; i += nwaves) {
-    const ItemRange it = item_range(t.items, t.rp, i);
-    if (it.e0 == it.r0 && it.e1 == it.r1) continue;  // finished by k_prefix_local
-    const int32_t d = it.r1 - it.r0;
-    const int64_t first = i - it.piece, end = first + (d + kItem - 1) / kItem;
-    // totals of the row's pieces before this one, and of the whole row
-    bool wrapped = false;
-    uint64_t before = 0, rest = 0;
-    for (int64_t j = first + lane; j < end; j += 64) {
-      const uint64_t x = t.item_sum[j];
-      if (j < i) before = add_wrap(before, x, wrapped);
-      else rest = add_wrap(rest, x, wrapped);
+  const int64_t spans = (t.nnz + kSpan - 1) / kSpan;
+  const uint64_t* tail = t.span_sums;
+  const uint64_t* head_sum = t.span_sums + spans;
+  bool wrapped = false, over = false;
+  for (int64_t sp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; sp < spans; sp += nwaves) {
+    const int64_t S = sp * kSpan;
+    const int32_t v0 = t.span_row[sp];
+    int32_t row[kPer];
+    bool head[kPer];
+    span_rows(t.rp, S, v0, sp + 1 < spans ? t.span_row[sp + 1] : t.n - 1, wh, row, head);
+    // the first row's sum over the earlier spans it covers
+    const int64_t start0 = (int64_t)row_of(t.rec, v0).x;
+    uint64_t carry = 0;
+    if (start0 < S) {
+      for (int64_t j = start0 / kSpan + lane; j < sp; j += 64) carry = add_wrap(carry, tail[j], wrapped);
+      carry = wave_sum_wrap(carry, wrapped);
     }
-    before = wave_sum_wrap(before, wrapped);
-    const uint64_t total = add_wrap(before, wave_sum_wrap(rest, wrapped), wrapped);
-    over |= M != kRowSigma ? wrapped : total > 0xFFFFFFFFull;
-    const bool guided = d >= kRowGuideMin;
-    const int g = guided ? row_guide_bits(d) : 0;
-    const int sh = guided ? row_guide_shift(total, g) : 0;
-    uint32_t* gd = guided ? t.guide + t.rec[it.v].w : nullptr;
-    uint64_t carry = before;  // the finished prefix just before this 64-entry chunk
-    for (int32_t e0 = it.e0; e0 < it.e1; e0 += 64) {
-      const int32_t e = e0 + lane;
-      const bool in = e < it.e1;
-      uint64_t hi = carry;
-      if (in) {
-        if (M == kRowSigma) {
-          hi = (uint64_t)t.acc_sigma[e] + before;
-          if (before) t.acc_sigma[e] = (uint32_t)hi;
-        } else {
-          uint64_t* out = row_out64<M>(t);
-          hi = out[e] + before;
-          if (before) out[e] = hi;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int o = lane + 64 * k;
+      const int64_t e = S + o;
+      uint64_t v = 0;
+      if (e < t.nnz) {
+        v = M == kRowSigma ? (uint64_t)t.acc_sigma[e] : row_out64<M>(t)[e];
+        if (carry && row[k] == v0) {
+          v = add_wrap(v, carry, wrapped);
+          if (M == kRowSigma) {
+            over |= v > 0xFFFFFFFFull;
+            t.acc_sigma[e] = (uint32_t)v;
+          } else {
+            row_out64<M>(t)[e] = v;
+          }
         }
       }
-      uint64_t lo = __shfl_up(hi, 1, 64);
-      if (lane == 0) lo = carry;
-      carry = __shfl(hi, 63, 64);
-      if (in && guided) guide_entries(gd, g, sh, lo, hi, e, it.r0, it.r1);
+      fh[o] = v;
     }
-    if (M == kRowSigma && it.e1 == it.r1 && lane == 0) t.rec[it.v].z = (uint32_t)total;
+    wave_lds_sync();
+    // total of the row that runs past the span's end, if one does
+    uint64_t total_on = 0;
+    if (sp + 1 < spans) {
+      const int32_t rn = t.span_row[sp + 1];
+      const uint2 rr = row_of(t.rec, rn);
+      if ((int64_t)rr.x < S + kSpan) {
+        const int64_t s1 = ((int64_t)rr.x + rr.y - 1) / kSpan;
+        uint64_t mid = 0;
+        for (int64_t j = sp + 1 + lane; j < s1; j += 64) mid = add_wrap(mid, tail[j], wrapped);
+        mid = wave_sum_wrap(mid, wrapped);
+        total_on = add_wrap(add_wrap(fh[kSpan - 1], mid, wrapped), head_sum[s1], wrapped);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int o = lane + 64 * k;
+      const int64_t e = S + o;
+      uint32_t goff = 0, b0 = 0, nb = 0, val = 0;  // this entry's guide buckets [b0, b0 + nb)
+      if (e < t.nnz) {
+        const int32_t r = row[k];
+        const uint4 rr = t.rec[r];  // row start, degree, (S_v), guide offset
+        const int64_t end = (int64_t)rr.x + rr.y;
+        const uint64_t total = end - S <= kSpan ? fh[end - 1 - S] : total_on;
+        const int32_t d = (int32_t)rr.y;
+        if (d >= kRowGuideMin) {
+          const int g = row_guide_bits(d);
+          const int sh = row_guide_shift(total, g);
+          const uint64_t lo = head[k] ? 0ull : (o ? fh[o - 1] : carry), hi = fh[o];
+          // entry e answers the buckets whose lower bound b * 2^sh lies in [lo, hi); the
+          // row's last entry also those at or above the total
+          const uint64_t lim = (1ull << g) + 1;
+          const uint64_t c0 = lo ? ((lo - 1) >> sh) + 1 : 0ull;
+          const uint64_t c1 = e == end - 1 ? lim : (hi ? ((hi - 1) >> sh) + 1 : 0ull);
+          b0 = (uint32_t)min(c0, lim);
+          nb = (uint32_t)(min(c1, lim) - b0) * (c1 > c0);
+          goff = rr.w;
+          val = (uint32_t)(e - rr.x);
+        }
+        if (M == kRowSigma && e == end - 1) {
+          over |= total > 0xFFFFFFFFull;
+          t.rec[r].z = (uint32_t)total;
+        }
+      }
+      wave_fill_guides(t.guide, goff, b0, nb, val);
+    }
+    wave_lds_sync();  // fin is reused by the wave's next span
   }
-  if (__ballot(over) != 0 && lane == 0) atomicOr(err, row_overflow_bit<M>());
+  if (M != kRowSigma && __ballot(wrapped) != 0 && lane == 0) atomicOr(err, row_overflow_bit<M>());
+  if (M == kRowSigma && __ballot(over) != 0 && lane == 0) atomicOr(err, kErrOverflow);
 }
 
 template <int M>
 static hipError_t row_tables_mode(const RowTables& t, uint32_t* err, hipStream_t s) {
-  const dim3 grid(item_grid(t.n_items)), block(256);
-  hipLaunchKernelGGL(k_prefix_local<M>, grid, block, 0, s, t, err);
+  const dim3 grid(spans_grid(t.nnz)), block(256);
+  hipLaunchKernelGGL(k_span_prefix<M>, grid, block, 0, s, t, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_finish<M>, grid, block, 0, s, t, err);
+  hipLaunchKernelGGL(k_span_finish<M>, grid, block, 0, s, t, err);
   return hipGetLastError();
 }
 
 hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStream_t s) {
-  if (t.n_items <= 0) return hipSuccess;
+  if (t.nnz <= 0) return hipSuccess;
   switch (mode) {
     case kRowSigma: return row_tables_mode<kRowSigma>(t, err, s);
     case kRowTau: return row_tables_mode<kRowTau>(t, err, s);
@@ -1143,7 +1241,9 @@ __device__ __forceinline__ int32_t row_pick(F value, int32_t d, uint64_t total, 
   const int g = row_guide_bits(d);
   const uint64_t b = x >> row_guide_shift(total, g);
   const uint2 w = load_pair(guide + goff + b);  // guide[b], guide[b + 1]
-  return first_above_by(value, (int32_t)w.x, (int32_t)w.y, x);
+  // the window lies inside the row for any guide contents (a correct guide needs no clamp)
+  const int32_t hi = min((int32_t)w.y, d - 1);
+  return first_above_by(value, min((int32_t)w.x, hi), hi, x);
 }
 
 struct PrefixOf32 {

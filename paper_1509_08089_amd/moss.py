@@ -32,6 +32,7 @@ MOSS_MIX_POOLED, MOSS_MIX_PAPER, MOSS_K4_MIN = 0x0, 0x1, 0x2
 MOSS_TABLES_K4, MOSS_TABLES_K5, MOSS_TABLES_K4MIN = 1 << 4, 1 << 5, 1 << 6
 MOSS_TAB_ACC_GAMMA, MOSS_TAB_ACC_GAMMA1, MOSS_TAB_ACC_GAMMA2, MOSS_TAB_ACC_SIGMA, MOSS_TAB_ACC_TAU = 5, 6, 7, 8, 9
 MOSS_TAB_ACC_GAMMA_MIN, MOSS_TAB_ACC_CHECK, MOSS_TAB_RANK, MOSS_TAB_COL_RANK = 11, 12, 13, 15
+MOSS_TAB_SIGMA_GUIDE, MOSS_TAB_TAU_GUIDE, MOSS_TAB_CHECK_GUIDE = 16, 17, 18
 
 # every symbol include/moss.h declares
 EXPORTED = [
@@ -216,7 +217,8 @@ def moss_table_read(g, which: int, count: int) -> np.ndarray:
     if which == MOSS_TAB_RANK:
         out = np.zeros((count, 2), np.uint32)
     else:
-        dtype = {MOSS_TAB_ACC_SIGMA: np.uint32, MOSS_TAB_COL_RANK: np.int32}.get(which, np.uint64)
+        dtype = {MOSS_TAB_ACC_SIGMA: np.uint32, MOSS_TAB_COL_RANK: np.int32, MOSS_TAB_SIGMA_GUIDE: np.uint32,
+                 MOSS_TAB_TAU_GUIDE: np.uint32, MOSS_TAB_CHECK_GUIDE: np.uint32}.get(which, np.uint64)
         out = np.zeros(count, dtype)
     _check(lib().moss_table_read(g, which, _hptr(out), count), "moss_table_read")
     return out
