@@ -288,7 +288,7 @@ T* at(void* base, size_t off) {
 // scan scratch, partials, records
 struct GraphLayout {
   size_t small, slots, filter, items, item_sum, guide_len, tmp[3], partials, rec, span_row, check_part, span_sums,
-      bytes;
+      span_groups, group_wrap, bytes;
 };
 
 GraphLayout graph_layout(int32_t n, int64_t nnz) {
@@ -307,6 +307,8 @@ GraphLayout graph_layout(int32_t n, int64_t nnz) {
   L.span_row = c.take<int32_t>((size_t)std::max<int64_t>(1, span_count(nnz)));
   L.check_part = c.take<uint64_t>((size_t)check_part_words());
   L.span_sums = c.take<uint64_t>(2 * (size_t)std::max<int64_t>(1, span_count(nnz)));
+  L.span_groups = c.take<uint64_t>((size_t)std::max<int64_t>(1, span_group_count(nnz)));
+  L.group_wrap = c.take<uint32_t>((size_t)std::max<int64_t>(1, span_group_count(nnz)));
   L.bytes = c.off;
   return L;
 }
@@ -494,6 +496,8 @@ moss_status finish_create(moss_graph* g) {
   g->span_row = at<int32_t>(m, L.span_row);
   g->check_part = at<uint64_t>(m, L.check_part);
   g->span_sums = at<uint64_t>(m, L.span_sums);
+  g->span_groups = at<uint64_t>(m, L.span_groups);
+  g->group_wrap = at<uint32_t>(m, L.group_wrap);
   if (!(g->h_stage = pinned_chunk())) return MOSS_E_NOMEM;
   if (!(g->ev0 = pooled_event(g->device)) || !(g->ev1 = pooled_event(g->device))) return MOSS_E_DEVICE;
   hipStream_t s = g->stream;
@@ -812,6 +816,10 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   t.span_row = g->span_row;
   t.acc_sigma = g->acc_sigma;
   t.span_sums = g->span_sums;
+  if (g->max_degree >= kSpanGroupMinDegree) {
+    t.span_groups = g->span_groups;
+    t.group_wrap = g->group_wrap;
+  }
   t.rec = g->rec;
   t.nnz = g->nnz;
   t.n = g->n;

@@ -41,6 +41,8 @@ struct moss_graph {
   int32_t* span_row = nullptr;           // per span of 256 entries: the row of its first entry
   uint64_t* check_part = nullptr;        // per-block counts of the creation check
   uint64_t* span_sums = nullptr;         // 2 per span: the row-prefix passes' span sums
+  uint64_t* span_groups = nullptr;       // per 64 spans: their summed span sums
+  uint32_t* group_wrap = nullptr;        // per 64 spans: whether that sum wrapped
   int64_t n_items = 0;
   int64_t row_guide_len = 0;             // entries of one row-guide array
 

@@ -108,6 +108,9 @@ hipError_t launch_node_prep(int32_t n, int64_t nnz, const int32_t* rp, uint64_t*
 // Spans of CSR entries walked by the creation checks and the hash-set build (span s
 // starts at entry 256 s); span_row holds span_count(nnz) rows.
 int64_t span_count(int64_t nnz);
+int64_t span_group_count(int64_t nnz);
+// Rows of at least this many entries add up their span sums by groups of 64 spans.
+constexpr int32_t kSpanGroupMinDegree = 64 * 256;
 // After item_end (scanned piece counts) and goff_end (scanned guide lengths): the packed
 // (row, piece) items, the node records {row start, degree, 0, row-guide offset} and
 // span_row[s], the row holding the span's first entry.  All do nothing once row_ptr
@@ -143,6 +146,8 @@ struct RowTables {
   uint64_t* acc_check;
   uint64_t* span_sums;      // 2 * span_count(nnz): per span, the open row's sum at its end,
                             // then the sum of its first row's entries in it
+  uint64_t* span_groups;    // span_group_count(nnz) sums of 64 consecutive span sums, or
+  uint32_t* group_wrap;     // null (rows short enough to add up their spans directly)
   uint4* rec;
   uint32_t* guide;
   int64_t nnz;

@@ -2,9 +2,9 @@
 ACC_check) must equal the oracle's; each row guide must follow its definition from the
 prefix read back: for a row with d >= 64, g = floor(log2 d) - 1, total T and
 s = max(0, bitlength(T) - g), entry b is the first i with A[i] > b * 2^s, else d - 1.
-Graphs have rows crossing several 256-entry spans (hubs), rows starting exactly at
-span boundaries, runs of rows without entries, rows whose weights are all zero and
-rows of one or two entries between hubs."""
+Graphs have rows crossing several 256-entry spans (hubs, one over 234 spans), rows
+starting exactly at span boundaries, runs of rows without entries, rows whose weights
+are all zero and rows of one or two entries between hubs."""
 import numpy as np
 import pytest
 
@@ -31,8 +31,22 @@ def _hubs_and_gaps():
     return gg.from_edges(n, sorted(edges), "hubs+gaps")
 
 
+def _big_hub():
+    """A hub joined to 60,000 of 70,000 nodes (a row over 234 spans, past the size at
+    which rows add up their span sums by groups of 64 spans), plus random edges so
+    that its neighbours' weights differ."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    n = 70_000
+    leaves = rng.choice(np.arange(1, n), 60_000, replace=False)
+    edges = [(0, int(x)) for x in leaves]
+    a = rng.integers(1, n, 40_000)
+    b = rng.integers(1, n, 40_000)
+    edges += [(int(x), int(y)) for x, y in zip(a, b) if x != y]
+    return gg.from_edges(n, edges, "big hub")
+
+
 GRAPHS = [_hubs_and_gaps(), gg.chung_lu(5000, 40000, 2.1, 900, 12), gg.star(3000), gg.wheel(700),
-          gg.complete_bipartite(3, 900), gg.complete(90)]
+          gg.complete_bipartite(3, 900), gg.complete(90), _big_hub()]
 
 
 def expected_guides(rp, acc):
