@@ -134,7 +134,7 @@ hipError_t launch_check_items(int64_t nnz, const int32_t* span_row, int32_t n, c
 // ---- table build ----
 // Row prefixes with their row guides: ACC_sigma (kRowSigma; also the node records'
 // S_v), ACC_tau (kRowTau, after ACC_sigma) or the MOSS-4Min prefix of d_{v,x} d_{x,v}
-// (kRowCheck, after the rank tables).  item_sum holds n_items u64.
+// (kRowCheck, after the rank tables), over 256-entry spans of the CSR.
 enum RowMode { kRowSigma = 0, kRowTau = 1, kRowCheck = 2 };
 struct RowTables {
   const int32_t* rp;
