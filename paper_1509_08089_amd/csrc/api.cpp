@@ -304,7 +304,7 @@ GraphLayout graph_layout(int32_t n, int64_t nnz) {
   for (int j = 0; j < 3; ++j) L.tmp[j] = c.take<uint64_t>((size_t)scan_tmp_elems(n));
   L.partials = c.take<uint64_t>(2 * (size_t)node_weight_blocks(n));
   L.rec = c.take<uint4>((size_t)n);
-  L.span_row = c.take<int32_t>((size_t)std::max<int64_t>(1, span_count(nnz)));
+  L.span_row = c.take<int32_t>((size_t)span_count(nnz) + 1);
   L.check_part = c.take<uint64_t>((size_t)check_part_words());
   L.span_sums = c.take<uint64_t>(2 * (size_t)std::max<int64_t>(1, span_count(nnz)));
   L.span_groups = c.take<uint64_t>((size_t)std::max<int64_t>(1, span_group_count(nnz)));
@@ -527,8 +527,8 @@ moss_status finish_create(moss_graph* g) {
     e = launch_scans(set, g->n, err, s);
   }
   if (e == hipSuccess)
-    e = launch_items_records(g->n, g->rp, g->item_sum, g->guide_len, cap, g->items, g->rec, g->span_row, g->small,
-                             s);
+    e = launch_items_records(g->n, g->nnz, g->rp, g->item_sum, g->guide_len, cap, g->items, g->rec, g->span_row,
+                             g->small, s);
   if (e == hipSuccess)
     e = launch_edge_insert(g->nnz, g->span_row, g->rp, g->col, g->n, g->edge_slots, g->edge_bits, g->filter,
                            g->filter_bits, g->small, s);

@@ -105,8 +105,8 @@ int64_t items_cap(int32_t n, int64_t nnz);
 // (small[kWMaxDeg]), piece count into item_cnt and row-guide length into guide_len.
 hipError_t launch_node_prep(int32_t n, int64_t nnz, const int32_t* rp, uint64_t* item_cnt, uint64_t* guide_len,
                             uint64_t* small, hipStream_t s);
-// Spans of CSR entries walked by the creation checks and the hash-set build (span s
-// starts at entry 256 s); span_row holds span_count(nnz) rows.
+// Spans of CSR entries walked by the creation checks, the hash-set build and the row
+// prefixes (span s starts at entry 256 s); span_row holds span_count(nnz) + 1 rows.
 int64_t span_count(int64_t nnz);
 int64_t span_group_count(int64_t nnz);
 // Rows of at least this many entries add up their span sums by groups of 64 spans.
@@ -115,9 +115,9 @@ constexpr int32_t kSpanGroupMinDegree = 64 * 256;
 // (row, piece) items, the node records {row start, degree, 0, row-guide offset} and
 // span_row[s], the row holding the span's first entry.  All do nothing once row_ptr
 // has been rejected.
-hipError_t launch_items_records(int32_t n, const int32_t* rp, const uint64_t* item_end, const uint64_t* goff_end,
-                                int64_t cap, uint64_t* items, uint4* rec, int32_t* span_row, uint64_t* small,
-                                hipStream_t s);
+hipError_t launch_items_records(int32_t n, int64_t nnz, const int32_t* rp, const uint64_t* item_end,
+                                const uint64_t* goff_end, int64_t cap, uint64_t* items, uint4* rec, int32_t* span_row,
+                                uint64_t* small, hipStream_t s);
 // The edge hash set (filled with empty keys beforehand) and the edge filter (zeroed)
 // from the entries (v, c) with v < c < n; nothing once row_ptr has been rejected.
 hipError_t launch_edge_insert(int64_t nnz, const int32_t* span_row, const int32_t* rp, const int32_t* col, int32_t n,

@@ -186,10 +186,13 @@ __device__ __forceinline__ bool rowptr_rejected(const uint64_t* small) {
 
 // item_end / goff_end: inclusive prefixes of the piece counts and guide lengths.
 // span_row[s] is the row holding entry s * kSpan (each such entry lies in exactly one
-// non-empty row, which writes it; a validated row_ptr keeps s below the span count).
-__global__ void k_items_records(int32_t n, const int32_t* __restrict__ rp, const uint64_t* __restrict__ item_end,
-                                const uint64_t* __restrict__ goff_end, int64_t cap, uint64_t* __restrict__ items,
-                                uint4* __restrict__ rec, int32_t* __restrict__ span_row, const uint64_t* small) {
+// non-empty row, which writes it; a validated row_ptr keeps s below the span count),
+// and span_row[spans] the last non-empty row, so that span_row[s + 1] bounds the rows
+// of span s also for the last span (rows without entries after it never enter).
+__global__ void k_items_records(int32_t n, int64_t nnz, const int32_t* __restrict__ rp,
+                                const uint64_t* __restrict__ item_end, const uint64_t* __restrict__ goff_end,
+                                int64_t cap, uint64_t* __restrict__ items, uint4* __restrict__ rec,
+                                int32_t* __restrict__ span_row, const uint64_t* small) {
   if (rowptr_rejected(small)) return;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r0 = rp[v], r1 = rp[v + 1], d = r1 - r0;
@@ -199,15 +202,16 @@ __global__ void k_items_records(int32_t n, const int32_t* __restrict__ rp, const
       if (first + j < (uint64_t)cap) items[first + j] = (uint64_t)v << 32 | j;
     rec[v] = make_uint4((uint32_t)r0, (uint32_t)d, 0u, (uint32_t)(goff_end[v] - row_guide_len(d)));
     for (int64_t sp = ((int64_t)r0 + kSpan - 1) / kSpan; sp * kSpan < (int64_t)r1; ++sp) span_row[sp] = (int32_t)v;
+    if (d > 0 && (int64_t)r1 == nnz) span_row[(nnz + kSpan - 1) / kSpan] = (int32_t)v;
   }
 }
 
-hipError_t launch_items_records(int32_t n, const int32_t* rp, const uint64_t* item_end, const uint64_t* goff_end,
-                                int64_t cap, uint64_t* items, uint4* rec, int32_t* span_row, uint64_t* small,
-                                hipStream_t s) {
+hipError_t launch_items_records(int32_t n, int64_t nnz, const int32_t* rp, const uint64_t* item_end,
+                                const uint64_t* goff_end, int64_t cap, uint64_t* items, uint4* rec, int32_t* span_row,
+                                uint64_t* small, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_items_records, dim3(fill_grid(n)), dim3(256), 0, s, n, rp, item_end, goff_end, cap, items, rec,
-                     span_row, small);
+  hipLaunchKernelGGL(k_items_records, dim3(fill_grid(n)), dim3(256), 0, s, n, nnz, rp, item_end, goff_end, cap, items,
+                     rec, span_row, small);
   return hipGetLastError();
 }
 
@@ -328,7 +332,7 @@ __global__ __launch_bounds__(256) void k_edge_insert(int64_t nnz, const int32_t*
     bool head[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) c[k] = S + lane + 64 * k < nnz ? col[S + lane + 64 * k] : -1;
-    span_rows(rp, S, span_row[sp], sp + 1 < spans ? span_row[sp + 1] : n - 1, wh, row, head);
+    span_rows(rp, S, span_row[sp], span_row[sp + 1], wh, row, head);
     uint64_t key[kPer], h[kPer];
     unsigned long long old[kPer];
     bool live[kPer];
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(256) void k_check_items(int64_t nnz, const int32_t*
 #pragma unroll
     for (int k = 0; k < kPer; ++k) c[k] = S + lane + 64 * k < nnz ? col[S + lane + 64 * k] : 0;
     const int32_t before_span = (lane == 0 && S > 0) ? col[S - 1] : 0;
-    span_rows(rp, S, span_row[sp], sp + 1 < spans ? span_row[sp + 1] : n - 1, wh, row, head);
+    span_rows(rp, S, span_row[sp], span_row[sp + 1], wh, row, head);
     // the previous entry's column: lane l - 1's, lane 63's of the previous round, or
     // the entry before the span
     int32_t prev[kPer];
@@ -631,7 +635,7 @@ __global__ __launch_bounds__(256) void k_span_prefix(RowTables t, uint32_t* err)
     const uint64_t before_span = (M == kRowTau && lane == 0 && S > 0) ? (uint64_t)t.acc_sigma[S - 1] : 0ull;
     int32_t row[kPer];
     bool head[kPer];
-    span_rows(t.rp, S, v0, sp + 1 < spans ? t.span_row[sp + 1] : t.n - 1, wh, row, head);
+    span_rows(t.rp, S, v0, t.span_row[sp + 1], wh, row, head);
     uint64_t x[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
@@ -743,7 +747,7 @@ __global__ __launch_bounds__(256) void k_span_finish(RowTables t, uint32_t* err)
     const int32_t v0 = t.span_row[sp];
     int32_t row[kPer];
     bool head[kPer];
-    span_rows(t.rp, S, v0, sp + 1 < spans ? t.span_row[sp + 1] : t.n - 1, wh, row, head);
+    span_rows(t.rp, S, v0, t.span_row[sp + 1], wh, row, head);
     // the first row's sum over the earlier spans it covers
     const int64_t start0 = (int64_t)row_of(t.rec, v0).x;
     const uint64_t carry =
@@ -1615,21 +1619,29 @@ using SortGroup = std::conditional_t<(kSortBits <= 8), uint8_t, uint16_t>;  // a
 static_assert(kSortGroups % 256 == 0 && kSortBits <= 16, "whole groups per scatter thread");
 constexpr uint32_t kSortSpan = 8192;   // samples per block of the counting passes
 static_assert(kSortSpan <= 65536 && kSortSpan % 16 == 0, "16-bit local offsets, 16-byte group loads");
-// Sorted entries a block takes per cursor step: 2048 while the sampled tables fit the
-// MALL, 512 beyond it.  Smaller windows keep the blocks of an XCD closer together in
-// the sorted order, so that they share more of their tables' lines in the L2; past the
-// MALL that matters most (n = 1e6, m = 1e7: T-5 / Path-5 for 5e7 samples each 6.18 /
-// 9.38 ms at 2048, 5.94 / 8.48 ms at 512, 5.94 / 8.37 at 256, 7.58 / 10.6 at 128),
-// while within it the extra cursor steps cost a little (n = 1e5, m = 1e6, MOSS-4
-// for 1e7 samples: 0.673 ms at 2048, 0.684 at 512, 0.725 at 256).
-uint32_t sort_window(uint64_t footprint_bytes) { return footprint_bytes > (256ull << 20) ? 512u : 2048u; }
+// Sorted entries a block takes per cursor step: 512 while the sampled tables fit the
+// MALL, 256 beyond it (multiples of the 256-thread block; 128 leaves half the threads
+// idle).  Smaller windows keep the blocks of an XCD closer together in the sorted
+// order, so that they share more of their tables' lines in the L2, as long as the
+// cursor atomics keep up.  Measured with the cursors apart (below): n = 1e6, m = 1e7,
+// T-5 / Path-5 for 5e7 samples each, 5.74 / 8.31 ms at 512, 5.72 / 8.19 at 256,
+// 7.31 / 10.36 at 128; n = 1e5, m = 1e6, MOSS-4 for 1e7 samples, 0.628 ms at 2048,
+// 0.600 at 1024, 0.575 at 512, 0.577 at 256, 0.63 at 384, 0.78 at 128.  A cursor per
+// wave instead of per block (no block barriers) measured 0.61 ms there.
+uint32_t sort_window(uint64_t footprint_bytes) { return footprint_bytes > (256ull << 20) ? 256u : 512u; }
+
+// The eight window cursors sit 256 bytes apart: packed into one line, every XCD's
+// cursor atomics queued on that line (n = 1e5, m = 1e6, MOSS-4 for 1e7 samples: 0.668
+// -> 0.624 ms; n = 1e6, m = 1e7, T-5 / Path-5 for 5e7 each at 256-sample windows:
+// 5.84 / 8.38 -> 5.72 / 8.19 ms).
+constexpr uint32_t kCursorStride = 64;  // u32
 
 struct SortScratch {
   SortGroup* group;   // n: group of each sample
   uint32_t* order;    // n: sample offsets sorted by group
   uint64_t* counts;   // kSortGroups * nblk: per (group, block) counts, then inclusive prefix
   uint64_t* tmp;      // scan block sums
-  uint32_t* cursors;  // kXcds window cursors
+  uint32_t* cursors;  // kXcds window cursors, kCursorStride apart
   uint32_t* err;      // the scan's wrap flag (cannot fire: the counts sum to n)
   uint32_t nblk;
 };
@@ -1648,7 +1660,7 @@ static SortScratch sort_scratch(void* base, uint64_t max_n) {
   t.order = reinterpret_cast<uint32_t*>(take(max_n * 4));
   t.counts = reinterpret_cast<uint64_t*>(take((size_t)kSortGroups * t.nblk * 8));
   t.tmp = reinterpret_cast<uint64_t*>(take((size_t)scan_tmp_elems((int64_t)kSortGroups * t.nblk) * 8));
-  t.cursors = reinterpret_cast<uint32_t*>(take(kXcds * 4));
+  t.cursors = reinterpret_cast<uint32_t*>(take(kXcds * kCursorStride * 4));
   t.err = reinterpret_cast<uint32_t*>(take(4));
   return t;
 }
@@ -1657,7 +1669,8 @@ int64_t grouped_scratch_bytes(uint64_t max_n) {
   const uint64_t nblk = std::max<uint64_t>(1, (max_n + kSortSpan - 1) / kSortSpan);
   auto r = [](uint64_t b) { return (b + 255) / 256 * 256; };
   return (int64_t)(r(max_n * sizeof(SortGroup)) + r(max_n * 4) + r(kSortGroups * nblk * 8) +
-                   r((uint64_t)scan_tmp_elems((int64_t)(kSortGroups * nblk)) * 8) + r(kXcds * 4) + r(4) + 256);
+                   r((uint64_t)scan_tmp_elems((int64_t)(kSortGroups * nblk)) * 8) + r(kXcds * kCursorStride * 4) +
+                   r(4) + 256);
 }
 
 // Block b counts the groups of samples [b * kSortSpan, (b + 1) * kSortSpan) into
@@ -1666,7 +1679,7 @@ int64_t grouped_scratch_bytes(uint64_t max_n) {
 template <int S>
 __global__ __launch_bounds__(256) void k_sort_count(uint64_t seed, uint64_t k0, uint64_t n, SortScratch t) {
   __shared__ uint32_t hist[kSortGroups];
-  if (blockIdx.x == 0 && threadIdx.x < kXcds) t.cursors[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < kXcds) t.cursors[threadIdx.x * kCursorStride] = 0;
   for (int g = threadIdx.x; g < kSortGroups; g += blockDim.x) hist[g] = 0;
   __syncthreads();
   const uint64_t lo = (uint64_t)blockIdx.x * kSortSpan;
@@ -1764,7 +1777,7 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
     const uint32_t x = (uint32_t)((blockIdx.x + step) % kXcds);
     const uint64_t lo = start(x * per_xcd), hi = start((x + 1) * per_xcd);
     for (;;) {
-      if (tid == 0) s_win = atomicAdd(&t.cursors[x], 1u);
+      if (tid == 0) s_win = atomicAdd(&t.cursors[x * kCursorStride], 1u);
       __syncthreads();
       const uint64_t p = lo + (uint64_t)s_win * window;
       __syncthreads();

@@ -104,11 +104,11 @@ def test_valid_graph_creates_and_samples_like_the_oracle(base):
     assert (heads % 256 == 0).any()
 
 
-def _cases(rp, col):
+def _cases(rp, col, positions=None):
     nnz = len(col)
     heads = set(int(x) for x in rp[:-1][np.diff(rp) > 0])
     row_of = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
-    for e in _positions(rp, nnz)[::3]:
+    for e in (_positions(rp, nnz)[::3] if positions is None else positions):
         v = int(row_of[e])
         c = col.copy()
         if e not in heads:
@@ -142,3 +142,19 @@ def test_defects_at_span_edges(base):
         assert _create_status(r, c) == want, (name, moss.STATUS[want])
         n_cases += 1
     assert n_cases > 150
+
+
+def test_trailing_rows_without_entries(base):
+    """The same graph with 5,000 more nodes that have no edges, after the last row with
+    entries: valid as it is, and defects in its last span are still found."""
+    rp, col, _ = base
+    rp2 = np.concatenate([rp, np.full(5000, rp[-1], np.int32)])
+    assert _create_status(rp2, col) == moss.MOSS_OK
+    nnz = len(col)
+    n_cases = 0
+    for name, r, c in _cases(rp2, col, [nnz - 1, nnz - 2, (nnz - 1) // 256 * 256, (nnz - 1) // 256 * 256 + 1]):
+        want = expected_status(r, c)
+        assert want != moss.MOSS_OK, name
+        assert _create_status(r, c) == want, (name, moss.STATUS[want])
+        n_cases += 1
+    assert n_cases >= 16

@@ -3,8 +3,9 @@ ACC_check) must equal the oracle's; each row guide must follow its definition fr
 prefix read back: for a row with d >= 64, g = floor(log2 d) - 1, total T and
 s = max(0, bitlength(T) - g), entry b is the first i with A[i] > b * 2^s, else d - 1.
 Graphs have rows crossing several 256-entry spans (hubs, one over 234 spans), rows
-starting exactly at span boundaries, runs of rows without entries, rows whose weights
-are all zero and rows of one or two entries between hubs."""
+starting exactly at span boundaries, runs of rows without entries (also after the last
+row with entries), rows whose weights are all zero and rows of one or two entries
+between hubs."""
 import numpy as np
 import pytest
 
@@ -45,8 +46,18 @@ def _big_hub():
     return gg.from_edges(n, edges, "big hub")
 
 
+def _trailing_empty():
+    """Edges only among the first 2,500 of 9,000 nodes (a hub among them): 6,500 rows
+    without entries after the last one with entries."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    edges = [(0, int(x)) for x in rng.choice(np.arange(1, 2500), 900, replace=False)]
+    a, b = rng.integers(1, 2500, 6000), rng.integers(1, 2500, 6000)
+    edges += [(int(x), int(y)) for x, y in zip(a, b) if x != y]
+    return gg.from_edges(9000, edges, "trailing empty rows")
+
+
 GRAPHS = [_hubs_and_gaps(), gg.chung_lu(5000, 40000, 2.1, 900, 12), gg.star(3000), gg.wheel(700),
-          gg.complete_bipartite(3, 900), gg.complete(90), _big_hub()]
+          gg.complete_bipartite(3, 900), gg.complete(90), _big_hub(), _trailing_empty()]
 
 
 def expected_guides(rp, acc):
