@@ -161,10 +161,11 @@ void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int
   int b = t.threads_per_block ? (int)t.threads_per_block : 256;
   int per_cu = t.blocks_per_cu ? (int)t.blocks_per_cu : 0;
   if (per_cu == 0) {
-    // grouped launches keep a narrow node range per L2: 20 waves per CU, 16 once the
-    // tables are beyond the MALL
+    // grouped launches: 28 waves per CU (n = 1e5, m = 1e6, MOSS-4 for 1e7 samples,
+    // 12 / 16 / 20 / 24 / 28 / 32 waves: 0.687 / 0.602 / 0.559 / 0.542 / 0.538 / 0.540
+    // ms; n = 1e6, m = 1e7, T-5 for 5e7: 6.14 / 5.71 / 5.61 / 5.60 / 5.61 / 5.62 ms)
     const uint64_t fp = sampling_footprint(g);
-    const int waves = grouped_schedule(g, nsamples) ? (fp > (256ull << 20) ? 16 : 20) : sampling_waves_per_cu(fp);
+    const int waves = grouped_schedule(g, nsamples) ? 28 : sampling_waves_per_cu(fp);
     const int cap = std::max(1, std::min(sample_kernel_blocks_per_cu(sampler, b), 8));
     per_cu = std::max(1, std::min(cap, waves / (b / 64)));
   }
