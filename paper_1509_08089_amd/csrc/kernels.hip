@@ -1035,16 +1035,26 @@ int edge_hash_bits(int64_t m) {
   return bits;
 }
 
-// Edge filter: 2^bits 64-bit words with at least kFilterBitsPerEdge bits per edge.
-// A sparse filter wins: at 4 bits per edge about 16% of non-edges get through to the
-// hash set, but the filter is small enough (0.5 MB for a million edges) to stay in
-// L2; denser filters (8-16 bits) measured slower on every workload tried.
-constexpr double kFilterBitsPerEdge = 4.0;
+// Edge filter: 2^bits 64-bit words, at least 8 bits per edge while that stays within
+// 8 MB, else the larger of 8 MB and 4 bits per edge.  At 8.4 bits per edge about 2% of
+// non-edges get through to the hash set, at 4.2 about 14%.  Measured with the grouped
+// schedule: n = 1e5, m = 1e6 (MOSS-4, 1e7 samples), 0.5 MB of filter (4.2 bits) 0.560
+// ms, 1 MB (8.4 bits) 0.514 ms; n = 1e6, m = 1e7 (T-5 / Path-5, 5e7 samples each), 8 MB
+// (6.7 bits) 5.61 / 8.06 ms, 16 MB (13.4 bits) 6.09 / 8.39 ms, 4 MB (3.4 bits) 5.85 /
+// 8.31 ms.  Past a few MB the filter no longer stays in the L2s and its own misses
+// cost more than the hash-set reads it saves.
+constexpr double kFilterBitsPerEdge = 8.0;
+constexpr double kFilterMinBitsPerEdge = 4.0;
+constexpr int kFilterCapBits = 20;  // 2^20 words = 8 MB
 
 int edge_filter_bits(int64_t m) {
-  int bits = 1;
-  while (bits < 34 && (double)(64ll << bits) < kFilterBitsPerEdge * (double)m) ++bits;
-  return bits;
+  auto bits_for = [m](double per_edge) {
+    int bits = 1;
+    while (bits < 34 && (double)(64ll << bits) < per_edge * (double)m) ++bits;
+    return bits;
+  };
+  const int bits = bits_for(kFilterBitsPerEdge);
+  return bits <= kFilterCapBits ? bits : std::max(kFilterCapBits, bits_for(kFilterMinBitsPerEdge));
 }
 
 // ---------------------------------------------------------------------------------
