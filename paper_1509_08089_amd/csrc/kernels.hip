@@ -1610,20 +1610,23 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
 // ---------------------------------------------------------------------------------
 // XCD-grouped sampling.  MI355X has 8 XCDs, each with its own 4 MB L2, and a launch's
 // workgroups go to the XCDs in turn (workgroup i to XCD i mod 8).  The node draw is
-// monotone in a sample's first random word, so the word's top 8 bits split the samples
-// into 256 groups of equal probability, each drawing v from one contiguous range of
-// nodes.  The samples of a chunk are counting-sorted by group (count per block, scan,
-// scatter), and in k_sample_sorted XCD x owns groups 32x .. 32x+31, one contiguous
-// range of the sorted order, which its blocks take window after window: every L2
-// serves one eighth of the nodes, and over time a narrow node range of it.  Blocks
-// then help drain the other XCDs' ranges, so every sample is drawn exactly once
+// monotone in a sample's first random word, so the word's top 10 bits split the
+// samples into 1024 groups of equal probability, each drawing v from one contiguous
+// range of nodes.  The samples of a chunk are counting-sorted by group (count per
+// block, scan, scatter), and in k_sample_sorted XCD x owns groups 128x .. 128x+127,
+// one contiguous range of the sorted order, which its blocks take window after window:
+// every L2 serves one eighth of the nodes, and over time a narrow node range of it.
+// Blocks then help drain the other XCDs' ranges, so every sample is drawn exactly once
 // wherever the workgroups actually run, and each sample's outcome is the one the
 // plain kernel gives it.  Measured at n = 1e6, m = 1e7 (T-5 / Path-5): plain 10.4 /
 // 14.9 ms; 32 groups found by scanning group bytes 7.0 / 11.5 ms; sorted into 256
-// groups 6.8 / 10.0 ms.
+// groups 6.8 / 10.0 ms.  With the windows and cursors below, 256 / 512 / 1024 / 2048 /
+// 4096 groups: 5.61 / 5.58 / 5.61 / 5.80 / 6.27 ms (T-5), 8.06 / 7.75 / 7.62 / 7.68 /
+// 8.07 ms (Path-5), and at n = 1e5, m = 1e6 (MOSS-4, 1e7 samples) 0.51 / 0.51 / 0.51 /
+// 0.55 / 0.63 ms.
 // ---------------------------------------------------------------------------------
 constexpr int kXcds = 8;
-constexpr int kSortBits = 8;
+constexpr int kSortBits = 10;
 constexpr int kSortGroups = 1 << kSortBits;
 using SortGroup = std::conditional_t<(kSortBits <= 8), uint8_t, uint16_t>;  // a sample's group
 static_assert(kSortGroups % 256 == 0 && kSortBits <= 16, "whole groups per scatter thread");
