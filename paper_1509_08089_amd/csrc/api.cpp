@@ -574,6 +574,11 @@ moss_status create_common(int32_t n, int64_t nnz, uint32_t flags, void* hip_stre
 
 }  // namespace
 
+namespace moss {
+moss_status device_block_alloc(hipStream_t s, void** p, size_t bytes) { return dev_alloc_bytes(s, p, bytes); }
+void device_block_free(hipStream_t s, void*& p) { dev_free(s, p); }
+}  // namespace moss
+
 extern "C" {
 
 const char* moss_status_string(moss_status s) {

@@ -19,6 +19,18 @@ std::mutex g_runner_mu;
 std::map<int, std::unique_ptr<BatchRunner>> g_runners;
 
 constexpr uint32_t kDefaultTile = 4096;
+
+// Batched items sorted by group first: at least 2^20 samples on a graph whose sampled
+// bytes are past 32 MB (the tuning's schedule overrides: PLAIN never, XCD always).
+constexpr uint64_t kBatchSortMinSamples = 1ull << 20;
+constexpr uint64_t kBatchSortMinFootprint = 32ull << 20;
+constexpr uint64_t kBatchSortChunk = 1ull << 25;
+
+bool batch_sorted(const moss_graph* g, uint64_t n, uint32_t schedule) {
+  if (schedule == MOSS_SCHEDULE_PLAIN) return false;
+  if (schedule == MOSS_SCHEDULE_XCD) return n > 0;
+  return n >= kBatchSortMinSamples && sampling_footprint(g) >= kBatchSortMinFootprint;
+}
 }  // namespace
 
 Tuning current_tuning() {
@@ -188,7 +200,8 @@ moss_status BatchRunner::capture(int grid, int block) {
 }
 
 moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots, uint64_t* bins_out,
-                             double* device_ms, hipStream_t wait_on, uint32_t tile_samples, uint32_t blocks_per_cu) {
+                             double* device_ms, hipStream_t wait_on, uint32_t tile_samples, uint32_t blocks_per_cu,
+                             bool sort_large) {
   DeviceScope scope(device_);
   if (!scope.ok()) return MOSS_E_DEVICE;
   if (!stream_) {
@@ -217,6 +230,43 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     uint64_t cost;
   };
   std::vector<PendingTile> tiles;
+  // sorted items: their chunks' orders share one device block, the grouping passes one
+  // scratch block (a chunk at a time, in stream order)
+  struct SortChunk {
+    int sampler;
+    uint64_t seed, a, n, off;
+  };
+  std::vector<SortChunk> chunks;
+  uint64_t sorted_total = 0, max_chunk = 0;
+  for (const WorkItem& w : work) {
+    if (!sort_large || w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
+    if (!batch_sorted(w.g, w.k1 - w.k0, tune.schedule)) continue;
+    for (uint64_t a = w.k0; a < w.k1; a += kBatchSortChunk) {
+      const uint64_t n = std::min<uint64_t>(kBatchSortChunk, w.k1 - a);
+      chunks.push_back({w.sampler, w.seed, a, n, sorted_total});
+      sorted_total += n;
+      max_chunk = std::max(max_chunk, n);
+    }
+  }
+  void* orders = nullptr;
+  void* sort_scratch_block = nullptr;
+  struct Release {  // the blocks go back to the cache once the stream's work has finished
+    hipStream_t s;
+    void*& a;
+    void*& b;
+    ~Release() {
+      if (!a && !b) return;
+      (void)hipStreamSynchronize(s);
+      device_block_free(s, a);
+      device_block_free(s, b);
+    }
+  } release{stream_, orders, sort_scratch_block};
+  if (sorted_total > 0) {
+    if (device_block_alloc(stream_, &orders, (size_t)sorted_total * sizeof(uint32_t)) != MOSS_OK ||
+        device_block_alloc(stream_, &sort_scratch_block, (size_t)grouped_scratch_bytes(max_chunk)) != MOSS_OK)
+      return MOSS_E_NOMEM;
+  }
+  size_t next_chunk = 0;
   for (const WorkItem& w : work) {
     if (w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
     auto key = std::make_pair((const moss_graph*)w.g, w.sampler);
@@ -230,6 +280,30 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
       vi = it->second;
     }
     const uint64_t weight = (w.sampler == kMoss4 || w.sampler == kMoss4Min) ? 2 : 3;
+    if (next_chunk < chunks.size() && chunks[next_chunk].a == w.k0 && sort_large &&
+        batch_sorted(w.g, w.k1 - w.k0, tune.schedule)) {
+      // this item's chunks, in order: places [p, p + T) of each chunk's sorted order
+      for (; next_chunk < chunks.size() && chunks[next_chunk].a < w.k1; ++next_chunk) {
+        const SortChunk& c = chunks[next_chunk];
+        for (uint64_t p = 0; p < c.n; p += T) {
+          Tile t{};
+          t.view = vi;
+          t.sampler = (uint32_t)w.sampler;
+          t.out = w.slot;
+          t.seed = w.seed;
+          t.k0 = p;
+          t.k1 = std::min<uint64_t>(c.n, p + T);
+          t.order = static_cast<const uint32_t*>(orders) + c.off;
+          t.base = c.a;
+          tiles.push_back({t, (t.k1 - t.k0) * weight});
+        }
+        if (c.a + c.n >= w.k1) {
+          ++next_chunk;
+          break;
+        }
+      }
+      continue;
+    }
     for (uint64_t a = w.k0; a < w.k1; a += T) {
       const uint64_t b = std::min<uint64_t>(w.k1, a + T);
       Tile t{};
@@ -279,6 +353,11 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   if (e == hipSuccess && tbytes) e = hipMemcpyAsync(d_tiles_, p + vbytes, tbytes, hipMemcpyHostToDevice, stream_);
   if (e == hipSuccess) e = hipMemcpyAsync(d_ctl_, np, sizeof(uint32_t), hipMemcpyHostToDevice, stream_);
   if (e == hipSuccess) e = hipEventRecord(ev0_, stream_);
+  for (const SortChunk& c : chunks) {  // the grouping passes count in the timed work
+    if (e != hipSuccess) break;
+    e = launch_group_chunk(c.sampler, c.seed, c.a, c.n, sort_scratch_block, max_chunk, stream_,
+                           static_cast<uint32_t*>(orders) + c.off);
+  }
   if (e == hipSuccess) e = hipGraphLaunch(exec_, stream_);
   if (e == hipSuccess) e = hipEventRecord(ev1_, stream_);
   if (e == hipSuccess && n_slots)
@@ -335,7 +414,8 @@ moss_status batch_impl(const moss_request* reqs, int32_t n, moss_result* out, hi
   std::lock_guard<std::mutex> lk(g_batch_mu);
   BatchRunner* runner = batch_runner(device);
   double ms = 0.0;
-  moss_status st = runner->run(work, (uint32_t)(2 * n), bins.data(), &ms, wait_on, tile_samples, blocks_per_cu);
+  moss_status st =
+      runner->run(work, (uint32_t)(2 * n), bins.data(), &ms, wait_on, tile_samples, blocks_per_cu, true);
   if (st != MOSS_OK) return st;
   for (int32_t i = 0; i < n; ++i) {
     moss_result& r = out[i];

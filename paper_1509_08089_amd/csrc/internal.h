@@ -133,6 +133,9 @@ void plain_launch_shape(const moss_graph* g, int sampler, uint64_t nsamples, int
 int sampling_waves_per_cu(uint64_t footprint_bytes);
 uint64_t sampling_footprint(const moss_graph* g);
 bool grouped_schedule(const moss_graph* g, uint64_t nsamples);
+// Device blocks from the library's stream-ordered cache (freed blocks are kept for reuse).
+moss_status device_block_alloc(hipStream_t s, void** p, size_t bytes);
+void device_block_free(hipStream_t s, void*& p);
 
 struct Tuning {
   uint32_t tile_samples = 0;

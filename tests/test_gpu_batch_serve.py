@@ -59,6 +59,41 @@ def test_batch_matches_oracle(graphs):
         assert_result_matches(r, og.estimate(k, ns, seed, flags, threads=8), float(lam))
 
 
+@pytest.mark.parametrize("tile", [256, 4096])
+def test_sorted_batch_equals_single_requests(graphs, tile):
+    """With the XCD schedule forced, every batched item is first sorted by group and its
+    tiles take the samples in that order (one item spans two 2^25-sample chunks): the
+    hits must equal each request run alone."""
+    gs, handles = graphs
+    reqs = _requests(handles, 30, 3) + [(handles[1].h, 4, (1 << 25) + 4097, 77, 0),
+                                        (handles[5].h, 5, 300_001, 78, 0), (handles[0].h, 4, 2, 79, 1)]
+    alone = [_alone(q) for q in reqs]
+    moss.moss_set_tuning(tile, 0, 0, moss.MOSS_SCHEDULE_XCD)
+    try:
+        for _ in range(2):
+            got = moss.moss_estimate_batch(reqs)
+            for a, b in zip(alone, got):
+                np.testing.assert_array_equal(a.hits_np, b.hits_np)
+                np.testing.assert_array_equal(a.estimate_np, b.estimate_np)
+    finally:
+        moss.moss_set_tuning(0, 0, 0, 0)
+
+
+def test_large_items_sorted_by_default():
+    """A graph past 32 MB of sampled bytes with items of 2^20 samples or more: sorted in
+    the batch by default; results equal the requests alone, mixed with small items."""
+    G = moss.Graph(gg.config_graph("C2"))
+    small = moss.Graph(gg.chung_lu(300, 1500, 2.4, 40, 31))
+    reqs = [(G.h, 4, 1_500_000, 11, 0), (G.h, 5, 1_200_001, 12, 1), (G.h, 4, 2_000_000, 13, moss.MOSS_K4_MIN),
+            (small.h, 4, 50_000, 14, 0), (G.h, 4, 1000, 15, 0)]
+    assert moss.moss_graph_get_info(G.h).sampling_bytes >= 32 << 20
+    alone = [_alone(q) for q in reqs]
+    got = moss.moss_estimate_batch(reqs)
+    for a, b in zip(alone, got):
+        np.testing.assert_array_equal(a.hits_np, b.hits_np)
+        np.testing.assert_array_equal(a.estimate_np, b.estimate_np)
+
+
 @pytest.mark.parametrize("tile,bpc", [(256, 1), (4096, 2), (65536, 8), (1 << 20, 4)])
 def test_tile_size_and_occupancy_do_not_change_results(graphs, tile, bpc):
     gs, handles = graphs
