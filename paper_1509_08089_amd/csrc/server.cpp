@@ -183,8 +183,10 @@ void moss_server::loop() {
     }
     lk.unlock();
     std::vector<uint64_t> bins(batch.size() * 2 * 22, 0);
+    // large chunks on large graphs go sorted by group, as in moss_estimate_batch
     moss_status st = work.empty() ? MOSS_OK
-                                  : runner->run(work, (uint32_t)(batch.size() * 2), bins.data(), nullptr, nullptr);
+                                  : runner->run(work, (uint32_t)(batch.size() * 2), bins.data(), nullptr, nullptr, 0,
+                                                0, true);
     lk.lock();
     ++iterations;
     // 3. account and complete
