@@ -120,18 +120,25 @@ uint64_t sampling_footprint(const moss_graph* g) {
 }
 
 // Whether a plain estimate on g draws its samples XCD-grouped (the tuning's schedule,
-// else by size): the sorting passes pay off once the sampled tables are well beyond
-// the L2 and the launch has millions of samples (measured: at n = 1e5, m = 1e6 and 1e7
-// samples the grouped kernel takes 0.68 ms against 0.73 ms; at n = 2e3, m = 1e4 it
-// loses; at n = 1e6, m = 1e7 it takes 15.6 ms against 25.2 ms for T-5 + Path-5).
+// else by size): the grouping passes pay off once the sampled tables are well beyond
+// the L2 and a sampler has enough samples.  Measured per estimate (plain / grouped):
+// n = 1e5, m = 1e6, MOSS-4 with 1e6 / 2e6 / 4e6 samples 0.106 / 0.171 / 0.316 ms
+// against 0.140 / 0.172 / 0.253 ms, T-5 + Path-5 with 2e6 / 4e6 samples 0.283 / 0.496
+// against 0.331 / 0.439 ms; n = 1e6, m = 1e7, T-5 + Path-5 with 1e6 / 2e6 / 4e6 samples
+// 0.299 / 0.557 / 1.06 against 0.361 / 0.504 / 0.760 ms.  So: at least 1.5 * 2^20
+// samples per sampler within the MALL, 2^19 beyond it; at n = 2e3, m = 1e4 grouping
+// loses at any size.
 constexpr uint64_t kGroupedMinFootprint = 32ull << 20;
-constexpr uint64_t kGroupedMinSamples = 1ull << 22;
+constexpr uint64_t kGroupedMinSamples = 3ull << 19;
+constexpr uint64_t kGroupedMinSamplesPastMall = 1ull << 19;
 
 bool grouped_schedule(const moss_graph* g, uint64_t nsamples) {
   const uint32_t sch = current_tuning().schedule;
   if (sch == MOSS_SCHEDULE_XCD) return true;
   if (sch == MOSS_SCHEDULE_PLAIN) return false;
-  return sampling_footprint(g) >= kGroupedMinFootprint && nsamples >= kGroupedMinSamples;
+  const uint64_t fp = sampling_footprint(g);
+  if (fp < kGroupedMinFootprint) return false;
+  return nsamples >= (fp > (256ull << 20) ? kGroupedMinSamplesPastMall : kGroupedMinSamples);
 }
 
 moss_status plan_estimate(int32_t k, uint64_t n_samples, uint32_t flags, EstimatePlan* p) {
