@@ -20,8 +20,9 @@ std::map<int, std::unique_ptr<BatchRunner>> g_runners;
 
 constexpr uint32_t kDefaultTile = 4096;
 
-// Batched items sorted by group first: at least 2^20 samples on a graph whose sampled
-// bytes are past 32 MB (the tuning's schedule overrides: PLAIN never, XCD always).
+// Batched items drawn by grouped launches of their own: at least 2^20 samples on a graph
+// whose sampled bytes are past 32 MB (the tuning's schedule overrides: PLAIN never, XCD
+// always).
 constexpr uint64_t kBatchSortMinSamples = 1ull << 20;
 constexpr uint64_t kBatchSortMinFootprint = 32ull << 20;
 constexpr uint64_t kBatchSortChunk = 1ull << 25;
@@ -230,45 +231,47 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     uint64_t cost;
   };
   std::vector<PendingTile> tiles;
-  // sorted items: their chunks' orders share one device block, the grouping passes one
-  // scratch block (a chunk at a time, in stream order)
+  // large items on large graphs run as grouped launches of their own after the
+  // persistent kernel (the plain path's grouping passes and sorted sampling kernel, one
+  // chunk at a time through one scratch block), adding into their histogram slots
   struct SortChunk {
     int sampler;
-    uint64_t seed, a, n, off;
+    uint64_t seed, a, n;
+    uint32_t slot, window;
+    int grid, block;
+    SamplerView view;
   };
   std::vector<SortChunk> chunks;
-  uint64_t sorted_total = 0, max_chunk = 0;
+  uint64_t max_chunk = 0;
   for (const WorkItem& w : work) {
     if (!sort_large || w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
     if (!batch_sorted(w.g, w.k1 - w.k0, tune.schedule)) continue;
+    const SamplerView view = sampler_view(w.g, w.sampler);
+    const uint32_t window = sort_window(sampling_footprint(w.g));
     for (uint64_t a = w.k0; a < w.k1; a += kBatchSortChunk) {
       const uint64_t n = std::min<uint64_t>(kBatchSortChunk, w.k1 - a);
-      chunks.push_back({w.sampler, w.seed, a, n, sorted_total});
-      sorted_total += n;
+      SortChunk c{w.sampler, w.seed, a, n, w.slot, window, 0, 0, view};
+      plain_launch_shape(w.g, w.sampler, n, &c.grid, &c.block);
+      chunks.push_back(c);
       max_chunk = std::max(max_chunk, n);
     }
   }
-  void* orders = nullptr;
   void* sort_scratch_block = nullptr;
-  struct Release {  // the blocks go back to the cache once the stream's work has finished
+  struct Release {  // the block goes back to the cache once the stream's work has finished
     hipStream_t s;
     void*& a;
-    void*& b;
     ~Release() {
-      if (!a && !b) return;
+      if (!a) return;
       (void)hipStreamSynchronize(s);
       device_block_free(s, a);
-      device_block_free(s, b);
     }
-  } release{stream_, orders, sort_scratch_block};
-  if (sorted_total > 0) {
-    if (device_block_alloc(stream_, &orders, (size_t)sorted_total * sizeof(uint32_t)) != MOSS_OK ||
-        device_block_alloc(stream_, &sort_scratch_block, (size_t)grouped_scratch_bytes(max_chunk)) != MOSS_OK)
-      return MOSS_E_NOMEM;
-  }
-  size_t next_chunk = 0;
+  } release{stream_, sort_scratch_block};
+  if (max_chunk > 0 &&
+      device_block_alloc(stream_, &sort_scratch_block, (size_t)grouped_scratch_bytes(max_chunk)) != MOSS_OK)
+    return MOSS_E_NOMEM;
   for (const WorkItem& w : work) {
     if (w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
+    if (sort_large && batch_sorted(w.g, w.k1 - w.k0, tune.schedule)) continue;  // a grouped launch
     auto key = std::make_pair((const moss_graph*)w.g, w.sampler);
     auto it = view_of.find(key);
     uint32_t vi;
@@ -280,30 +283,6 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
       vi = it->second;
     }
     const uint64_t weight = (w.sampler == kMoss4 || w.sampler == kMoss4Min) ? 2 : 3;
-    if (next_chunk < chunks.size() && chunks[next_chunk].a == w.k0 && sort_large &&
-        batch_sorted(w.g, w.k1 - w.k0, tune.schedule)) {
-      // this item's chunks, in order: places [p, p + T) of each chunk's sorted order
-      for (; next_chunk < chunks.size() && chunks[next_chunk].a < w.k1; ++next_chunk) {
-        const SortChunk& c = chunks[next_chunk];
-        for (uint64_t p = 0; p < c.n; p += T) {
-          Tile t{};
-          t.view = vi;
-          t.sampler = (uint32_t)w.sampler;
-          t.out = w.slot;
-          t.seed = w.seed;
-          t.k0 = p;
-          t.k1 = std::min<uint64_t>(c.n, p + T);
-          t.order = static_cast<const uint32_t*>(orders) + c.off;
-          t.base = c.a;
-          tiles.push_back({t, (t.k1 - t.k0) * weight});
-        }
-        if (c.a + c.n >= w.k1) {
-          ++next_chunk;
-          break;
-        }
-      }
-      continue;
-    }
     for (uint64_t a = w.k0; a < w.k1; a += T) {
       const uint64_t b = std::min<uint64_t>(w.k1, a + T);
       Tile t{};
@@ -353,12 +332,14 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   if (e == hipSuccess && tbytes) e = hipMemcpyAsync(d_tiles_, p + vbytes, tbytes, hipMemcpyHostToDevice, stream_);
   if (e == hipSuccess) e = hipMemcpyAsync(d_ctl_, np, sizeof(uint32_t), hipMemcpyHostToDevice, stream_);
   if (e == hipSuccess) e = hipEventRecord(ev0_, stream_);
-  for (const SortChunk& c : chunks) {  // the grouping passes count in the timed work
+  if (e == hipSuccess) e = hipGraphLaunch(exec_, stream_);  // clears every slot first
+  for (const SortChunk& c : chunks) {
     if (e != hipSuccess) break;
-    e = launch_group_chunk(c.sampler, c.seed, c.a, c.n, sort_scratch_block, max_chunk, stream_,
-                           static_cast<uint32_t*>(orders) + c.off);
+    e = launch_group_chunk(c.sampler, c.seed, c.a, c.n, sort_scratch_block, max_chunk, stream_);
+    if (e == hipSuccess)
+      e = launch_sample_chunk(c.sampler, c.view, c.seed, c.a, c.n, sort_scratch_block, max_chunk, c.window,
+                              d_bins_ + (uint64_t)c.slot * 22, nullptr, c.grid, c.block, stream_);
   }
-  if (e == hipSuccess) e = hipGraphLaunch(exec_, stream_);
   if (e == hipSuccess) e = hipEventRecord(ev1_, stream_);
   if (e == hipSuccess && n_slots)
     e = hipMemcpyAsync(h_bins_, d_bins_, (size_t)n_slots * 22 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream_);

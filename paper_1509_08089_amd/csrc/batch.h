@@ -28,9 +28,9 @@ class BatchRunner {
   // Runs every work item in one persistent launch; bins_out receives n_slots x 22
   // counters.  `wait_on` (may be null) is a stream whose queued work must finish
   // first.  tile_samples / blocks_per_cu of 0 use the current tuning.  With
-  // `sort_large`, items with many samples on graphs past the L2s are first sorted by
-  // group (the grouping passes of the plain grouped schedule) and their tiles take the
-  // samples in that order.
+  // `sort_large`, items with many samples on graphs past the L2s run instead as grouped
+  // launches of their own (the plain path's grouping passes and sorted sampling
+  // kernel), after the persistent kernel, adding into their histogram slots.
   moss_status run(const std::vector<WorkItem>& work, uint32_t n_slots, uint64_t* bins_out, double* device_ms,
                   hipStream_t wait_on, uint32_t tile_samples = 0, uint32_t blocks_per_cu = 0,
                   bool sort_large = false);

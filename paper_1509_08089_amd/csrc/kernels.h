@@ -63,14 +63,12 @@ constexpr int32_t kRowGuideMin = 64;
 
 // One unit of batched work: samples [k0, k1) of one sampler on one graph.
 struct Tile {
-  uint32_t view;          // index into the SamplerView array
-  uint32_t sampler;       // kMoss4 / kMoss4Min / kT5 / kPath5
-  uint32_t out;           // histogram slot (22 counters each)
+  uint32_t view;     // index into the SamplerView array
+  uint32_t sampler;  // kMoss4 / kMoss4Min / kT5 / kPath5
+  uint32_t out;      // histogram slot (22 counters each)
   uint32_t pad;
   uint64_t seed;
-  uint64_t k0, k1;        // sample indices, or places in `order` when it is set
-  const uint32_t* order;  // null, or a chunk's samples sorted by group: place p draws
-  uint64_t base;          // sample base + order[p]
+  uint64_t k0, k1;   // sample indices
 };
 
 hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], const uint8_t lut5p[64]);
@@ -199,12 +197,11 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
 // events; a scratch block serves one chunk at a time.  block must be 64, 128, 192 or 256
 // threads; class_out (may be null) receives the chunk's classes at [0, n).
 // `window`: sorted entries a block takes at a time (sort_window of the bytes the
-// samples read at random).  With order_out (n u32) the grouping passes write the sorted
-// order there instead of into the scratch block (for the batched launch's tiles).
+// samples read at random).
 int64_t grouped_scratch_bytes(uint64_t max_n);
 uint32_t sort_window(uint64_t footprint_bytes);
 hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n, void* scratch, uint64_t max_n,
-                              hipStream_t s, uint32_t* order_out = nullptr);
+                              hipStream_t s);
 hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed, uint64_t a, uint64_t n,
                                void* scratch, uint64_t max_n, uint32_t window, unsigned long long* hits,
                                uint8_t* class_out, int grid, int block, hipStream_t s);

@@ -1813,10 +1813,9 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
 }
 
 hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n, void* scratch, uint64_t max_n,
-                              hipStream_t s, uint32_t* order_out) {
+                              hipStream_t s) {
   if (n == 0 || n > max_n || max_n > (1ull << 31)) return hipErrorInvalidValue;
   SortScratch tc = sort_scratch(scratch, max_n);
-  if (order_out) tc.order = order_out;
   tc.nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
   const uint32_t nblk = tc.nblk;
   switch (sampler) {
@@ -1928,20 +1927,18 @@ __global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict_
     if (t >= n_tiles) break;
     const Tile tile = tiles[t];
     const SamplerView v = views[tile.view];
-    // a sorted tile's places map to sample indices through its chunk's order
-    auto index = [&](uint64_t p) -> uint64_t { return tile.order ? tile.base + tile.order[p] : p; };
     if (tile.sampler == kMoss4) {
-      for (uint64_t p = tile.k0 + tid; p < tile.k1; p += blockDim.x)
-        atomicAdd(&lb[wave][draw_moss4(v, lut4, tile.seed, index(p), nullptr)], 1u);
+      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
+        atomicAdd(&lb[wave][draw_moss4(v, lut4, tile.seed, k, nullptr)], 1u);
     } else if (tile.sampler == kMoss4Min) {
-      for (uint64_t p = tile.k0 + tid; p < tile.k1; p += blockDim.x)
-        count_sample(lb[wave], draw_moss4min(v, lut4, tile.seed, index(p), nullptr));
+      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
+        count_sample(lb[wave], draw_moss4min(v, lut4, tile.seed, k, nullptr));
     } else if (tile.sampler == kT5) {
-      for (uint64_t p = tile.k0 + tid; p < tile.k1; p += blockDim.x)
-        atomicAdd(&lb[wave][draw_t5(v, lut5t, tile.seed, index(p), nullptr)], 1u);
+      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
+        atomicAdd(&lb[wave][draw_t5(v, lut5t, tile.seed, k, nullptr)], 1u);
     } else {
-      for (uint64_t p = tile.k0 + tid; p < tile.k1; p += blockDim.x)
-        atomicAdd(&lb[wave][draw_path5(v, lut5p, tile.seed, index(p), nullptr)], 1u);
+      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
+        atomicAdd(&lb[wave][draw_path5(v, lut5p, tile.seed, k, nullptr)], 1u);
     }
     __syncthreads();
     if (tid < kBins) {

@@ -61,9 +61,9 @@ def test_batch_matches_oracle(graphs):
 
 @pytest.mark.parametrize("tile", [256, 4096])
 def test_sorted_batch_equals_single_requests(graphs, tile):
-    """With the XCD schedule forced, every batched item is first sorted by group and its
-    tiles take the samples in that order (one item spans two 2^25-sample chunks): the
-    hits must equal each request run alone."""
+    """With the XCD schedule forced, every batched item runs as grouped launches of its
+    own after the persistent kernel (one item spans two 2^25-sample chunks): the hits
+    must equal each request run alone."""
     gs, handles = graphs
     reqs = _requests(handles, 30, 3) + [(handles[1].h, 4, (1 << 25) + 4097, 77, 0),
                                         (handles[5].h, 5, 300_001, 78, 0), (handles[0].h, 4, 2, 79, 1)]
@@ -80,8 +80,9 @@ def test_sorted_batch_equals_single_requests(graphs, tile):
 
 
 def test_large_items_sorted_by_default():
-    """A graph past 32 MB of sampled bytes with items of 2^20 samples or more: sorted in
-    the batch by default; results equal the requests alone, mixed with small items."""
+    """A graph past 32 MB of sampled bytes with items of 2^20 samples or more: drawn by
+    grouped launches beside the persistent kernel by default; results equal the
+    requests alone, mixed with small items."""
     G = moss.Graph(gg.config_graph("C2"))
     small = moss.Graph(gg.chung_lu(300, 1500, 2.4, 40, 31))
     reqs = [(G.h, 4, 1_500_000, 11, 0), (G.h, 5, 1_200_001, 12, 1), (G.h, 4, 2_000_000, 13, moss.MOSS_K4_MIN),
