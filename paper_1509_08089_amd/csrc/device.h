@@ -14,6 +14,20 @@ constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
 
+// The 128-bit product a * b as four 32 x 32 -> 64-bit partial products, each one
+// multiply-add (v_mad_u64_u32); none of the partial sums exceeds 64 bits.  Spelled out
+// because the high half written as __umul64hi next to a 64-bit low product compiles to
+// about a third more multiplies (the Philox rounds are what the grouping pass spends
+// its time on).
+__device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a1 * b0 + (p >> 32);
+  const uint64_t u = (uint64_t)a0 * b1 + (uint32_t)t;
+  hi = (uint64_t)a1 * b1 + (t >> 32) + (u >> 32);
+  lo = (u << 32) | (uint32_t)p;
+}
+
 // Random words of block `blk` of sample `k`: counter (k, blk, 0, 0), key (seed, tag).
 __device__ __forceinline__ void philox_block(uint64_t k, uint64_t blk, uint64_t seed, uint64_t tag,
                                              uint64_t out[4]) {
@@ -25,8 +39,9 @@ __device__ __forceinline__ void philox_block(uint64_t k, uint64_t blk, uint64_t 
       k0 += kPhiloxW0;
       k1 += kPhiloxW1;
     }
-    const uint64_t hi0 = __umul64hi(kPhiloxM0, x0), lo0 = kPhiloxM0 * x0;
-    const uint64_t hi1 = __umul64hi(kPhiloxM1, x2), lo1 = kPhiloxM1 * x2;
+    uint64_t hi0, lo0, hi1, lo1;
+    mul_wide(x0, kPhiloxM0, hi0, lo0);
+    mul_wide(x2, kPhiloxM1, hi1, lo1);
     x0 = hi1 ^ x1 ^ k0;
     x1 = lo1;
     x2 = hi0 ^ x3 ^ k1;
