@@ -1649,15 +1649,51 @@ uint32_t sort_window(uint64_t footprint_bytes) { return footprint_bytes > (256ul
 // 5.84 / 8.38 -> 5.72 / 8.19 ms).
 constexpr uint32_t kCursorStride = 64;  // u32
 
+// The (block, group) count table is stored block-major, one 4 KB row per block, so that
+// the grouping pass writes and the sorting pass reads whole rows.  Its group-major
+// prefix (the place of each (block, group) run in the sorted order) is taken column by
+// column: the rows are cut into at most kSortRuns runs of consecutive blocks, each run
+// sums its rows per group, one wave per four groups scans those sums across the runs,
+// and each run then walks its rows again writing places.  All counts fit 32 bits (a
+// chunk has at most 2^31 samples).  Against a group-major table of 64-bit inclusive
+// counts (one strided 8-byte store and load per (block, group), through the general
+// three-kernel scan): n = 1e5, m = 1e6, MOSS-4 for 1e7 samples, sampling launch 0.493
+// -> 0.476 ms; n = 1e6, m = 1e7, T-5 / Path-5 for 5e7 samples each, 5.58 / 7.57 ->
+// 5.49 / 7.47 ms.
+constexpr uint32_t kSortRuns = 64;  // at most one run per lane of the scanning wave
+constexpr uint32_t kSortQuads = kSortGroups / 4;
+static_assert(kSortQuads == 256, "one group quad per thread of a 256-thread block");
+
 struct SortScratch {
   SortGroup* group;   // n: group of each sample
   uint32_t* order;    // n: sample offsets sorted by group
-  uint64_t* counts;   // kSortGroups * nblk: per (group, block) counts, then inclusive prefix
-  uint64_t* tmp;      // scan block sums
+  uint32_t* counts;   // nblk rows of kSortGroups: block b's count of group g at b * kSortGroups + g
+  uint32_t* place;    // same layout: where run (b, g) starts in the sorted order
+  uint32_t* rsum;     // kSortRuns rows of kSortGroups: per (run, group) sums, then their exclusive prefix
+  uint32_t* gtot;     // kSortGroups: samples per group
+  uint32_t* gstart;   // kSortGroups + 1: start of each group in the sorted order (the last is n)
   uint32_t* cursors;  // kXcds window cursors, kCursorStride apart
-  uint32_t* err;      // the scan's wrap flag (cannot fire: the counts sum to n)
-  uint32_t nblk;
+  uint32_t nblk;      // blocks (rows) of this chunk
+  uint32_t rows;      // rows per run
+  uint32_t runs;      // runs, <= kSortRuns
 };
+
+__device__ __forceinline__ uint4* quad_at(uint32_t* table, uint32_t row, uint32_t q) {
+  return reinterpret_cast<uint4*>(table + (size_t)row * kSortGroups) + q;
+}
+
+__device__ __forceinline__ void add4(uint4& a, const uint4& b) {
+  a.x += b.x;
+  a.y += b.y;
+  a.z += b.z;
+  a.w += b.w;
+}
+
+static void set_runs(SortScratch& t, uint64_t n) {
+  t.nblk = (uint32_t)std::max<uint64_t>(1, (n + kSortSpan - 1) / kSortSpan);
+  t.rows = (t.nblk + kSortRuns - 1) / kSortRuns;
+  t.runs = (t.nblk + t.rows - 1) / t.rows;
+}
 
 static SortScratch sort_scratch(void* base, uint64_t max_n) {
   SortScratch t;
@@ -1667,28 +1703,28 @@ static SortScratch sort_scratch(void* base, uint64_t max_n) {
     p += (bytes + 255) / 256 * 256;
     return q;
   };
-  t.nblk = (uint32_t)((max_n + kSortSpan - 1) / kSortSpan);
-  if (t.nblk == 0) t.nblk = 1;
+  set_runs(t, max_n);
   t.group = reinterpret_cast<SortGroup*>(take(max_n * sizeof(SortGroup)));
   t.order = reinterpret_cast<uint32_t*>(take(max_n * 4));
-  t.counts = reinterpret_cast<uint64_t*>(take((size_t)kSortGroups * t.nblk * 8));
-  t.tmp = reinterpret_cast<uint64_t*>(take((size_t)scan_tmp_elems((int64_t)kSortGroups * t.nblk) * 8));
+  t.counts = reinterpret_cast<uint32_t*>(take((size_t)kSortGroups * t.nblk * 4));
+  t.place = reinterpret_cast<uint32_t*>(take((size_t)kSortGroups * t.nblk * 4));
+  t.rsum = reinterpret_cast<uint32_t*>(take((size_t)kSortGroups * kSortRuns * 4));
+  t.gtot = reinterpret_cast<uint32_t*>(take((size_t)kSortGroups * 4));
+  t.gstart = reinterpret_cast<uint32_t*>(take((size_t)(kSortGroups + 1) * 4));
   t.cursors = reinterpret_cast<uint32_t*>(take(kXcds * kCursorStride * 4));
-  t.err = reinterpret_cast<uint32_t*>(take(4));
   return t;
 }
 
 int64_t grouped_scratch_bytes(uint64_t max_n) {
   const uint64_t nblk = std::max<uint64_t>(1, (max_n + kSortSpan - 1) / kSortSpan);
   auto r = [](uint64_t b) { return (b + 255) / 256 * 256; };
-  return (int64_t)(r(max_n * sizeof(SortGroup)) + r(max_n * 4) + r(kSortGroups * nblk * 8) +
-                   r((uint64_t)scan_tmp_elems((int64_t)(kSortGroups * nblk)) * 8) + r(kXcds * kCursorStride * 4) +
-                   r(4) + 256);
+  return (int64_t)(r(max_n * sizeof(SortGroup)) + r(max_n * 4) + 2 * r(kSortGroups * nblk * 4) +
+                   r(kSortGroups * kSortRuns * 4) + r(kSortGroups * 4) + r((kSortGroups + 1) * 4) +
+                   r(kXcds * kCursorStride * 4) + 256);
 }
 
-// Block b counts the groups of samples [b * kSortSpan, (b + 1) * kSortSpan) into
-// counts[g * nblk + b] (group-major, so the inclusive scan gives each (group, block)
-// its place in the sorted order).
+// Block b counts the groups of samples [b * kSortSpan, (b + 1) * kSortSpan) into row b
+// of the count table.
 template <int S>
 __global__ __launch_bounds__(256) void k_sort_count(uint64_t seed, uint64_t k0, uint64_t n, SortScratch t) {
   __shared__ uint32_t hist[kSortGroups];
@@ -1705,7 +1741,78 @@ __global__ __launch_bounds__(256) void k_sort_count(uint64_t seed, uint64_t k0, 
     atomicAdd(&hist[g], 1u);
   }
   __syncthreads();
-  for (int g = threadIdx.x; g < kSortGroups; g += blockDim.x) t.counts[(uint64_t)g * t.nblk + blockIdx.x] = hist[g];
+  for (int g = threadIdx.x; g < kSortGroups; g += blockDim.x) t.counts[(size_t)blockIdx.x * kSortGroups + g] = hist[g];
+}
+
+// Run r sums rows [r * rows, (r + 1) * rows) of the count table per group.  The rows'
+// loads go out 16 at a time.
+__global__ __launch_bounds__(256) void k_sort_runsum(SortScratch t) {
+  const uint32_t q = threadIdx.x;  // blockDim.x == kSortQuads
+  const uint32_t b0 = blockIdx.x * t.rows, b1 = min(t.nblk, b0 + t.rows);
+  uint4 s = make_uint4(0, 0, 0, 0);
+  for (uint32_t b = b0; b < b1; b += 16) {
+    uint4 c[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = b + k < b1 ? *quad_at(t.counts, b + k, q) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) add4(s, c[k]);
+  }
+  *quad_at(t.rsum, blockIdx.x, q) = s;
+}
+
+// One wave per four groups: lane r holds run r's sums and the wave scans them, leaving
+// each run's exclusive prefix in place and the groups' totals in gtot.  Two 32-bit sums
+// share a 64-bit lane value; neither half carries into the other, since every sum is at
+// most the chunk's sample count (< 2^32).
+__global__ __launch_bounds__(256) void k_sort_runscan(SortScratch t) {
+  const uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), r = (uint32_t)lane_id();
+  if (q >= kSortQuads) return;  // whole waves
+  const uint4 v = r < t.runs ? *quad_at(t.rsum, r, q) : make_uint4(0, 0, 0, 0);
+  const uint64_t lo = (uint64_t)v.x | ((uint64_t)v.y << 32), hi = (uint64_t)v.z | ((uint64_t)v.w << 32);
+  bool unused = false;
+  const uint64_t ilo = wave_inclusive_scan(lo, unused), ihi = wave_inclusive_scan(hi, unused);
+  const uint64_t elo = ilo - lo, ehi = ihi - hi;
+  if (r < t.runs)
+    *quad_at(t.rsum, r, q) = make_uint4((uint32_t)elo, (uint32_t)(elo >> 32), (uint32_t)ehi, (uint32_t)(ehi >> 32));
+  if (r == t.runs - 1)
+    *quad_at(t.gtot, 0, q) = make_uint4((uint32_t)ilo, (uint32_t)(ilo >> 32), (uint32_t)ihi, (uint32_t)(ihi >> 32));
+}
+
+// Each run block first turns the group totals into group starts (a block scan; block 0
+// stores them, with n after the last), then walks its rows: the place of run (b, g) is
+// g's start, plus the samples of g in earlier runs, plus those in the run's earlier rows.
+__global__ __launch_bounds__(256) void k_sort_place(uint64_t n, SortScratch t) {
+  __shared__ uint32_t wsum[4];
+  const uint32_t q = threadIdx.x;  // blockDim.x == kSortQuads
+  const int lane = lane_id(), wave = (int)(q >> 6);
+  const uint4 tot = *quad_at(t.gtot, 0, q);
+  const uint32_t mine = tot.x + tot.y + tot.z + tot.w;
+  bool unused = false;
+  const uint32_t incl = (uint32_t)wave_inclusive_scan((uint64_t)mine, unused);
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t off = incl - mine;
+  for (int w = 0; w < wave; ++w) off += wsum[w];
+  const uint4 start = make_uint4(off, off + tot.x, off + tot.x + tot.y, off + tot.x + tot.y + tot.z);
+  if (blockIdx.x == 0) {
+    *quad_at(t.gstart, 0, q) = start;
+    if (q == 0) t.gstart[kSortGroups] = (uint32_t)n;
+  }
+  uint4 run = *quad_at(t.rsum, blockIdx.x, q);
+  add4(run, start);
+  const uint32_t b0 = blockIdx.x * t.rows, b1 = min(t.nblk, b0 + t.rows);
+  for (uint32_t b = b0; b < b1; b += 16) {
+    uint4 c[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c[k] = b + k < b1 ? *quad_at(t.counts, b + k, q) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (b + k < b1) {
+        *quad_at(t.place, b + k, q) = run;
+        add4(run, c[k]);
+      }
+    }
+  }
 }
 
 // The same blocks place their samples.  A block first sorts its span by group in LDS
@@ -1726,17 +1833,15 @@ __global__ __launch_bounds__(256) void k_sort_scatter(uint64_t n, SortScratch t)
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;  // blockDim.x == 256
   const uint64_t lo = (uint64_t)blockIdx.x * kSortSpan;
   const uint32_t len = (uint32_t)(n < lo + kSortSpan ? n - lo : kSortSpan);
-  // the block's share of each of this thread's groups: [inclusive count before it, its
-  // inclusive count) (a chunk has at most 2^31 samples, so the places fit 32 bits)
+  // the block's share of each of this thread's groups: its place and its size
   uint32_t size[kPerThread];
   uint32_t mine = 0;
 #pragma unroll
   for (int j = 0; j < kPerThread; ++j) {
     const uint32_t g = (uint32_t)tid * kPerThread + j;
-    const uint64_t idx = (uint64_t)g * t.nblk + blockIdx.x;
-    const uint64_t before = idx ? t.counts[idx - 1] : 0;
-    base[g] = (uint32_t)before;
-    size[j] = (uint32_t)(t.counts[idx] - before);
+    const size_t idx = (size_t)blockIdx.x * kSortGroups + g;
+    base[g] = t.place[idx];
+    size[j] = t.counts[idx];
     mine += size[j];
   }
   if (len == kSortSpan) {  // whole span: 16-byte loads
@@ -1781,10 +1886,8 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
   for (int i = tid; i < nw * (kBins + 2); i += blockDim.x) bins[i / (kBins + 2)][i % (kBins + 2)] = 0;
   load_lut<S>(lut);
   __syncthreads();
-  // start of group g in the sorted order: the inclusive count through all earlier groups
-  auto start = [&](uint32_t g) -> uint64_t {
-    return g == 0 ? 0ull : (g >= (uint32_t)kSortGroups ? n : t.counts[(uint64_t)g * t.nblk - 1]);
-  };
+  // start of group g in the sorted order
+  auto start = [&](uint32_t g) -> uint64_t { return g >= (uint32_t)kSortGroups ? n : (uint64_t)t.gstart[g]; };
   const uint32_t per_xcd = kSortGroups / kXcds;
   for (int step = 0; step < kXcds; ++step) {
     const uint32_t x = (uint32_t)((blockIdx.x + step) % kXcds);
@@ -1816,7 +1919,7 @@ hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n
                               hipStream_t s) {
   if (n == 0 || n > max_n || max_n > (1ull << 31)) return hipErrorInvalidValue;
   SortScratch tc = sort_scratch(scratch, max_n);
-  tc.nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
+  set_runs(tc, n);
   const uint32_t nblk = tc.nblk;
   switch (sampler) {
     case kMoss4: hipLaunchKernelGGL(k_sort_count<kMoss4>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
@@ -1825,13 +1928,9 @@ hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n
     case kPath5: hipLaunchKernelGGL(k_sort_count<kPath5>, dim3(nblk), dim3(256), 0, s, seed, a, n, tc); break;
     default: return hipErrorInvalidValue;
   }
-  ScanSet set{};
-  set.data[0] = tc.counts;
-  set.tmp[0] = tc.tmp;
-  set.err_bit[0] = 0;
-  set.count = 1;
-  hipError_t e = launch_scans(set, (int64_t)kSortGroups * nblk, tc.err, s);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_runsum, dim3(tc.runs), dim3(kSortQuads), 0, s, tc);
+  hipLaunchKernelGGL(k_sort_runscan, dim3(kSortQuads / 4), dim3(256), 0, s, tc);
+  hipLaunchKernelGGL(k_sort_place, dim3(tc.runs), dim3(kSortQuads), 0, s, n, tc);
   hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(256), 0, s, n, tc);
   return hipGetLastError();
 }
@@ -1843,7 +1942,7 @@ hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed,
       window == 0)
     return hipErrorInvalidValue;
   SortScratch tc = sort_scratch(scratch, max_n);
-  tc.nblk = (uint32_t)((n + kSortSpan - 1) / kSortSpan);
+  set_runs(tc, n);
   // no more blocks than windows (each block visits every cursor once at least), a
   // multiple of the XCD count so that every XCD gets its share of blocks
   const uint64_t wins = (n + window - 1) / window;

@@ -72,6 +72,24 @@ def test_grouped_across_chunks(mid, schedule):
     assert int(b.sum()) == n
 
 
+def test_grouped_classes_over_many_count_rows(mid, schedule):
+    """Past 64 blocks of 8192 samples the grouping passes sum several count rows per run
+    before scanning across runs (here 66 rows in 33 runs); every sample must still be
+    drawn exactly once, with the outcome the plain launch gives it."""
+    G = moss.Graph(mid)
+    k0, n = 11, 65 * 8192 + 333
+    out = []
+    for sch in (moss.MOSS_SCHEDULE_PLAIN, moss.MOSS_SCHEDULE_XCD):
+        schedule(sch)
+        cls = torch.full((n,), 255, dtype=torch.uint8, device="cuda")
+        hits = G.sample_range(moss.MOSS_SAMPLER_MOSS4, 4, k0, k0 + n, cls)
+        out.append((hits, cls.cpu().numpy()))
+    (ha, ca), (hb, cb) = out
+    assert (ca != 255).all()
+    np.testing.assert_array_equal(ca, cb)
+    np.testing.assert_array_equal(ha, hb)
+
+
 def test_tiny_and_empty_ranges(small, schedule):
     G, og = moss.Graph(small), oracle.Graph(small)
     schedule(moss.MOSS_SCHEDULE_XCD)
