@@ -920,7 +920,8 @@ __global__ __launch_bounds__(256) void k_rank_local(int64_t n_items, const uint6
     for (int c = 0; c < kItem / 64; ++c) {
       const int32_t e = it.e0 + c * 64 + lane;
       if (e >= it.e1) continue;
-      rank32[2 * (int64_t)e] = above[c];
+      // the mirror rank is written later, by the entry's upper partner; zero meanwhile
+      reinterpret_cast<uint2*>(rank32)[e] = make_uint2(above[c], 0u);
       if (single) col_rank[it.r0 + (int32_t)above[c]] = x[c];
       else keys[it.e0 + (int32_t)above[c]] = k[c];
     }
@@ -983,7 +984,15 @@ __global__ __launch_bounds__(256) void k_rank_mirror(int64_t n_items, const uint
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
     const ItemRange it = item_range(items, rp, i);
-    for (int32_t e = it.e0 + lane; e < it.e1; e += 64) {
+    // Only entries (v, x) with x >= v search: each finds its partner (x, v) and writes
+    // both mirror ranks.  The row is ascending, so they are the piece's tail.
+    int32_t s0 = it.e0, s1 = it.e1;
+    while (s0 < s1) {  // wave-uniform: first entry of the piece not below v
+      const int32_t mid = s0 + ((s1 - s0) >> 1);
+      if (col[mid] < it.v) s0 = mid + 1;
+      else s1 = mid;
+    }
+    for (int32_t e = s0 + lane; e < it.e1; e += 64) {
       const uint2 X = row_of(rec, col[e]);
       int32_t lo = (int32_t)X.x, hi = (int32_t)(X.x + X.y);
       while (lo < hi) {  // first entry of row x not below v
@@ -991,9 +1000,12 @@ __global__ __launch_bounds__(256) void k_rank_mirror(int64_t n_items, const uint
         if (col[mid] < it.v) lo = mid + 1;
         else hi = mid;
       }
-      // a symmetric CSR always holds (x, v); without it (unchecked input) the weight is 0
-      const bool found = lo < (int32_t)(X.x + X.y) && col[lo] == it.v;
-      rank32[2 * (int64_t)e + 1] = found ? rank32[2 * (int64_t)lo] : 0u;
+      // a symmetric CSR always holds (x, v); without it (unchecked input) the weight
+      // stays 0
+      if (lo < (int32_t)(X.x + X.y) && col[lo] == it.v) {
+        rank32[2 * (int64_t)e + 1] = rank32[2 * (int64_t)lo];
+        rank32[2 * (int64_t)lo + 1] = rank32[2 * (int64_t)e];
+      }
     }
   }
 }
