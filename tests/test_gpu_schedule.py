@@ -72,12 +72,14 @@ def test_grouped_across_chunks(mid, schedule):
     assert int(b.sum()) == n
 
 
-def test_grouped_classes_over_many_count_rows(mid, schedule):
+@pytest.mark.parametrize("n", [64 * 8192, 65 * 8192 + 333])
+def test_grouped_classes_over_many_count_rows(mid, schedule, n):
     """Past 64 blocks of 8192 samples the grouping passes sum several count rows per run
-    before scanning across runs (here 66 rows in 33 runs); every sample must still be
-    drawn exactly once, with the outcome the plain launch gives it."""
+    before scanning across runs (64 rows: one per run; 66 rows: two per run in 33 runs);
+    every sample must still be drawn exactly once, with the outcome the plain launch
+    gives it."""
     G = moss.Graph(mid)
-    k0, n = 11, 65 * 8192 + 333
+    k0 = 11
     out = []
     for sch in (moss.MOSS_SCHEDULE_PLAIN, moss.MOSS_SCHEDULE_XCD):
         schedule(sch)
