@@ -868,7 +868,8 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     // ranks (the row prefix array serves as their key scratch), the prefix of
     // d_{v,x} d_{x,v} with its row guides, check-Gamma_v, its scan and guide
     if (e == hipSuccess)
-      e = launch_rank_tables(g->n_items, g->items, g->rp, g->col, g->rec, g->acc_check, g->rank, g->col_rank, s);
+      e = launch_rank_tables(g->n_items, g->items, g->nnz, g->span_row, g->rp, g->col, g->rec, g->acc_check, g->rank,
+                             g->col_rank, s);
     if (e == hipSuccess) {
       t.rank = g->rank;
       t.acc_check = g->acc_check;

@@ -977,41 +977,72 @@ __global__ __launch_bounds__(256) void k_rank_merge(int64_t n_items, const uint6
   }
 }
 
-__global__ __launch_bounds__(256) void k_rank_mirror(int64_t n_items, const uint64_t* __restrict__ items,
+// Mirror ranks: the entry (v, x) with x >= v finds its partner (x, v) by a binary
+// search of row x and writes both entries' d_{x,v}.  A wave takes a 256-entry span of
+// the CSR, four entries a lane (their rows from the span's row starts), and runs the
+// lane's four searches in step, so their loads go out together.  A symmetric CSR
+// always holds the partner; without it (unchecked input) the weight stays 0.
+__global__ __launch_bounds__(256) void k_rank_mirror(int64_t nnz, const int32_t* __restrict__ span_row,
                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                      const uint4* __restrict__ rec, uint32_t* __restrict__ rank32) {
+  __shared__ __align__(16) uint32_t hist[4][kSpan];
+  constexpr int kPer = kSpanPer;
   const int lane = lane_id();
+  uint32_t* wh = hist[threadIdx.x >> 6];
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n_items; i += nwaves) {
-    const ItemRange it = item_range(items, rp, i);
-    // Only entries (v, x) with x >= v search: each finds its partner (x, v) and writes
-    // both mirror ranks.  The row is ascending, so they are the piece's tail.
-    int32_t s0 = it.e0, s1 = it.e1;
-    while (s0 < s1) {  // wave-uniform: first entry of the piece not below v
-      const int32_t mid = s0 + ((s1 - s0) >> 1);
-      if (col[mid] < it.v) s0 = mid + 1;
-      else s1 = mid;
+  const int64_t spans = (nnz + kSpan - 1) / kSpan;
+  for (int64_t sp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; sp < spans; sp += nwaves) {
+    const int64_t S = sp * kSpan;
+    int32_t c[kPer], row[kPer], lo[kPer], len[kPer], end[kPer];
+    bool head[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) c[k] = S + lane + 64 * k < nnz ? col[S + lane + 64 * k] : -1;
+    span_rows(rp, S, span_row[sp], span_row[sp + 1], wh, row, head);
+    uint2 X[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) X[k] = row_of(rec, c[k] >= row[k] ? c[k] : 0);  // 4 loads, one wait
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const bool up = c[k] >= row[k];  // x >= v; never past nnz, where c = -1
+      lo[k] = up ? (int32_t)X[k].x : 0;
+      len[k] = up ? (int32_t)X[k].y : 0;
+      end[k] = lo[k] + len[k];
     }
-    for (int32_t e = s0 + lane; e < it.e1; e += 64) {
-      const uint2 X = row_of(rec, col[e]);
-      int32_t lo = (int32_t)X.x, hi = (int32_t)(X.x + X.y);
-      while (lo < hi) {  // first entry of row x not below v
-        const int32_t mid = lo + ((hi - lo) >> 1);
-        if (col[mid] < it.v) lo = mid + 1;
-        else hi = mid;
+    for (;;) {  // first entry of row x not below v, four searches in step
+      bool more = false;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) more |= len[k] > 0;
+      if (!more) break;
+      int32_t probe[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) probe[k] = col[len[k] > 0 ? lo[k] + (len[k] >> 1) : 0];  // 4 loads, one wait
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        if (len[k] > 0) {
+          const int32_t half = len[k] >> 1;
+          if (probe[k] < row[k]) {
+            lo[k] += half + 1;
+            len[k] -= half + 1;
+          } else {
+            len[k] = half;
+          }
+        }
       }
-      // a symmetric CSR always holds (x, v); without it (unchecked input) the weight
-      // stays 0
-      if (lo < (int32_t)(X.x + X.y) && col[lo] == it.v) {
-        rank32[2 * (int64_t)e + 1] = rank32[2 * (int64_t)lo];
-        rank32[2 * (int64_t)lo + 1] = rank32[2 * (int64_t)e];
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int64_t e = S + lane + 64 * k;
+      if (c[k] >= row[k] && lo[k] < end[k] && col[lo[k]] == row[k]) {
+        rank32[2 * e + 1] = rank32[2 * (int64_t)lo[k]];
+        rank32[2 * (int64_t)lo[k] + 1] = rank32[2 * e];
       }
     }
   }
 }
 
-hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, const int32_t* rp, const int32_t* col,
-                              const uint4* rec, uint64_t* keys, uint2* rank, int32_t* col_rank, hipStream_t s) {
+hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, int64_t nnz, const int32_t* span_row,
+                              const int32_t* rp, const int32_t* col, const uint4* rec, uint64_t* keys, uint2* rank,
+                              int32_t* col_rank, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   const dim3 grid(item_grid(n_items)), block(256);
   uint32_t* rank32 = reinterpret_cast<uint32_t*>(rank);
@@ -1019,7 +1050,7 @@ hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, const int3
   const int merge_grid = (int)std::min<int64_t>(n_items, 65536);
   hipLaunchKernelGGL(k_rank_merge, dim3(merge_grid), dim3(kItem), 0, s, n_items, items, rp, col, rec, keys, rank32,
                      col_rank);
-  hipLaunchKernelGGL(k_rank_mirror, grid, block, 0, s, n_items, items, rp, col, rec, rank32);
+  hipLaunchKernelGGL(k_rank_mirror, dim3(spans_grid(nnz)), block, 0, s, nnz, span_row, rp, col, rec, rank32);
   return hipGetLastError();
 }
 
