@@ -157,7 +157,8 @@ hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStr
 
 // MOSS-4Min rank tables (Section 4.2.1, order of Section 3.2): for every entry (v, x),
 // rank[e] = {d_{v,x}, d_{x,v}}, and col_rank holds each row in descending order.
-// `keys` (nnz u64) is scratch: each piece's keys, sorted.  Needs the node records.
+// `keys` (nnz u64) is scratch: each piece's keys, sorted.  Needs the node records and
+// the first row of every 256-entry span of the CSR (`span_row`, spans + 1 entries).
 hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, int64_t nnz, const int32_t* span_row,
                               const int32_t* rp, const int32_t* col, const uint4* rec, uint64_t* keys, uint2* rank,
                               int32_t* col_rank, hipStream_t s);
