@@ -87,22 +87,46 @@ struct moss_server {
     return b;
   }
 
-  // Makes room for `need` bytes by evicting idle graphs other than `keep`; returns
-  // whether the budget now allows it.  Called with mu held.
-  bool make_room(uint64_t need, const moss_graph* keep) {
+  enum class Room { kOk, kWait, kNever };
+
+  // Makes room within the memory budget for building `mask` on ge's graph, with mu
+  // held: evicts the tables of idle graphs other than ge's (least recently used
+  // first), then, if ge's graph is idle, its own table sets that `mask` does not
+  // name.  kOk: the tables now fit.  kWait: what still stands in the way is held by
+  // running requests, or by a call of another caller on an idle graph (its claim
+  // failed), and will be released.  kNever: nothing left to evict.
+  Room make_room(GraphEntry& ge, uint32_t mask) {
     const uint64_t budget = cfg.mem_budget_bytes;
-    if (!budget) return true;
-    while (resident_bytes() + need > budget) {
+    if (!budget) return Room::kOk;
+    std::vector<char> held(graphs.size(), 0);  // idle graphs whose claim failed
+    bool waiting = false;
+    for (;;) {
+      if (resident_bytes() + moss::table_bytes_needed(ge.g, mask) <= budget) return Room::kOk;
       GraphEntry* victim = nullptr;
-      for (GraphEntry& e : graphs)
-        if (e.g != keep && e.active == 0 && e.g->built && (!victim || e.last_use < victim->last_use)) victim = &e;
-      if (!victim) return false;
+      for (size_t i = 0; i < graphs.size(); ++i) {
+        GraphEntry& e = graphs[i];
+        if (&e != &ge && !held[i] && e.active == 0 && e.g->built && (!victim || e.last_use < victim->last_use))
+          victim = &e;
+      }
+      uint32_t drop = MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN;
+      if (!victim && ge.active == 0 && (ge.g->built & ~mask)) {
+        victim = &ge;
+        drop = ge.g->built & ~mask;  // the sets this request needs stay
+      }
+      if (!victim) break;
       moss::GraphClaim claim(victim->g);
-      if (!claim.ok()) return false;
-      moss::free_graph_tables(victim->g, MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN);
+      if (!claim.ok()) {
+        held[(size_t)(victim - graphs.data())] = 1;
+        waiting = true;
+        if (victim == &ge) break;
+        continue;
+      }
+      moss::free_graph_tables(victim->g, drop);
       ++evictions;
     }
-    return true;
+    for (const GraphEntry& e : graphs)
+      if (e.active > 0 && e.g->table_bytes) waiting = true;
+    return waiting ? Room::kWait : Room::kNever;
   }
 
   void loop();
@@ -121,6 +145,7 @@ void moss_server::loop() {
       return;
     }
     // 1. admission
+    bool blocked = false;  // the oldest waiting request waits for memory to be released
     while (active.size() < cfg.max_slots && !pending.empty()) {
       std::shared_ptr<Req> r = pending.front();
       if (r->cancelled) {
@@ -139,7 +164,16 @@ void moss_server::loop() {
           finish(r, MOSS_E_ADMISSION);
           continue;
         }
-        if (!make_room(need, ge.g)) break;  // wait for running requests to release memory
+        const Room room = make_room(ge, mask);
+        if (room == Room::kNever) {
+          pending.pop_front();
+          finish(r, MOSS_E_ADMISSION);
+          continue;
+        }
+        if (room == Room::kWait) {  // running requests (or another caller) will release memory
+          blocked = true;
+          break;
+        }
         moss_status st;
         {
           moss::GraphClaim claim(ge.g);
@@ -161,8 +195,14 @@ void moss_server::loop() {
     }
     cv_done.notify_all();
     if (active.empty()) {
-      // nothing admissible now: wait for a new arrival or a stop
-      cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      if (blocked) {
+        // only a call of another caller on an idle graph holds the memory; its end is
+        // not signalled here, so look again shortly (the wait releases mu)
+        cv_work.wait_for(lk, std::chrono::milliseconds(1), [&] { return stop; });
+      } else {
+        // nothing waiting: wait for a new arrival or a stop
+        cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+      }
       continue;
     }
     // 2. next chunk of every admitted request

@@ -14,16 +14,13 @@ def rel_close(a, b, scale=0.0, tol=1e-12):
 
 
 def assert_result_matches(gpu: moss.moss_result, orc: oracle.Result, lam: float):
-    """Hits bit-exact; estimates and variances within 1e-12 relative (n_2 / eta_2 and
-    their variances relative to Lambda, whose subtraction cancels in double)."""
+    """Hits bit-exact; estimates and variances within 1e-12 relative.  The estimate of
+    n_2 / eta_2 is a difference taken from Lambda, which cancels in double, so its bound
+    is relative to max(|x|, Lambda); every variance is held to 1e-12 of its own size."""
     assert gpu.k == orc.k and gpu.n_motifs == orc.n_motifs
     assert [int(gpu.K[0]), int(gpu.K[1])] == orc.K
     np.testing.assert_array_equal(gpu.hits_np, orc.hits)
     for i in range(orc.n_motifs):
         scale = lam if i == 1 else 0.0
         assert rel_close(gpu.estimate[i], orc.estimate[i], scale), (i, gpu.estimate[i], orc.estimate[i])
-        vscale = 0.0
-        if i == 1:
-            vscale = max(abs(orc.variance[1]), 1e-300)
-        assert rel_close(gpu.variance[i], orc.variance[i], vscale, 1e-10 if i == 1 else 1e-12), \
-            (i, gpu.variance[i], orc.variance[i])
+        assert rel_close(gpu.variance[i], orc.variance[i]), (i, gpu.variance[i], orc.variance[i])

@@ -171,6 +171,65 @@ def test_server_memory_budget_evicts_and_rejects():
         moss.moss_server_destroy(srv)
 
 
+def _table_bytes(g, mask):
+    """Device bytes that building `mask` on a fresh copy of graph g adds."""
+    h = moss.Graph(g)
+    try:
+        before = h.info().device_bytes
+        h.build_tables(mask)
+        return h.info().device_bytes - before
+    finally:
+        h.close()
+
+
+def test_server_evicts_own_idle_tables():
+    """A budget that holds the 5-node tables alone but not beside the 4-node ones: after a
+    k=4 request, a k=5 request on the same graph must evict the graph's own idle 4-node
+    tables (not wait forever for memory no one will release), and the k=4 request after
+    it must evict the 5-node ones."""
+    g = gg.chung_lu(3000, 20000, 2.2, 300, 47)
+    b4, b5, b45 = (_table_bytes(g, m) for m in
+                   (moss.MOSS_TABLES_K4, moss.MOSS_TABLES_K5, moss.MOSS_TABLES_K4 | moss.MOSS_TABLES_K5))
+    budget = b5 + (b45 - b5) // 2
+    assert b4 <= budget and b5 <= budget < b45
+    h = moss.Graph(g)
+    srv = moss.moss_server_create(budget, 4, 10_000)
+    try:
+        gid = moss.moss_server_add_graph(srv, h.h)
+        for i, k in enumerate((4, 5, 4, 5)):
+            t = moss.moss_server_submit(srv, gid, k, 30_000, i + 1)
+            r = moss.moss_server_wait(srv, t, 60_000)
+            a = moss.Graph(g).estimate(k, 30_000, i + 1)
+            np.testing.assert_array_equal(r.hits_np, a.hits_np)
+            np.testing.assert_array_equal(r.estimate_np, a.estimate_np)
+        st = moss.moss_server_stats_get(srv)
+        assert st.evictions >= 3 and st.completed == 4 and st.table_bytes <= budget
+    finally:
+        moss.moss_server_destroy(srv)
+
+
+def test_server_refuses_sets_that_never_fit_together():
+    """MOSS-4 + MOSS-4Min needs the 4-node and the MOSS-4Min tables at once; with a budget
+    below their sum and the 4-node tables already resident, the request is refused with
+    MOSS_E_ADMISSION (no other graph or set can be evicted), and the server stays usable."""
+    g = gg.chung_lu(3000, 20000, 2.2, 300, 48)
+    both = _table_bytes(g, moss.MOSS_TABLES_K4 | moss.MOSS_TABLES_K4MIN)
+    h = moss.Graph(g)
+    srv = moss.moss_server_create(both - 1, 4, 10_000)
+    try:
+        gid = moss.moss_server_add_graph(srv, h.h)
+        r = moss.moss_server_wait(srv, moss.moss_server_submit(srv, gid, 4, 20_000, 1), 60_000)
+        np.testing.assert_array_equal(r.hits_np, moss.Graph(g).estimate(4, 20_000, 1).hits_np)
+        t = moss.moss_server_submit(srv, gid, 4, 20_000, 2, moss.MOSS_K4_MIN)
+        with pytest.raises(moss.MossError) as e:
+            moss.moss_server_wait(srv, t, 60_000)
+        assert e.value.status == moss.MOSS_E_ADMISSION
+        r = moss.moss_server_wait(srv, moss.moss_server_submit(srv, gid, 4, 20_000, 3), 60_000)
+        np.testing.assert_array_equal(r.hits_np, moss.Graph(g).estimate(4, 20_000, 3).hits_np)
+    finally:
+        moss.moss_server_destroy(srv)
+
+
 def test_server_cancel_and_timeout(graphs):
     gs, handles = graphs
     srv = moss.moss_server_create(0, 2, 1 << 16)

@@ -27,7 +27,7 @@ def test_estimate_to_precision_matches_oracle(k, flags, eps, delta, mask, cap):
     assert r.n_samples == K
     lam = og.totals()["lambda3" if k == 4 else "lambda4"]
     assert_result_matches(r, o, float(lam))
-    np.testing.assert_allclose(moss.moss_concentrations(r), oracle.concentrations(o), rtol=1e-11, atol=1e-15)
+    np.testing.assert_allclose(moss.moss_concentrations(r), oracle.concentrations(o), rtol=1e-12, atol=0)
 
 
 def test_estimate_to_precision_rejects_bad_arguments():

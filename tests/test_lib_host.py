@@ -56,11 +56,14 @@ def test_class_tables_match_oracle_classifier(sampler):
         assert int(lut[mask]) == oracle.classify(k, adj), (sampler, mask)
 
 
-def _rel_close(a, b, scale, tol=1e-12):
-    return abs(a - b) <= tol * max(abs(a), abs(b), scale, 1e-300)
+def _same(a, b):
+    """The library's finals and the oracle's evaluate the same written formulas in the
+    same order in double, so they must agree to the last bit (stricter than the 1e-12
+    relative bound the estimates are held to)."""
+    return a == b or (a != a and b != b)
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(100))
 def test_finals4_match_oracle(seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     K = int(rng.integers(1, 10**9))
@@ -76,12 +79,11 @@ def test_finals4_match_oracle(seed):
     moss.moss_finals(r)
     est, var = oracle.finals4(K, hits, gamma, lam)
     for i in range(6):
-        scale = float(lam) if i == 1 else 0.0
-        assert _rel_close(r.estimate[i], est[i], scale), (i, r.estimate[i], est[i])
-        assert _rel_close(r.variance[i], var[i], scale * scale / K if i == 1 else 0.0), (i, r.variance[i], var[i])
+        assert _same(r.estimate[i], est[i]), (i, r.estimate[i], est[i])
+        assert _same(r.variance[i], var[i]), (i, r.variance[i], var[i])
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(100))
 @pytest.mark.parametrize("mix", [moss.MOSS_MIX_POOLED, moss.MOSS_MIX_PAPER])
 def test_finals5_match_oracle(seed, mix):
     rng = np.random.Generator(np.random.PCG64(100 + seed))
@@ -101,12 +103,11 @@ def test_finals5_match_oracle(seed, mix):
     moss.moss_finals(r)
     est, var, _ = oracle.finals5(K1, K2, h1, h2, g1, g2, lam, mix)
     for i in range(21):
-        scale = float(lam) if i == 1 else 0.0
-        assert _rel_close(r.estimate[i], est[i], scale), (i, r.estimate[i], est[i])
-        assert _rel_close(r.variance[i], var[i], 0.0, 1e-11), (i, r.variance[i], var[i])
+        assert _same(r.estimate[i], est[i]), (i, r.estimate[i], est[i])
+        assert _same(r.variance[i], var[i]), (i, r.variance[i], var[i])
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(100))
 @pytest.mark.parametrize("mix", [moss.MOSS_MIX_POOLED, moss.MOSS_MIX_PAPER])
 def test_finals4_min_match_oracle(seed, mix):
     """MOSS-4 mixed with MOSS-4Min (reach-count bins in hits[1][7..9])."""
@@ -129,9 +130,8 @@ def test_finals4_min_match_oracle(seed, mix):
     moss.moss_finals(r)
     est, var = oracle.finals4min(K, h4, gamma, lam, Kc, hm[:10], gmin, mix)
     for i in range(6):
-        scale = float(lam) if i == 1 else 0.0
-        assert _rel_close(r.estimate[i], est[i], scale), (i, r.estimate[i], est[i])
-        assert _rel_close(r.variance[i], var[i], 0.0, 1e-11), (i, r.variance[i], var[i])
+        assert _same(r.estimate[i], est[i]), (i, r.estimate[i], est[i])
+        assert _same(r.variance[i], var[i]), (i, r.variance[i], var[i])
 
 
 def _pilot_pair(rng, n_motifs):
