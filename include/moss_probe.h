@@ -26,14 +26,17 @@ extern "C" {
  * output function of seed + i).  words >= 1. */
 int moss_probe_fill(uint64_t* buf, uint64_t words, uint64_t seed, void* stream);
 
-/* Dependent gathers: lane t of the launch (blocks x 256 lanes) starts at a place given
- * by its index and then, `steps` times, loads x = buf[j] and moves to
- * j = floor((x ^ salt_t) * words / 2^64), where salt_t is an odd per-lane constant (so
- * that lanes do not fall into one another's chains).  Lane t writes the sum of the
- * values it loaded to out[t] (out holds blocks * 256 words), which keeps the loads
- * live.  One load per step and lane: blocks * 256 * steps loads in all, each to a line
- * the lane picks at random.  1 <= blocks <= 2^20, 1 <= steps <= 2^20. */
-int moss_probe_gather(const uint64_t* buf, uint64_t words, uint32_t blocks, uint32_t steps,
+/* Dependent gathers: each lane t of the launch (blocks x 256 lanes) follows `chains`
+ * chains side by side.  Chain c starts at a place given by (t, c) and then, `steps`
+ * times, loads x = buf[j] and moves to j = floor((x ^ salt) * words / 2^64), where salt
+ * is an odd constant of the chain (so that chains do not fall into one another).  A
+ * chain's loads depend on one another, the chains of a lane do not, so a lane keeps
+ * `chains` loads in flight: with one chain the probe measures the latency-bound rate,
+ * with several the rate the memory system sustains for random lines.  Lane t writes
+ * the sum of the values it loaded to out[t] (out holds blocks * 256 words), which
+ * keeps the loads live.  blocks * 256 * chains * steps loads in all, each to a line
+ * picked at random.  1 <= blocks <= 2^20, 1 <= steps <= 2^20, chains in {1, 2, 4, 8}. */
+int moss_probe_gather(const uint64_t* buf, uint64_t words, uint32_t blocks, uint32_t steps, uint32_t chains,
                       uint64_t* out, void* stream);
 
 #ifdef __cplusplus

@@ -25,7 +25,7 @@ def lib():
             L = ctypes.CDLL(LIB_PATH)
             P, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
             L.moss_probe_fill.argtypes = [P, u64, u64, P]
-            L.moss_probe_gather.argtypes = [P, u64, u32, u32, P, P]
+            L.moss_probe_gather.argtypes = [P, u64, u32, u32, u32, P, P]
             for name in EXPORTED:
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
@@ -50,9 +50,10 @@ def moss_probe_fill(buf, seed: int, stream=None) -> None:
            "moss_probe_fill")
 
 
-def moss_probe_gather(buf, blocks: int, steps: int, out, stream=None) -> None:
-    """blocks x 256 lanes, each `steps` dependent loads over buf; out holds blocks * 256 words."""
+def moss_probe_gather(buf, blocks: int, steps: int, out, chains: int = 1, stream=None) -> None:
+    """blocks x 256 lanes, each following `chains` chains of `steps` dependent loads over
+    buf; out holds blocks * 256 words."""
     assert buf.is_cuda and buf.dtype.itemsize == 8 and buf.is_contiguous()
     assert out.is_cuda and out.dtype.itemsize == 8 and out.is_contiguous() and out.numel() >= blocks * 256
-    _check(lib().moss_probe_gather(ctypes.c_void_p(buf.data_ptr()), buf.numel(), blocks, steps,
+    _check(lib().moss_probe_gather(ctypes.c_void_p(buf.data_ptr()), buf.numel(), blocks, steps, chains,
                                    ctypes.c_void_p(out.data_ptr()), _stream(stream)), "moss_probe_gather")

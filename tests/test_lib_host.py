@@ -200,10 +200,12 @@ def test_probe_library_exports_and_rejects_bad_arguments():
     fake = P(4096)  # never dereferenced: every call below fails its argument checks first
     assert L.moss_probe_fill(None, 10, 1, None) == -1
     assert L.moss_probe_fill(fake, 0, 1, None) == -1
-    assert L.moss_probe_gather(None, 10, 1, 1, fake, None) == -1
-    assert L.moss_probe_gather(fake, 10, 1, 1, None, None) == -1
-    assert L.moss_probe_gather(fake, 0, 1, 1, fake, None) == -1
-    assert L.moss_probe_gather(fake, 10, 0, 1, fake, None) == -1
-    assert L.moss_probe_gather(fake, 10, (1 << 20) + 1, 1, fake, None) == -1
-    assert L.moss_probe_gather(fake, 10, 1, 0, fake, None) == -1
-    assert L.moss_probe_gather(fake, 10, 1, (1 << 20) + 1, fake, None) == -1
+    assert L.moss_probe_gather(None, 10, 1, 1, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 1, 1, 1, None, None) == -1
+    assert L.moss_probe_gather(fake, 0, 1, 1, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 0, 1, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, (1 << 20) + 1, 1, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 1, 0, 1, fake, None) == -1
+    assert L.moss_probe_gather(fake, 10, 1, (1 << 20) + 1, 1, fake, None) == -1
+    for chains in (0, 3, 5, 16):
+        assert L.moss_probe_gather(fake, 10, 1, 1, chains, fake, None) == -1
