@@ -87,7 +87,7 @@ def lib():
                                                     ctypes.POINTER(_Result), ctypes.POINTER(u64)]
             L.orc_estimate.argtypes = [P, ctypes.c_int, u64, u64, ctypes.c_int, ctypes.c_int,
                                        ctypes.POINTER(_Result)]
-            L.orc_count_cis.argtypes = [P, ctypes.c_int, P]
+            L.orc_count_cis.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
             L.orc_count4_exact.argtypes = [P, P]
             L.orc_line_count.argtypes = [P, ctypes.c_int, u64, u64, u64, ctypes.POINTER(ctypes.c_double)]
             _lib = L
@@ -220,9 +220,9 @@ class Graph:
             raise OracleError(st, "orc_estimate_to_precision")
         return Result(r), int(K.value)
 
-    def count_cis(self, k: int) -> np.ndarray:
+    def count_cis(self, k: int, threads: int = 1) -> np.ndarray:
         out = np.zeros(22, np.uint64)
-        st = lib().orc_count_cis(self._h, k, _ptr(out))
+        st = lib().orc_count_cis(self._h, k, threads, _ptr(out))
         if st != OK:
             raise OracleError(st, "orc_count_cis")
         return out

@@ -1082,20 +1082,31 @@ static void esu_extend(esu_state *st, int sz, int level, int ext_len, int32_t st
   }
 }
 
-int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]) {
-  if (!g || !counts || (k != 4 && k != 5)) return ORC_E_ARG;
-  memset(counts, 0, 22 * sizeof(uint64_t));
+/* One worker of the enumeration: the start vertices s = first, first + step, ... */
+typedef struct {
+  const orc_graph *g;
+  int k, first, step, status;
+  uint64_t counts[22];
+} esu_job;
+
+static void *esu_run(void *arg) {
+  esu_job *job = (esu_job *)arg;
+  const orc_graph *g = job->g;
   int32_t dmax = 0;
   for (int32_t v = 0; v < g->n; ++v) if (degree(g, v) > dmax) dmax = degree(g, v);
-  size_t cap = (size_t)k * (size_t)(dmax + 1) + 1;
+  size_t cap = (size_t)job->k * (size_t)(dmax + 1) + 1;
   esu_state st;
   memset(&st, 0, sizeof(st));
-  st.g = g; st.k = k; st.counts = counts;
+  st.g = g; st.k = job->k; st.counts = job->counts;
   for (int i = 0; i < 6; ++i) {
     st.ext[i] = (int32_t *)malloc(cap * sizeof(int32_t));
-    if (!st.ext[i]) { for (int j = 0; j < i; ++j) free(st.ext[j]); return ORC_E_NOMEM; }
+    if (!st.ext[i]) {
+      for (int j = 0; j < i; ++j) free(st.ext[j]);
+      job->status = ORC_E_NOMEM;
+      return NULL;
+    }
   }
-  for (int32_t s = 0; s < g->n; ++s) {
+  for (int32_t s = job->first; s < g->n; s += job->step) {
     int len = 0;
     for (int64_t e = g->rp[s]; e < g->rp[s + 1]; ++e)
       if (g->col[e] > s) st.ext[1][len++] = g->col[e];
@@ -1103,7 +1114,32 @@ int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]) {
     esu_extend(&st, 1, 1, len, s);
   }
   for (int i = 0; i < 6; ++i) free(st.ext[i]);
-  return ORC_OK;
+  job->status = ORC_OK;
+  return NULL;
+}
+
+/* Every CIS is enumerated exactly once, from its smallest vertex; the start vertices
+   are dealt to `nthreads` workers in turn and their counts added. */
+int orc_count_cis(const orc_graph *g, int k, int nthreads, uint64_t counts[22]) {
+  if (!g || !counts || (k != 4 && k != 5)) return ORC_E_ARG;
+  if (nthreads < 1) nthreads = 1;
+  esu_job *jobs = (esu_job *)calloc((size_t)nthreads, sizeof(esu_job));
+  pthread_t *tids = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+  if (!jobs || !tids) { free(jobs); free(tids); return ORC_E_NOMEM; }
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t].g = g; jobs[t].k = k; jobs[t].first = t; jobs[t].step = nthreads;
+  }
+  for (int t = 1; t < nthreads; ++t) pthread_create(&tids[t], NULL, esu_run, &jobs[t]);
+  esu_run(&jobs[0]);
+  for (int t = 1; t < nthreads; ++t) pthread_join(tids[t], NULL);
+  int status = ORC_OK;
+  memset(counts, 0, 22 * sizeof(uint64_t));
+  for (int t = 0; t < nthreads; ++t) {
+    if (jobs[t].status != ORC_OK) status = jobs[t].status;
+    for (int c = 0; c < 22; ++c) counts[c] += jobs[t].counts[c];
+  }
+  free(jobs); free(tids);
+  return status;
 }
 
 /* ------------------------------------------------------------------------ */

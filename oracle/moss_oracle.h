@@ -151,7 +151,7 @@ int orc_estimate_to_precision(const orc_graph *g, int k, int with_min, double ep
                               int mix, int nthreads, orc_result *res, uint64_t *final_samples);
 
 /* exact counts of k-node connected induced subgraphs per class (ESU enumeration) */
-int orc_count_cis(const orc_graph *g, int k, uint64_t counts[22]);
+int orc_count_cis(const orc_graph *g, int k, int nthreads, uint64_t counts[22]);
 
 /* exact counts n_1..n_6 (counts[1..6]) from non-induced pattern counts: 3-paths, 3-stars,
    4-cycles, triangles with a pendant, diamonds and 4-cliques, converted with the matrix of

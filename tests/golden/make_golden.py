@@ -9,7 +9,7 @@ the seeded input generators.
   exact_c2.json     exact 4-node counts of the C2 graph (non-induced patterns converted
                     through the containment matrix; enumeration is infeasible there)
 
-Usage: python tests/golden/make_golden.py [--skip-exact5]
+Usage: python tests/golden/make_golden.py [--skip-exact5] [--only lines|c1|c2] [--threads T]
 """
 from __future__ import annotations
 
@@ -45,15 +45,15 @@ def line_counts(samples: int) -> dict:
     return out
 
 
-def exact_c1(with5: bool) -> dict:
+def exact_c1(with5: bool, threads: int) -> dict:
     g = gg.config_graph("C1")
     og = oracle.Graph(g)
     t = time.time()
-    c4 = [int(x) for x in og.count_cis(4)[1:7]]
-    res = {"graph_sha256": g.sha256(), "n4": c4, "seconds4": round(time.time() - t, 1)}
+    c4 = [int(x) for x in og.count_cis(4, threads)[1:7]]
+    res = {"graph_sha256": g.sha256(), "n4": c4, "seconds4": round(time.time() - t, 1), "threads": threads}
     if with5:
         t = time.time()
-        res["eta5"] = [int(x) for x in og.count_cis(5)[1:22]]
+        res["eta5"] = [int(x) for x in og.count_cis(5, threads)[1:22]]
         res["seconds5"] = round(time.time() - t, 1)
     res.update(og.totals())
     return res
@@ -67,21 +67,27 @@ def exact_c2() -> dict:
     return {"graph_sha256": g.sha256(), "n4": n4, "seconds": round(time.time() - t, 1)}
 
 
+def write(name: str, obj: dict):
+    """Writes tests/golden/<name> only once its values are computed (atomically)."""
+    path = os.path.join(HERE, name)
+    with open(path + ".tmp", "w") as f:
+        json.dump(obj, f, indent=1)
+    os.replace(path + ".tmp", path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=200_000)
     ap.add_argument("--skip-exact5", action="store_true")
     ap.add_argument("--only", choices=["lines", "c1", "c2"], default=None)
+    ap.add_argument("--threads", type=int, default=os.cpu_count() or 1, help="threads of the enumeration")
     a = ap.parse_args()
     if a.only in (None, "lines"):
-        with open(os.path.join(HERE, "line_counts.json"), "w") as f:
-            json.dump(line_counts(a.samples), f, indent=1)
+        write("line_counts.json", line_counts(a.samples))
     if a.only in (None, "c1"):
-        with open(os.path.join(HERE, "exact_c1.json"), "w") as f:
-            json.dump(exact_c1(not a.skip_exact5), f, indent=1)
+        write("exact_c1.json", exact_c1(not a.skip_exact5, a.threads))
     if a.only in (None, "c2"):
-        with open(os.path.join(HERE, "exact_c2.json"), "w") as f:
-            json.dump(exact_c2(), f, indent=1)
+        write("exact_c2.json", exact_c2())
 
 
 if __name__ == "__main__":

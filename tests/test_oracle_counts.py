@@ -20,6 +20,8 @@ def test_enumeration_matches_brute_force(g, k):
     got = oracle.Graph(g).count_cis(k)
     want = pins.brute_counts(g, k)
     assert [int(x) for x in got] == want
+    for threads in (2, 3, 16):  # start vertices dealt to several workers: the same counts
+        assert [int(x) for x in oracle.Graph(g).count_cis(k, threads)] == want
 
 
 @pytest.mark.parametrize("n", [5, 6, 8])
