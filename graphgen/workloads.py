@@ -17,10 +17,12 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
 from .chung_lu import chung_lu
+from .csr import CSR
 
 
 @dataclasses.dataclass(frozen=True)
@@ -32,8 +34,23 @@ class GraphSpec:
     seed: int
 
     def build(self):
-        return chung_lu(self.n, self.m, self.beta, self.dmax, self.seed,
-                        name=f"CL(n={self.n},m={self.m},beta={self.beta},dmax={self.dmax},seed={self.seed})")
+        """The graph on the host.  With MOSS_GRAPH_CACHE naming a directory, the CSR is
+        kept there as an .npz after the first build and read back by later builds."""
+        name = f"CL(n={self.n},m={self.m},beta={self.beta},dmax={self.dmax},seed={self.seed})"
+        cache = os.environ.get("MOSS_GRAPH_CACHE")
+        path = None
+        if cache:
+            path = os.path.join(cache, f"cl_{self.n}_{self.m}_{self.beta}_{self.dmax}_{self.seed}.npz")
+            if os.path.exists(path):
+                with np.load(path) as z:
+                    return CSR(z["row_ptr"], z["col"], name)
+        g = chung_lu(self.n, self.m, self.beta, self.dmax, self.seed, name=name)
+        if path:
+            os.makedirs(cache, exist_ok=True)
+            tmp = path + ".tmp.npz"
+            np.savez(tmp, row_ptr=g.row_ptr, col=g.col)
+            os.replace(tmp, path)
+        return g
 
     def build_device(self, device="cuda"):
         """(row_ptr, col) int32 tensors generated on the device (see chung_lu_device)."""
