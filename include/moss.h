@@ -54,7 +54,8 @@ typedef enum {
   MOSS_E_BUSY = -10,       /* another call on the same graph is in flight */
   MOSS_E_TIMEOUT = -11,    /* server wait timed out (the request keeps running) */
   MOSS_E_CANCELLED = -12,  /* server request cancelled or server shut down */
-  MOSS_E_ADMISSION = -13   /* server cannot ever admit the request (memory budget) */
+  MOSS_E_ADMISSION = -13,  /* server cannot ever admit the request (memory budget) */
+  MOSS_E_TOO_LARGE = -14   /* more samples than moss_sample_range_noalloc's fixed scratch holds */
 } moss_status;
 
 /* sampler ids (also the Philox key tag of each sampler) */
@@ -225,6 +226,30 @@ moss_status moss_estimate(moss_graph *g, int32_t k, uint64_t n_samples, uint64_t
    gives exactly the same total. */
 moss_status moss_sample_range(moss_graph *g, int32_t sampler, uint64_t seed, uint64_t k0,
                               uint64_t k1, uint8_t *d_class_out, uint64_t hits[22]);
+
+/* ---- calls that allocate nothing -------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture or in a
+ * tight serving loop, and harnesses that forbid hipMalloc.
+ *
+ * moss_sample_range_noalloc: moss_sample_range (same arguments, same hits and classes,
+ * same kernels) with no allocation of any kind.
+ *  - The sampler's tables must already be built (moss_build_tables): MOSS_E_NOT_BUILT
+ *    otherwise.  Hits go through the graph's own buffers, made at its creation.
+ *  - k1 - k0 <= MOSS_NOALLOC_MAX_SAMPLES (2^22), else MOSS_E_TOO_LARGE.  Larger ranges
+ *    go as several calls; their hits add up to those of the whole range.
+ *  - When the samples run XCD-grouped (moss_tuning.schedule), their sorting scratch
+ *    (each sample's group and sorted place, per-block group counts, window cursors) is a
+ *    fixed device array of MOSS_NOALLOC_SCRATCH_BYTES (32 MiB) inside the library.  Each
+ *    device holds its own copy from the library's load until the process ends, and the
+ *    array keeps the last call's contents, which no call reads before writing.  Calls on
+ *    one device share that array: the library lets one of them use it at a time (a call
+ *    waits while another, on any graph of the device, runs), so calls that would overlap
+ *    on one device run one after the other.
+ *  - Synchronous: returns when the hits are on the host. */
+#define MOSS_NOALLOC_MAX_SAMPLES (1ull << 22)
+#define MOSS_NOALLOC_SCRATCH_BYTES (32ull << 20)
+moss_status moss_sample_range_noalloc(moss_graph *g, int32_t sampler, uint64_t seed, uint64_t k0, uint64_t k1,
+                                      uint8_t *d_class_out, uint64_t hits[22]);
 
 /* Node tuples of chosen samples: for each of the count sample indices d_index[i] (device
    u64), d_nodes_out[5 i .. 5 i + 4] (device i32) receives v, u, w, r, t (t = -1 for

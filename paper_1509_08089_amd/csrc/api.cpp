@@ -604,6 +604,7 @@ const char* moss_status_string(moss_status s) {
     case MOSS_E_TIMEOUT: return "timed out";
     case MOSS_E_CANCELLED: return "cancelled";
     case MOSS_E_ADMISSION: return "request can never be admitted";
+    case MOSS_E_TOO_LARGE: return "sample range larger than the fixed scratch of the no-allocation call";
   }
   return "unknown status";
 }
@@ -939,19 +940,27 @@ namespace {
 // and then the sampling launch of each chunk.  (Running the grouping of chunk j on a
 // second stream while chunk j - 1 samples measured slower: 0.81 against 0.68 ms for
 // 1e7 samples in two halves at n = 1e5, m = 1e6; no gain at n = 1e6, m = 1e7.)
+// With `fixed` (a scratch of the caller's, fixed_samples samples per chunk) nothing is
+// allocated.
 moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0, const uint64_t* k1, int count,
-                         uint64_t seed, uint8_t* class_out, uint64_t hits[][22], double* device_ms) {
+                         uint64_t seed, uint8_t* class_out, uint64_t hits[][22], double* device_ms,
+                         void* fixed = nullptr, uint64_t fixed_samples = 0) {
   hipStream_t s = g->stream;
   unsigned long long* d_hits = (unsigned long long*)(g->small + kWHits);
-  // XCD-grouped launches sort each chunk of at most 2^25 samples by group (5 bytes per
+  // XCD-grouped launches sort each chunk of at most 2^25 samples by group (6 bytes per
   // sample of scratch)
   void* scratch = nullptr;
   uint64_t max_n = 0;
   for (int i = 0; i < count; ++i) max_n = std::max<uint64_t>(max_n, k1[i] > k0[i] ? k1[i] - k0[i] : 0);
   if (grouped_schedule(g, max_n)) {
-    max_n = std::min<uint64_t>(max_n, 1ull << 25);
-    if (max_n > 0 && dev_alloc_bytes(s, &scratch, (size_t)grouped_scratch_bytes(max_n)) != MOSS_OK)
-      return MOSS_E_NOMEM;
+    if (fixed) {
+      max_n = std::min<uint64_t>(max_n, fixed_samples);
+      scratch = fixed;
+    } else {
+      max_n = std::min<uint64_t>(max_n, 1ull << 25);
+      if (max_n > 0 && dev_alloc_bytes(s, &scratch, (size_t)grouped_scratch_bytes(max_n)) != MOSS_OK)
+        return MOSS_E_NOMEM;
+    }
   }
   // (with a scratch block, every launch below runs grouped; chunks of at most max_n)
   const uint32_t window = sort_window(sampling_footprint(g));
@@ -980,7 +989,7 @@ moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0,
     e = hipMemcpyAsync(g->h_stage, d_hits, 2 * 22 * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   const hipError_t es = hipStreamSynchronize(s);
   if (e == hipSuccess) e = es;
-  dev_free(s, scratch);  // idle after the synchronisation
+  if (scratch != fixed) dev_free(s, scratch);  // idle after the synchronisation
   if (e != hipSuccess) return status_of(e);
   for (int i = 0; i < count; ++i) std::memcpy(hits[i], g->h_stage + 22 * i, 22 * sizeof(uint64_t));
   float ms = 0.f;
@@ -1051,6 +1060,34 @@ moss_status moss_sample_range(moss_graph* g, int32_t sampler, uint64_t seed, uin
     if (e != hipSuccess) return status_of(e);
   }
   st = run_samplers(g, samplers, a, b, 1, seed, d_class_out, h, nullptr);
+  if (st != MOSS_OK) return st;
+  std::memcpy(hits, h[0], sizeof(h[0]));
+  return MOSS_OK;
+}
+
+moss_status moss_sample_range_noalloc(moss_graph* g, int32_t sampler, uint64_t seed, uint64_t k0, uint64_t k1,
+                                      uint8_t* d_class_out, uint64_t hits[22]) {
+  if (!g || !hits || !valid_sampler(sampler) || k1 < k0) return MOSS_E_ARG;
+  if (k1 - k0 > MOSS_NOALLOC_MAX_SAMPLES) return MOSS_E_TOO_LARGE;
+  static_assert(MOSS_NOALLOC_MAX_SAMPLES == kFixedScratchSamples, "the header states the fixed scratch's size");
+  GraphClaim claim(g);
+  if (!claim.ok()) return MOSS_E_BUSY;
+  DeviceScope scope(g->device);
+  if (!scope.ok()) return MOSS_E_DEVICE;
+  const uint32_t need = sampler_tables(sampler);
+  if ((g->built & need) != need) return MOSS_E_NOT_BUILT;
+  void* fixed = nullptr;
+  hipError_t e = fixed_scratch(g->device, &fixed);
+  if (e != hipSuccess) return status_of(e);
+  std::lock_guard<std::mutex> lk(fixed_scratch_lock(g->device));  // one user of the array at a time
+  if (d_class_out && g->total[sampler_slot(sampler)] == 0 && k1 > k0) {
+    e = launch_fill_u8(d_class_out, 0, (int64_t)(k1 - k0), g->stream);
+    if (e != hipSuccess) return status_of(e);
+  }
+  uint64_t h[2][22];
+  const int samplers[1] = {sampler};
+  const uint64_t a[1] = {k0}, b[1] = {k1};
+  moss_status st = run_samplers(g, samplers, a, b, 1, seed, d_class_out, h, nullptr, fixed, kFixedScratchSamples);
   if (st != MOSS_OK) return st;
   std::memcpy(hits, h[0], sizeof(h[0]));
   return MOSS_OK;

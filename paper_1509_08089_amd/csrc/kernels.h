@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace moss {
 
 // Sampler ids double as Philox key tags.
@@ -75,6 +77,7 @@ hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], con
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t value, int64_t count, hipStream_t s);
 
 // Up to four fills of u64 ranges in one launch (unused entries: count 0).
 struct FillSet {
@@ -201,6 +204,15 @@ hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint6
 // `window`: sorted entries a block takes at a time (sort_window of the bytes the
 // samples read at random).
 int64_t grouped_scratch_bytes(uint64_t max_n);
+
+// The no-allocation calls' fixed scratch: a device array of kFixedScratchBytes that holds
+// one grouped chunk of up to kFixedScratchSamples samples.  fixed_scratch gives its
+// address on `device`, which must be the current device (looked up on the first call,
+// then kept); fixed_scratch_lock is held around every use of a device's copy.
+constexpr uint64_t kFixedScratchSamples = 1ull << 22;
+constexpr uint64_t kFixedScratchBytes = 32ull << 20;
+hipError_t fixed_scratch(int device, void** out);
+std::mutex& fixed_scratch_lock(int device);
 uint32_t sort_window(uint64_t footprint_bytes);
 hipError_t launch_group_chunk(int sampler, uint64_t seed, uint64_t a, uint64_t n, void* scratch, uint64_t max_n,
                               hipStream_t s);

@@ -23,6 +23,7 @@
 // All counting is integer; a sample's outcome depends only on (graph, seed, sampler,
 // sample index), never on which lane, block or launch draws it.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "device.h"
@@ -43,6 +44,11 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t value, int64_t count) {
 }
 
 __global__ void k_fill_u64(uint64_t* p, uint64_t value, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = value;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint8_t value, int64_t count) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = value;
 }
@@ -73,6 +79,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t count, hipStream
 hipError_t launch_fill_u64(uint64_t* p, uint64_t value, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(count)), dim3(256), 0, s, p, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint8_t value, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(fill_grid(count)), dim3(256), 0, s, p, value, count);
   return hipGetLastError();
 }
 
@@ -1758,13 +1770,53 @@ static SortScratch sort_scratch(void* base, uint64_t max_n) {
   return t;
 }
 
-int64_t grouped_scratch_bytes(uint64_t max_n) {
+constexpr uint64_t scratch_bytes_for(uint64_t max_n) {
   const uint64_t nblk = std::max<uint64_t>(1, (max_n + kSortSpan - 1) / kSortSpan);
   auto r = [](uint64_t b) { return (b + 255) / 256 * 256; };
-  return (int64_t)(r(max_n * sizeof(SortGroup)) + r(max_n * 4) + 2 * r(kSortGroups * nblk * 4) +
-                   r(kSortGroups * kSortRuns * 4) + r(kSortGroups * 4) + r((kSortGroups + 1) * 4) +
-                   r(kXcds * kCursorStride * 4) + 256);
+  return r(max_n * sizeof(SortGroup)) + r(max_n * 4) + 2 * r(kSortGroups * nblk * 4) +
+         r(kSortGroups * kSortRuns * 4) + r(kSortGroups * 4) + r((kSortGroups + 1) * 4) +
+         r(kXcds * kCursorStride * 4) + 256;
 }
+
+int64_t grouped_scratch_bytes(uint64_t max_n) { return (int64_t)scratch_bytes_for(max_n); }
+
+// The fixed scratch of the no-allocation calls: one grouped chunk of up to
+// kFixedScratchSamples samples (group and order of each sample, the per-block group
+// counts and places, the window cursors) in a device array of the library itself.  Each
+// device the library runs on holds its own copy from the module's load until the
+// process ends.  Every kernel that reads a part of it writes that part first within the
+// same chunk (the cursors are reset by the grouping pass), so no clearing is needed
+// between calls.  In host code the array's name only stands in for it: its address on a
+// device comes from the runtime, looked up once per device with that device current.
+static_assert(scratch_bytes_for(kFixedScratchSamples) <= kFixedScratchBytes, "one chunk fits the fixed scratch");
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void* g_fixed_ptr[kMaxDevices] = {};
+std::mutex g_fixed_use[kMaxDevices];
+}  // namespace
+
+hipError_t fixed_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (!g_fixed_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // callers make the device current first
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_fixed_ptr[device] = p;
+  }
+  *out = g_fixed_ptr[device];
+  return hipSuccess;
+}
+
+std::mutex& fixed_scratch_lock(int device) { return g_fixed_use[device]; }
 
 // Block b counts the groups of samples [b * kSortSpan, (b + 1) * kSortSpan) into row b
 // of the count table.

@@ -21,7 +21,7 @@ STATUS = {
     0: "MOSS_OK", -1: "MOSS_E_ARG", -2: "MOSS_E_UNSORTED", -3: "MOSS_E_SELF_LOOP", -4: "MOSS_E_DUPLICATE",
     -5: "MOSS_E_ASYMMETRIC", -6: "MOSS_E_OVERFLOW", -7: "MOSS_E_NOMEM", -8: "MOSS_E_DEVICE",
     -9: "MOSS_E_NOT_BUILT", -10: "MOSS_E_BUSY", -11: "MOSS_E_TIMEOUT", -12: "MOSS_E_CANCELLED",
-    -13: "MOSS_E_ADMISSION",
+    -13: "MOSS_E_ADMISSION", -14: "MOSS_E_TOO_LARGE",
 }
 globals().update({v: k for k, v in STATUS.items()})
 
@@ -33,6 +33,7 @@ MOSS_TABLES_K4, MOSS_TABLES_K5, MOSS_TABLES_K4MIN = 1 << 4, 1 << 5, 1 << 6
 MOSS_TAB_ACC_GAMMA, MOSS_TAB_ACC_GAMMA1, MOSS_TAB_ACC_GAMMA2, MOSS_TAB_ACC_SIGMA, MOSS_TAB_ACC_TAU = 5, 6, 7, 8, 9
 MOSS_TAB_ACC_GAMMA_MIN, MOSS_TAB_ACC_CHECK, MOSS_TAB_RANK, MOSS_TAB_COL_RANK = 11, 12, 13, 15
 MOSS_TAB_SIGMA_GUIDE, MOSS_TAB_TAU_GUIDE, MOSS_TAB_CHECK_GUIDE = 16, 17, 18
+MOSS_NOALLOC_MAX_SAMPLES, MOSS_NOALLOC_SCRATCH_BYTES = 1 << 22, 32 << 20
 
 # every symbol include/moss.h declares
 EXPORTED = [
@@ -41,7 +42,7 @@ EXPORTED = [
     "moss_sample_nodes", "moss_class_lut", "moss_finals", "moss_estimate_batch", "moss_set_tuning",
     "moss_get_tuning", "moss_autotune", "moss_server_create", "moss_server_add_graph", "moss_server_submit",
     "moss_server_wait", "moss_server_cancel", "moss_server_stats_get", "moss_server_destroy",
-    "moss_plan_budget", "moss_estimate_to_precision", "moss_concentrations",
+    "moss_plan_budget", "moss_estimate_to_precision", "moss_concentrations", "moss_sample_range_noalloc",
 ]
 
 
@@ -127,6 +128,7 @@ def lib():
             "moss_table_read": ([P, i32, P, i64], ctypes.c_int),
             "moss_estimate": ([P, i32, u64, u64, u32, ctypes.POINTER(moss_result)], ctypes.c_int),
             "moss_sample_range": ([P, i32, u64, u64, u64, P, P], ctypes.c_int),
+            "moss_sample_range_noalloc": ([P, i32, u64, u64, u64, P, P], ctypes.c_int),
             "moss_sample_nodes": ([P, i32, u64, P, i64, P, P], ctypes.c_int),
             "moss_class_lut": ([i32, P, i32], ctypes.c_int),
             "moss_finals": ([ctypes.POINTER(moss_result)], ctypes.c_int),
@@ -233,6 +235,13 @@ def moss_estimate(g, k: int, n_samples: int, seed: int, flags: int = 0) -> moss_
 def moss_sample_range(g, sampler: int, seed: int, k0: int, k1: int, d_class_out=None) -> np.ndarray:
     hits = np.zeros(22, np.uint64)
     _check(lib().moss_sample_range(g, sampler, seed, k0, k1, _dptr(d_class_out), _hptr(hits)), "moss_sample_range")
+    return hits
+
+
+def moss_sample_range_noalloc(g, sampler: int, seed: int, k0: int, k1: int, d_class_out=None) -> np.ndarray:
+    hits = np.zeros(22, np.uint64)
+    _check(lib().moss_sample_range_noalloc(g, sampler, seed, k0, k1, _dptr(d_class_out), _hptr(hits)),
+           "moss_sample_range_noalloc")
     return hits
 
 
