@@ -182,3 +182,21 @@ def test_pattern_conversion_on_c1():
     want = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_c1.json")))
     assert want["graph_sha256"] == g.sha256()
     assert og.count4_exact()[1:7].tolist() == want["n4"]
+
+
+def test_stored_c1_counts_meet_the_identities():
+    """tests/golden/exact_c1.json (written by make_golden.py from the oracle's enumeration)
+    must describe the C1 graph and satisfy Eq. n2 (Lambda_3 = n_2 + n_4 + 2 n_5 + 4 n_6)
+    and its 5-node twin Lambda_4 = sum_i phi^(3)_i eta_i (Section 5.1.3), with Lambda
+    counted here from the degrees."""
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "exact_c1.json")))
+    g = gg.config_graph("C1")
+    assert d["graph_sha256"] == g.sha256()
+    deg = [int(x) for x in g.degrees()]
+    lam3, lam4 = sum(choose(x, 3) for x in deg), sum(choose(x, 4) for x in deg)
+    n = dict(enumerate(d["n4"], 1))
+    assert n[2] + n[4] + 2 * n[5] + 4 * n[6] == lam3
+    eta = dict(enumerate(d["eta5"], 1))
+    assert len(eta) == 21 and sum(pins.PHI5_3[i] * eta[i] for i in eta) == lam4
