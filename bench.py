@@ -239,7 +239,7 @@ def read_counter_summary(workload: str):
         return None
     out = {}
     for line in open(p):
-        m = re.match(r"^([a-z0-9_]+(?: [A-Z0-9_]+)?):\s*([0-9a-fA-F.eE+-]+)\s*$", line.strip())
+        m = re.match(r"^([a-z0-9_]+(?: [A-Za-z0-9_]+)?):\s*([0-9a-fA-F.eE+-]+)\s*$", line.strip())
         if m:
             out[m.group(1)] = m.group(2)
     if out.get("kernel_source_sha") != kernel_source_sha():
@@ -322,17 +322,19 @@ def gather_ceiling(footprint_bytes: int, waves=(8, 16, 32), chains=(1, 4, 8), lo
 
 
 # buffer sizes of the gather probe: inside one CU's vector L1 (32 KB), inside one XCD's
-# L2 (4 MB), inside the 256 MB MALL, and the C3 samplers' footprint (past the MALL)
-PROBE_LEVELS = {"l1": 16 << 10, "l2": 2 << 20, "mall": 128 << 20}
+# L2 (4 MB), past the eight L2s (32 MB in all) but inside the 256 MB MALL, and the C3
+# samplers' footprint (past the MALL)
+PROBE_LEVELS = {"l1": 16 << 10, "l2": 2 << 20, "mall": 48 << 20}
 
 
 def gather_levels(line, plain):
     """The random-gather ceilings of each level of the memory hierarchy (dependent
     8-byte loads at random places, several chains per lane, best occupancy), and each
-    sampling launch's rate at that level against them: vector-L1 line accesses
-    (TCP_TOTAL_CACHE_ACCESSES) against the L1-resident probe, L2 requests (TCC_REQ)
-    against the L2-resident probe, read requests past the L2s (TCC_EA0_RDREQ) against the
-    best probe whose buffer exceeds the L2s."""
+    sampling launch's rate at that level against them: L2 requests (TCC_REQ) against the
+    L2-resident probe (whose loads each make one L2 request), read requests past the L2s
+    (TCC_EA0_RDREQ) against the best probe whose buffer exceeds the L2s.  The L1-resident
+    probe and the kernels' vector-L1 line accesses are reported beside them (a wave's
+    loads into a 16 KB buffer share lines, so that probe's loads are not line accesses)."""
     sizes = dict(PROBE_LEVELS, hbm=plain["C3"]["sampling_bytes"] if "C3" in plain else 665_683_712)
     out = {"levels": {}}
     for lvl, nbytes in sizes.items():
@@ -350,12 +352,11 @@ def gather_levels(line, plain):
         rates = {"tcp_accesses_per_s": c.get("per_launch TCP_TOTAL_CACHE_ACCESSES_sum", 0.0) / secs,
                  "l2_requests_per_s": c["tcc_req_per_launch"] / secs,
                  "fabric_reads_per_s": c["ea_rdreq_per_launch"] / secs}
-        rates["l1_frac"] = rates["tcp_accesses_per_s"] / out["levels"]["l1"]["loads_per_s"]
         rates["l2_frac"] = rates["l2_requests_per_s"] / out["levels"]["l2"]["loads_per_s"]
         rates["fabric_frac"] = rates["fabric_reads_per_s"] / fabric_ceiling
         out[name] = rates
     if "C4" in out:
-        out["frac"] = max(out["C4"]["l1_frac"], out["C4"]["l2_frac"], out["C4"]["fabric_frac"])
+        out["frac"] = max(out["C4"]["l2_frac"], out["C4"]["fabric_frac"])
     return out
 
 

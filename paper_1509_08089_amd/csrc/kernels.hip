@@ -1616,6 +1616,69 @@ __device__ __forceinline__ void count_sample(uint32_t* bins, int c) {
   if (c >> 8) atomicAdd(&bins[c >> 8], 1u);
 }
 
+// ---------------------------------------------------------------------------------
+// Lane order.  A sample's node v is monotone in its first random word W0 (the node draw
+// inverts the prefix of the node weights), so samples whose first words share their
+// top bits draw v from one narrow range of nodes.  A block can take its samples
+// kLaneChunk at a time, counting-sort them in LDS by the top 8 bits of W0, and let its
+// lanes draw them in that order: the 64 lanes of a wave then cover about 1/64 of the
+// node-weight mass of the chunk, so their reads of the node prefix, guide, record, row
+// prefix and row entries of v fall on a few cache lines instead of one per lane.  Each
+// sample is still drawn once from its own index, so the counts are those of index
+// order.
+// ---------------------------------------------------------------------------------
+constexpr int kLaneChunk = 4096;
+constexpr int kLaneBuckets = 256;
+
+template <int N>
+struct LaneSort {
+  uint16_t order[N];             // item offsets in bucket order
+  uint8_t bucket[N];             // bucket of each offset
+  uint32_t start[kLaneBuckets];  // bucket counts, then each bucket's next place
+};
+
+// Sorts the items j < n <= N (sample index index_of(j)) of sampler S by bits
+// [shift, shift + 8) of their first word into ls.order.  Called by every thread of the
+// block; returns synchronised.
+template <int S, int N, typename F>
+__device__ void lane_sort(LaneSort<N>& ls, uint64_t seed, F index_of, uint32_t n, int shift) {
+  const int tid = threadIdx.x, bd = blockDim.x;
+  for (int i = tid; i < kLaneBuckets; i += bd) ls.start[i] = 0;
+  __syncthreads();
+  for (uint32_t j = tid; j < n; j += bd) {
+    uint64_t W[4];
+    philox_block(index_of(j), 0, seed, S, W);
+    const uint32_t b = (uint32_t)(W[0] >> shift) & (kLaneBuckets - 1);
+    ls.bucket[j] = (uint8_t)b;
+    atomicAdd(&ls.start[b], 1u);
+  }
+  __syncthreads();
+  if (tid < kLaneBuckets / 4) {  // exclusive prefix of the counts, four per lane of wave 0
+    const uint4 c = reinterpret_cast<const uint4*>(ls.start)[tid];
+    const uint32_t sum = c.x + c.y + c.z + c.w;
+    bool unused = false;
+    const uint32_t b = (uint32_t)(wave_inclusive_scan(sum, unused) - sum);
+    reinterpret_cast<uint4*>(ls.start)[tid] = make_uint4(b, b + c.x, b + c.x + c.y, b + c.x + c.y + c.z);
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j < n; j += bd) ls.order[atomicAdd(&ls.start[ls.bucket[j]], 1u)] = (uint16_t)j;
+  __syncthreads();
+}
+
+// Samples [k0, k1) of sampler S drawn by the whole block in lane order (by the top 8
+// bits of the first word), counted into `bins` (the calling wave's LDS counters).
+// Returns synchronised.
+template <int S>
+__device__ void draw_lane_sorted(const SamplerView& a, const uint8_t* lut, uint64_t seed, uint64_t k0, uint64_t k1,
+                                 LaneSort<kLaneChunk>& ls, uint32_t* bins) {
+  for (uint64_t s0 = k0; s0 < k1; s0 += kLaneChunk) {
+    const uint32_t n = (uint32_t)min((uint64_t)kLaneChunk, k1 - s0);
+    lane_sort<S>(ls, seed, [&](uint32_t j) { return s0 + j; }, n, 56);
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) count_sample(bins, draw<S>(a, lut, seed, s0 + ls.order[j], nullptr));
+    __syncthreads();  // the next chunk reuses ls
+  }
+}
+
 template <int S>
 __global__ __launch_bounds__(256, 8) void k_sample(SamplerView a, uint64_t seed, uint64_t k0, uint64_t k1,
                                                 unsigned long long* __restrict__ hits, uint8_t* __restrict__ class_out) {
@@ -1703,6 +1766,7 @@ uint32_t sort_window(uint64_t footprint_bytes) { return footprint_bytes > (256ul
 // -> 0.624 ms; n = 1e6, m = 1e7, T-5 / Path-5 for 5e7 each at 256-sample windows:
 // 5.84 / 8.38 -> 5.72 / 8.19 ms).
 constexpr uint32_t kCursorStride = 64;  // u32
+constexpr int kMaxWindow = 512;         // sorted entries a block takes at a time, at most
 
 // The (block, group) count table is stored block-major, one 4 KB row per block, so that
 // the grouping pass writes and the sorting pass reads whole rows.  Its group-major
@@ -1977,6 +2041,7 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
   __shared__ uint32_t bins[kMaxWaves][kBins + 2];
   __shared__ uint8_t lut[64];
   __shared__ uint32_t s_win;
+  __shared__ LaneSort<kMaxWindow> ls;
   const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int i = tid; i < nw * (kBins + 2); i += blockDim.x) bins[i / (kBins + 2)][i % (kBins + 2)] = 0;
   load_lut<S>(lut);
@@ -1993,13 +2058,17 @@ __global__ __launch_bounds__(256, 8) void k_sample_sorted(SamplerView a, uint64_
       const uint64_t p = lo + (uint64_t)s_win * window;
       __syncthreads();
       if (p >= hi) break;
-      const uint64_t q = hi < p + window ? hi : p + window;
-      for (uint64_t j = p + tid; j < q; j += blockDim.x) {
-        const uint64_t i = t.order[j];
+      const uint32_t m = (uint32_t)((hi < p + window ? hi : p + window) - p);
+      // lane order inside the window: its samples share the group (the top kSortBits
+      // bits of the first word); the next 8 bits order them
+      lane_sort<S>(ls, seed, [&](uint32_t j) { return k0 + t.order[p + j]; }, m, 64 - kSortBits - 8);
+      for (uint32_t j = tid; j < m; j += blockDim.x) {
+        const uint64_t i = t.order[p + ls.order[j]];
         const int c = draw<S>(a, lut, seed, k0 + i, nullptr);
         count_sample(bins[wave], c);
         if (class_out) class_out[i] = (uint8_t)c;
       }
+      __syncthreads();  // the next window reuses ls
     }
   }
   __syncthreads();
@@ -2034,7 +2103,7 @@ hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed,
                                void* scratch, uint64_t max_n, uint32_t window, unsigned long long* hits,
                                uint8_t* class_out, int grid, int block, hipStream_t s) {
   if (block != 64 * (block / 64) || block > 256 || block < 64 || n == 0 || n > max_n || max_n > (1ull << 31) ||
-      window == 0)
+      window == 0 || window > (uint32_t)kMaxWindow)
     return hipErrorInvalidValue;
   SortScratch tc = sort_scratch(scratch, max_n);
   set_runs(tc, n);
@@ -2106,6 +2175,7 @@ __global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict_
   __shared__ uint32_t lb[kMaxWaves][kBins + 2];
   __shared__ uint8_t lut4[64], lut5t[64], lut5p[64];
   __shared__ uint32_t cur;
+  __shared__ LaneSort<kLaneChunk> ls;
   const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
   if (tid < 64) {
     lut4[tid] = tid < 8 ? c_lut4[tid] : 0;
@@ -2121,20 +2191,10 @@ __global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict_
     if (t >= n_tiles) break;
     const Tile tile = tiles[t];
     const SamplerView v = views[tile.view];
-    if (tile.sampler == kMoss4) {
-      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
-        atomicAdd(&lb[wave][draw_moss4(v, lut4, tile.seed, k, nullptr)], 1u);
-    } else if (tile.sampler == kMoss4Min) {
-      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
-        count_sample(lb[wave], draw_moss4min(v, lut4, tile.seed, k, nullptr));
-    } else if (tile.sampler == kT5) {
-      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
-        atomicAdd(&lb[wave][draw_t5(v, lut5t, tile.seed, k, nullptr)], 1u);
-    } else {
-      for (uint64_t k = tile.k0 + tid; k < tile.k1; k += blockDim.x)
-        atomicAdd(&lb[wave][draw_path5(v, lut5p, tile.seed, k, nullptr)], 1u);
-    }
-    __syncthreads();
+    if (tile.sampler == kMoss4) draw_lane_sorted<kMoss4>(v, lut4, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
+    else if (tile.sampler == kMoss4Min) draw_lane_sorted<kMoss4Min>(v, lut4, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
+    else if (tile.sampler == kT5) draw_lane_sorted<kT5>(v, lut5t, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
+    else draw_lane_sorted<kPath5>(v, lut5p, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
     if (tid < kBins) {
       uint64_t s = 0;
       for (int w = 0; w < nw; ++w) s += lb[w][tid];
