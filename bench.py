@@ -407,8 +407,10 @@ def run_c4(moss, gg, args, step_only=False):
     if not step_only:
         best, tune_ms = moss.moss_autotune(q)
         out["tuning"] = {"tile_samples": best.tile_samples, "blocks_per_cu": best.blocks_per_cu,
-                         "autotune_best_ms": tune_ms}
-        log(f"[bench] C4: autotuned ({best.tile_samples} samples per tile, {best.blocks_per_cu} blocks/CU)")
+                         "group_min_samples_log2": best.group_min_samples_log2,
+                         "group_min_footprint_mb": best.group_min_footprint_mb, "autotune_best_ms": tune_ms}
+        log(f"[bench] C4: autotuned ({best.tile_samples} samples per tile, {best.blocks_per_cu} blocks/CU, grouping "
+            f"thresholds {best.group_min_samples_log2 or 'default'} / {best.group_min_footprint_mb or 'default'})")
     for i in range(args.warmup):
         moss.moss_estimate_batch(q)
         log(f"[bench] C4 warmup {i + 1}/{args.warmup} done")

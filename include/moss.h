@@ -294,9 +294,12 @@ moss_status moss_estimate_to_precision(moss_graph *g, int32_t k, double eps, dou
 moss_status moss_concentrations(const moss_result *r, double omega[21]);
 
 /* ---- batching: many requests in one persistent launch --------------------------------
- * Every request's samples are cut into tiles of consecutive sample indices; one
- * persistent kernel (replayed from a captured hipGraph) drains the whole tile list and
- * keeps per-request hit counts.  out[i] equals moss_estimate(reqs[i]...) exactly.
+ * One persistent kernel (replayed from a captured hipGraph) takes the requests' sample
+ * ranges as a list of items in graph-major order, cuts them into tiles of consecutive
+ * sample indices as its workgroups ask for work, draws each tile's samples in the order
+ * of their first random word, and keeps per-request hit counts; items with many samples
+ * on graphs with large tables run instead as XCD-grouped launches of their own after it
+ * (moss_tuning's grouping thresholds).  out[i] equals moss_estimate(reqs[i]...) exactly.
  * Requests may name different graphs (all on the current device). */
 typedef struct {
   moss_graph *g;
@@ -309,8 +312,13 @@ typedef struct {
 moss_status moss_estimate_batch(const moss_request *reqs, int32_t n, moss_result *out, void *hip_stream);
 
 /* Launch shape knobs (0 = automatic).  tile_samples: samples per tile in the batched
-   kernel; blocks_per_cu: resident workgroups per compute unit for the sampling kernels;
-   schedule: how a plain estimate spreads its samples (MOSS_SCHEDULE_*).  No knob
+   kernel (a tile's samples are shared by the block's waves: tile_samples / (threads
+   per block / 64) per wavefront); blocks_per_cu: resident workgroups per compute unit for
+   the sampling kernels; schedule: how a plain estimate spreads its samples
+   (MOSS_SCHEDULE_*); group_min_samples_log2 / group_min_footprint_mb: a batched or
+   served item runs as an XCD-grouped launch of its own (instead of in the persistent
+   kernel) when it has at least 2^group_min_samples_log2 samples (default 2^20) on a
+   graph whose sampled bytes reach group_min_footprint_mb MB (default 32).  No knob
    changes any result. */
 enum {
   MOSS_SCHEDULE_AUTO = 0,   /* by the graph's footprint */
@@ -324,15 +332,20 @@ typedef struct {
   uint32_t blocks_per_cu;
   uint32_t threads_per_block;
   uint32_t schedule;
+  uint32_t group_min_samples_log2;  /* <= 40 */
+  uint32_t group_min_footprint_mb;  /* <= 2^20 */
 } moss_tuning;
 
 moss_status moss_set_tuning(const moss_tuning *t);
 moss_status moss_get_tuning(moss_tuning *t);
 
 /* Autotuner: times moss_estimate_batch over the given requests (host tile list and
-   staging included) for each candidate tile size and occupancy (results are identical
-   for every candidate) and keeps the fastest as the process-wide tuning; best_ms
-   receives its wall time. */
+   staging included; best of two calls) first for each tile size {2048, 4096, 16384,
+   65536} and occupancy {2, 3, 4, 5, 6, 8} blocks per CU, then, with the best of those,
+   for each grouping threshold (items of at least 2^{17..22} samples on graphs of at
+   least {4, 8, 16, 32, 64} MB of sampled bytes); results are identical for every
+   candidate (checked).  Keeps the fastest as the process-wide tuning (the schedule knob
+   is left as it was); best_ms receives its wall time. */
 moss_status moss_autotune(const moss_request *reqs, int32_t n, moss_tuning *best, double *best_ms);
 
 /* ---- serving: continuous batching over resident graphs --------------------------------

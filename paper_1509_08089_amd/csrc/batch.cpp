@@ -27,10 +27,12 @@ constexpr uint64_t kBatchSortMinSamples = 1ull << 20;
 constexpr uint64_t kBatchSortMinFootprint = 32ull << 20;
 constexpr uint64_t kBatchSortChunk = 1ull << 25;
 
-bool batch_sorted(const moss_graph* g, uint64_t n, uint32_t schedule) {
-  if (schedule == MOSS_SCHEDULE_PLAIN) return false;
-  if (schedule == MOSS_SCHEDULE_XCD) return n > 0;
-  return n >= kBatchSortMinSamples && sampling_footprint(g) >= kBatchSortMinFootprint;
+bool batch_sorted(const moss_graph* g, uint64_t n, const Tuning& t) {
+  if (t.schedule == MOSS_SCHEDULE_PLAIN) return false;
+  if (t.schedule == MOSS_SCHEDULE_XCD) return n > 0;
+  const uint64_t min_n = t.group_min_samples_log2 ? 1ull << t.group_min_samples_log2 : kBatchSortMinSamples;
+  const uint64_t min_fp = t.group_min_footprint_mb ? (uint64_t)t.group_min_footprint_mb << 20 : kBatchSortMinFootprint;
+  return n >= min_n && sampling_footprint(g) >= min_fp;
 }
 }  // namespace
 
@@ -87,14 +89,14 @@ void BatchRunner::release() {
   graph_ = nullptr;
   graph_grid_ = graph_block_ = 0;
   if (d_views_) (void)hipFree(d_views_);
-  if (d_tiles_) (void)hipFree(d_tiles_);
+  if (d_items_) (void)hipFree(d_items_);
   if (d_ctl_) (void)hipFree(d_ctl_);
   if (d_bins_) (void)hipFree(d_bins_);
   d_views_ = nullptr;
-  d_tiles_ = nullptr;
+  d_items_ = nullptr;
   d_ctl_ = nullptr;
   d_bins_ = nullptr;
-  cap_views_ = cap_tiles_ = cap_slots_ = 0;
+  cap_views_ = cap_items_ = cap_slots_ = 0;
   if (h_in_) (void)hipHostFree(h_in_);
   if (h_bins_) (void)hipHostFree(h_bins_);
   h_in_ = nullptr;
@@ -108,7 +110,7 @@ void BatchRunner::release() {
   stream_ = nullptr;
 }
 
-moss_status BatchRunner::reserve(size_t views, size_t tiles, size_t slots) {
+moss_status BatchRunner::reserve(size_t views, size_t items, size_t slots) {
   bool changed = false;
   auto grow = [&](size_t need, size_t& cap, auto** ptr, size_t elem) -> moss_status {
     if (need <= cap) return MOSS_OK;
@@ -125,7 +127,7 @@ moss_status BatchRunner::reserve(size_t views, size_t tiles, size_t slots) {
     return MOSS_OK;
   };
   moss_status st = grow(std::max<size_t>(views, 64), cap_views_, &d_views_, sizeof(SamplerView));
-  if (st == MOSS_OK) st = grow(std::max<size_t>(tiles, 1024), cap_tiles_, &d_tiles_, sizeof(Tile));
+  if (st == MOSS_OK) st = grow(std::max<size_t>(items, 512), cap_items_, &d_items_, sizeof(BatchItem));
   if (st == MOSS_OK) {
     const size_t old = cap_slots_;
     st = grow(std::max<size_t>(slots, 512), cap_slots_, &d_bins_, 22 * sizeof(unsigned long long));
@@ -146,7 +148,7 @@ moss_status BatchRunner::reserve(size_t views, size_t tiles, size_t slots) {
     }
     changed = true;
   }
-  const size_t in_bytes = cap_views_ * sizeof(SamplerView) + cap_tiles_ * sizeof(Tile) + 64;
+  const size_t in_bytes = cap_views_ * sizeof(SamplerView) + cap_items_ * sizeof(BatchItem) + 64;
   if (in_bytes > cap_in_) {
     if (h_in_) (void)hipHostFree(h_in_);
     h_in_ = nullptr;
@@ -180,8 +182,8 @@ moss_status BatchRunner::capture(int grid, int block) {
   hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return status_of(e);
   hipError_t e1 = launch_fill_u64((uint64_t*)d_bins_, 0, (int64_t)cap_slots_ * 22, stream_);
-  if (e1 == hipSuccess) e1 = launch_fill_u32(d_ctl_ + 1, 0, 1, stream_);
-  if (e1 == hipSuccess) e1 = launch_batch(d_views_, d_tiles_, d_ctl_, d_ctl_ + 1, d_bins_, grid, block, stream_);
+  if (e1 == hipSuccess) e1 = launch_fill_u32(d_ctl_ + kCtlCounter, 0, 1, stream_);
+  if (e1 == hipSuccess) e1 = launch_batch(d_views_, d_items_, d_ctl_, d_bins_, grid, block, stream_);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(stream_, &g);
   if (e1 != hipSuccess || e != hipSuccess) {
@@ -226,11 +228,8 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   // views: one per distinct (graph, sampler)
   std::vector<SamplerView> views;
   std::map<std::pair<const moss_graph*, int>, uint32_t> view_of;
-  struct PendingTile {
-    Tile t;
-    uint64_t cost;
-  };
-  std::vector<PendingTile> tiles;
+  std::vector<BatchItem> items;
+  std::vector<uint64_t> item_cost;
   // large items on large graphs run as grouped launches of their own after the
   // persistent kernel (the plain path's grouping passes and sorted sampling kernel, one
   // chunk at a time through one scratch block), adding into their histogram slots
@@ -245,7 +244,7 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   uint64_t max_chunk = 0;
   for (const WorkItem& w : work) {
     if (!sort_large || w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
-    if (!batch_sorted(w.g, w.k1 - w.k0, tune.schedule)) continue;
+    if (!batch_sorted(w.g, w.k1 - w.k0, tune)) continue;
     const SamplerView view = sampler_view(w.g, w.sampler);
     const uint32_t window = sort_window(sampling_footprint(w.g));
     for (uint64_t a = w.k0; a < w.k1; a += kBatchSortChunk) {
@@ -271,7 +270,7 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     return MOSS_E_NOMEM;
   for (const WorkItem& w : work) {
     if (w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
-    if (sort_large && batch_sorted(w.g, w.k1 - w.k0, tune.schedule)) continue;  // a grouped launch
+    if (sort_large && batch_sorted(w.g, w.k1 - w.k0, tune)) continue;  // a grouped launch
     auto key = std::make_pair((const moss_graph*)w.g, w.sampler);
     auto it = view_of.find(key);
     uint32_t vi;
@@ -282,46 +281,52 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     } else {
       vi = it->second;
     }
-    const uint64_t weight = (w.sampler == kMoss4 || w.sampler == kMoss4Min) ? 2 : 3;
-    for (uint64_t a = w.k0; a < w.k1; a += T) {
-      const uint64_t b = std::min<uint64_t>(w.k1, a + T);
-      Tile t{};
-      t.view = vi;
-      t.sampler = (uint32_t)w.sampler;
-      t.out = w.slot;
-      t.seed = w.seed;
-      t.k0 = a;
-      t.k1 = b;
-      tiles.push_back({t, (b - a) * weight});
-    }
+    BatchItem b{};
+    b.view = vi;
+    b.sampler = (uint32_t)w.sampler;
+    b.out = w.slot;
+    b.seed = w.seed;
+    b.k0 = w.k0;
+    b.k1 = w.k1;
+    items.push_back(b);
+    item_cost.push_back((w.k1 - w.k0) * ((w.sampler == kMoss4 || w.sampler == kMoss4Min) ? 2 : 3));
   }
-  // Graph-major order: the tiles of one (graph, sampler) view run together, so at any
+  // Graph-major order: the items of one (graph, sampler) view run together, so at any
   // moment the chip works on one graph's tables and they stay in L2 and the MALL
   // (interleaving the graphs of a batch measured about 15% slower per sample).  The
-  // views with the most work go first; every view's partial tile comes last in it.
+  // views with the most work go first, and the largest items first within a view.  The
+  // kernel cuts each item into tiles itself; the host hands over the item list only.
   std::vector<uint64_t> view_cost(views.size(), 0);
-  for (const PendingTile& t : tiles) view_cost[t.t.view] += t.cost;
-  std::stable_sort(tiles.begin(), tiles.end(), [&](const PendingTile& x, const PendingTile& y) {
-    if (x.t.view != y.t.view) {
-      const uint64_t cx = view_cost[x.t.view], cy = view_cost[y.t.view];
-      return cx != cy ? cx > cy : x.t.view < y.t.view;
-    }
-    return x.cost > y.cost;
+  for (size_t i = 0; i < items.size(); ++i) view_cost[items[i].view] += item_cost[i];
+  std::vector<size_t> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    const uint32_t vx = items[x].view, vy = items[y].view;
+    if (vx != vy) return view_cost[vx] != view_cost[vy] ? view_cost[vx] > view_cost[vy] : vx < vy;
+    return item_cost[x] > item_cost[y];
   });
-  if (tiles.size() >= 0xFFFFFFFFull) return MOSS_E_ARG;
-  moss_status st = reserve(views.size(), tiles.size(), n_slots);
+  uint64_t n_tiles = 0;
+  for (size_t i : order) {
+    items[i].first_tile = (uint32_t)n_tiles;
+    n_tiles += (items[i].k1 - items[i].k0 + T - 1) / T;
+    if (n_tiles >= 0xFFFFFFFFull) return MOSS_E_ARG;
+  }
+  moss_status st = reserve(views.size(), items.size(), n_slots);
   if (st != MOSS_OK) return st;
   st = capture(grid, block);
   if (st != MOSS_OK) return st;
 
-  // stage views | tiles | n_tiles in pinned memory and copy in one transfer each
+  // stage views | items | control words in pinned memory and copy in one transfer each
   unsigned char* p = h_in_;
-  const size_t vbytes = views.size() * sizeof(SamplerView), tbytes = tiles.size() * sizeof(Tile);
+  const size_t vbytes = views.size() * sizeof(SamplerView), ibytes = items.size() * sizeof(BatchItem);
   std::memcpy(p, views.data(), vbytes);
-  Tile* tp = (Tile*)(p + vbytes);
-  for (size_t i = 0; i < tiles.size(); ++i) tp[i] = tiles[i].t;
-  uint32_t* np = (uint32_t*)(p + vbytes + tbytes);
-  np[0] = (uint32_t)tiles.size();
+  BatchItem* ip = (BatchItem*)(p + vbytes);
+  for (size_t i = 0; i < order.size(); ++i) ip[i] = items[order[i]];
+  uint32_t* np = (uint32_t*)(p + vbytes + ibytes);
+  np[kCtlTiles] = (uint32_t)n_tiles;
+  np[kCtlCounter] = 0;
+  np[kCtlItems] = (uint32_t)items.size();
+  np[kCtlTileSize] = T;
 
   hipError_t e = hipSuccess;
   if (wait_on) {
@@ -329,8 +334,8 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     if (e == hipSuccess) e = hipStreamWaitEvent(stream_, ev_wait_, 0);
   }
   if (e == hipSuccess && vbytes) e = hipMemcpyAsync(d_views_, p, vbytes, hipMemcpyHostToDevice, stream_);
-  if (e == hipSuccess && tbytes) e = hipMemcpyAsync(d_tiles_, p + vbytes, tbytes, hipMemcpyHostToDevice, stream_);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_ctl_, np, sizeof(uint32_t), hipMemcpyHostToDevice, stream_);
+  if (e == hipSuccess && ibytes) e = hipMemcpyAsync(d_items_, p + vbytes, ibytes, hipMemcpyHostToDevice, stream_);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_ctl_, np, 4 * sizeof(uint32_t), hipMemcpyHostToDevice, stream_);
   if (e == hipSuccess) e = hipEventRecord(ev0_, stream_);
   if (e == hipSuccess) e = hipGraphLaunch(exec_, stream_);  // clears every slot first
   for (const SortChunk& c : chunks) {
@@ -425,11 +430,14 @@ moss_status moss_set_tuning(const moss_tuning* t) {
   if (!t) return MOSS_E_ARG;
   if (t->threads_per_block && (t->threads_per_block % 64 != 0 || t->threads_per_block > 256)) return MOSS_E_ARG;
   if (t->blocks_per_cu > 64 || t->schedule > MOSS_SCHEDULE_XCD) return MOSS_E_ARG;
+  if (t->group_min_samples_log2 > 40 || t->group_min_footprint_mb > (1u << 20)) return MOSS_E_ARG;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuning.tile_samples = t->tile_samples;
   g_tuning.blocks_per_cu = t->blocks_per_cu;
   g_tuning.threads_per_block = t->threads_per_block;
   g_tuning.schedule = t->schedule;
+  g_tuning.group_min_samples_log2 = t->group_min_samples_log2;
+  g_tuning.group_min_footprint_mb = t->group_min_footprint_mb;
   return MOSS_OK;
 }
 
@@ -440,6 +448,8 @@ moss_status moss_get_tuning(moss_tuning* t) {
   t->blocks_per_cu = g_tuning.blocks_per_cu;
   t->threads_per_block = g_tuning.threads_per_block;
   t->schedule = g_tuning.schedule;
+  t->group_min_samples_log2 = g_tuning.group_min_samples_log2;
+  t->group_min_footprint_mb = g_tuning.group_min_footprint_mb;
   return MOSS_OK;
 }
 
@@ -447,29 +457,71 @@ moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best
   if (!reqs || n <= 0 || !best) return MOSS_E_ARG;
   static const uint32_t kTiles[] = {2048, 4096, 16384, 65536};
   static const uint32_t kBpc[] = {2, 3, 4, 5, 6, 8};
+  static const uint32_t kGroupLog2[] = {17, 18, 19, 20, 21, 22};
+  static const uint32_t kGroupMb[] = {4, 8, 16, 32, 64};
+  const moss_tuning before = [] {
+    moss_tuning t{};
+    (void)moss_get_tuning(&t);
+    return t;
+  }();
   std::vector<moss_result> ref((size_t)n), cur((size_t)n);
   moss_status st = batch_impl(reqs, n, ref.data(), nullptr, kDefaultTile, 4, nullptr);  // warm-up, reference
   if (st != MOSS_OK) return st;
-  double best_t = 1e300;
-  moss_tuning b{};
-  for (uint32_t T : kTiles) {
-    for (uint32_t bpc : kBpc) {
-      // the whole call: smaller tiles cost host time (tile list, staging) as well
+  // the whole call, best of two (host time included: item list, staging, copies)
+  auto timed = [&](uint32_t T, uint32_t bpc, double* ms) -> moss_status {
+    *ms = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
       const auto t0 = std::chrono::steady_clock::now();
-      st = batch_impl(reqs, n, cur.data(), nullptr, T, bpc, nullptr);
-      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      if (st != MOSS_OK) return st;
+      moss_status s = batch_impl(reqs, n, cur.data(), nullptr, T, bpc, nullptr);
+      const double t = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (s != MOSS_OK) return s;
       for (int32_t i = 0; i < n; ++i)
         if (std::memcmp(cur[i].hits, ref[i].hits, sizeof(ref[i].hits)) != 0) return MOSS_E_DEVICE;
+      *ms = std::min(*ms, t);
+    }
+    return MOSS_OK;
+  };
+  double best_t = 1e300;
+  moss_tuning b = before;
+  b.threads_per_block = 256;
+  // 1. tile size and occupancy of the persistent kernel, at the default grouping
+  moss_tuning c = b;
+  c.group_min_samples_log2 = c.group_min_footprint_mb = 0;
+  for (uint32_t T : kTiles) {
+    for (uint32_t bpc : kBpc) {
+      c.tile_samples = T;
+      c.blocks_per_cu = bpc;
+      if ((st = moss_set_tuning(&c)) != MOSS_OK) break;
+      double ms;
+      if ((st = timed(T, bpc, &ms)) != MOSS_OK) break;
       if (ms < best_t) {
         best_t = ms;
-        b.tile_samples = T;
-        b.blocks_per_cu = bpc;
-        b.threads_per_block = 256;
+        b = c;
+      }
+    }
+    if (st != MOSS_OK) break;
+  }
+  // 2. which items leave the persistent kernel for grouped launches of their own: the
+  // fewest samples per item and the smallest sampled footprint of its graph
+  for (uint32_t lg : kGroupLog2) {
+    if (st != MOSS_OK) break;
+    for (uint32_t mb : kGroupMb) {
+      c = b;
+      c.group_min_samples_log2 = lg;
+      c.group_min_footprint_mb = mb;
+      if ((st = moss_set_tuning(&c)) != MOSS_OK) break;
+      double ms;
+      if ((st = timed(c.tile_samples, c.blocks_per_cu, &ms)) != MOSS_OK) break;
+      if (ms < best_t) {
+        best_t = ms;
+        b = c;
       }
     }
   }
-  b.schedule = current_tuning().schedule;
+  if (st != MOSS_OK) {
+    (void)moss_set_tuning(&before);
+    return st;
+  }
   st = moss_set_tuning(&b);
   if (st != MOSS_OK) return st;
   *best = b;

@@ -41,18 +41,18 @@ class BatchRunner {
   void release();
 
  private:
-  moss_status reserve(size_t views, size_t tiles, size_t slots);
+  moss_status reserve(size_t views, size_t items, size_t slots);
   moss_status capture(int grid, int block);
 
   int device_;
   hipStream_t stream_ = nullptr;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr, ev_wait_ = nullptr;
   SamplerView* d_views_ = nullptr;
-  Tile* d_tiles_ = nullptr;
-  uint32_t* d_ctl_ = nullptr;  // [0] n_tiles, [1] tile counter
+  BatchItem* d_items_ = nullptr;
+  uint32_t* d_ctl_ = nullptr;  // control words (kCtl*)
   unsigned long long* d_bins_ = nullptr;
-  size_t cap_views_ = 0, cap_tiles_ = 0, cap_slots_ = 0;
-  unsigned char* h_in_ = nullptr;  // pinned staging for views + tiles + n_tiles
+  size_t cap_views_ = 0, cap_items_ = 0, cap_slots_ = 0;
+  unsigned char* h_in_ = nullptr;  // pinned staging for views + items + control words
   size_t cap_in_ = 0;
   uint64_t* h_bins_ = nullptr;     // pinned, cap_slots_ x 22
   hipGraph_t graph_ = nullptr;

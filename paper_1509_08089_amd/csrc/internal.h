@@ -142,6 +142,8 @@ struct Tuning {
   uint32_t blocks_per_cu = 0;
   uint32_t threads_per_block = 0;
   uint32_t schedule = 0;  // MOSS_SCHEDULE_*
+  uint32_t group_min_samples_log2 = 0;  // batched items drawn grouped: at least 2^x samples (0 = default)
+  uint32_t group_min_footprint_mb = 0;  // ... on graphs whose sampled bytes reach x MB (0 = default)
 };
 Tuning current_tuning();
 

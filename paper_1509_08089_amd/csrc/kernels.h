@@ -63,15 +63,21 @@ constexpr int kWords = 64;
 // Rows with at least this many entries get a guide table for their weighted picks.
 constexpr int32_t kRowGuideMin = 64;
 
-// One unit of batched work: samples [k0, k1) of one sampler on one graph.
-struct Tile {
-  uint32_t view;     // index into the SamplerView array
-  uint32_t sampler;  // kMoss4 / kMoss4Min / kT5 / kPath5
-  uint32_t out;      // histogram slot (22 counters each)
-  uint32_t pad;
+// One item of batched work: samples [k0, k1) of one sampler on one graph, cut into tiles
+// of the launch's tile size; its tiles are numbered from first_tile on (the items of a
+// launch in order, each with at least one tile).
+struct BatchItem {
+  uint32_t view;        // index into the SamplerView array
+  uint32_t sampler;     // kMoss4 / kMoss4Min / kT5 / kPath5
+  uint32_t out;         // histogram slot (22 counters each)
+  uint32_t first_tile;  // tiles of the items before it
   uint64_t seed;
-  uint64_t k0, k1;   // sample indices
+  uint64_t k0, k1;      // sample indices
 };
+
+// Control words of a batched launch: tiles in all, the tile counter (cleared by the
+// launch), items, samples per tile.
+constexpr int kCtlTiles = 0, kCtlCounter = 1, kCtlItems = 2, kCtlTileSize = 3;
 
 hipError_t upload_class_luts(const uint8_t lut4[8], const uint8_t lut5t[64], const uint8_t lut5p[64]);
 
@@ -223,9 +229,10 @@ hipError_t launch_sample_chunk(int sampler, const SamplerView& v, uint64_t seed,
 hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed, const uint64_t* index,
                                int64_t count, int32_t* nodes_out, uint8_t* class_out, hipStream_t s);
 
-// Batched persistent launch over a tile list resident in device memory.
-hipError_t launch_batch(const SamplerView* views, const Tile* tiles, const uint32_t* n_tiles,
-                        uint32_t* tile_counter, unsigned long long* bins, int grid, int block, hipStream_t s);
+// Batched persistent launch over an item list resident in device memory: blocks take
+// tiles from ctl[kCtlCounter] until ctl[kCtlTiles] are drawn, each finding its item.
+hipError_t launch_batch(const SamplerView* views, const BatchItem* items, uint32_t* ctl, unsigned long long* bins,
+                        int grid, int block, hipStream_t s);
 
 // Registers/VGPR usage probe for occupancy decisions (max active blocks per CU).
 int sample_kernel_blocks_per_cu(int sampler, int block);

@@ -16,8 +16,8 @@
 // Sampling (Algorithms 1, 3, 4):
 //   k_sample<S>        grid-stride loop, one sample per lane per step,
 //                      per-wave LDS histograms flushed with u64 atomics
-//   k_batch            persistent kernel draining a tile list of many
-//                      (graph, sampler, sample range) requests
+//   k_batch            persistent kernel cutting a list of many
+//                      (graph, sampler, sample range) items into tiles
 //   k_sample_nodes<S>  the same draw for chosen sample indices, with nodes
 //
 // All counting is integer; a sample's outcome depends only on (graph, seed, sampler,
@@ -2169,12 +2169,12 @@ hipError_t launch_sample_nodes(int sampler, const SamplerView& v, uint64_t seed,
 // samples are spread over the block's lanes; its histogram is flushed to the tile's
 // output slot.  The sampler is uniform within a tile, so the branch is uniform.
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict__ views, const Tile* __restrict__ tiles,
-                                               const uint32_t* __restrict__ n_tiles_p, uint32_t* tile_counter,
+__global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict__ views,
+                                               const BatchItem* __restrict__ items, uint32_t* ctl,
                                                unsigned long long* __restrict__ bins) {
   __shared__ uint32_t lb[kMaxWaves][kBins + 2];
   __shared__ uint8_t lut4[64], lut5t[64], lut5p[64];
-  __shared__ uint32_t cur;
+  __shared__ uint32_t cur, cur_item;
   __shared__ LaneSort<kLaneChunk> ls;
   const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
   if (tid < 64) {
@@ -2182,31 +2182,47 @@ __global__ __launch_bounds__(256, 8) void k_batch(const SamplerView* __restrict_
     lut5t[tid] = c_lut5t[tid];
     lut5p[tid] = c_lut5p[tid];
   }
-  const uint32_t n_tiles = *n_tiles_p;
+  const uint32_t n_tiles = ctl[kCtlTiles], n_items = ctl[kCtlItems], T = ctl[kCtlTileSize];
+  uint32_t from = 0;  // tiles come in increasing order, so a block's items never go back
   for (;;) {
-    if (tid == 0) cur = atomicAdd(tile_counter, 1u);
+    if (tid == 0) {
+      const uint32_t t = atomicAdd(&ctl[kCtlCounter], 1u);
+      cur = t;
+      if (t < n_tiles) {  // the last item whose first tile is at or before t
+        uint32_t lo = from, hi = n_items - 1;
+        while (lo < hi) {
+          const uint32_t mid = lo + (hi - lo + 1) / 2;
+          if (items[mid].first_tile <= t) lo = mid;
+          else hi = mid - 1;
+        }
+        cur_item = lo;
+      }
+    }
     for (int i = tid; i < nw * (kBins + 2); i += blockDim.x) lb[i / (kBins + 2)][i % (kBins + 2)] = 0;
     __syncthreads();
     const uint32_t t = cur;
     if (t >= n_tiles) break;
-    const Tile tile = tiles[t];
-    const SamplerView v = views[tile.view];
-    if (tile.sampler == kMoss4) draw_lane_sorted<kMoss4>(v, lut4, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
-    else if (tile.sampler == kMoss4Min) draw_lane_sorted<kMoss4Min>(v, lut4, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
-    else if (tile.sampler == kT5) draw_lane_sorted<kT5>(v, lut5t, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
-    else draw_lane_sorted<kPath5>(v, lut5p, tile.seed, tile.k0, tile.k1, ls, lb[wave]);
+    from = cur_item;
+    const BatchItem it = items[from];
+    const SamplerView v = views[it.view];
+    const uint64_t a = it.k0 + (uint64_t)(t - it.first_tile) * T;
+    const uint64_t b = it.k1 - a < T ? it.k1 : a + T;
+    if (it.sampler == kMoss4) draw_lane_sorted<kMoss4>(v, lut4, it.seed, a, b, ls, lb[wave]);
+    else if (it.sampler == kMoss4Min) draw_lane_sorted<kMoss4Min>(v, lut4, it.seed, a, b, ls, lb[wave]);
+    else if (it.sampler == kT5) draw_lane_sorted<kT5>(v, lut5t, it.seed, a, b, ls, lb[wave]);
+    else draw_lane_sorted<kPath5>(v, lut5p, it.seed, a, b, ls, lb[wave]);
     if (tid < kBins) {
       uint64_t s = 0;
       for (int w = 0; w < nw; ++w) s += lb[w][tid];
-      if (s) atomicAdd(&bins[(uint64_t)tile.out * kBins + tid], (unsigned long long)s);
+      if (s) atomicAdd(&bins[(uint64_t)it.out * kBins + tid], (unsigned long long)s);
     }
     __syncthreads();
   }
 }
 
-hipError_t launch_batch(const SamplerView* views, const Tile* tiles, const uint32_t* n_tiles, uint32_t* tile_counter,
-                        unsigned long long* bins, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), 0, s, views, tiles, n_tiles, tile_counter, bins);
+hipError_t launch_batch(const SamplerView* views, const BatchItem* items, uint32_t* ctl, unsigned long long* bins,
+                        int grid, int block, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), 0, s, views, items, ctl, bins);
   return hipGetLastError();
 }
 

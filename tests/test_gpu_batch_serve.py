@@ -109,11 +109,31 @@ def test_tile_size_and_occupancy_do_not_change_results(graphs, tile, bpc):
         np.testing.assert_array_equal(a.hits_np, b.hits_np)
 
 
+@pytest.mark.parametrize("lg,mb", [(10, 0), (12, 1), (17, 4), (40, 1 << 20)])
+def test_grouping_thresholds_do_not_change_results(graphs, lg, mb):
+    """Items of at least 2^lg samples on graphs of at least mb MB of sampled bytes leave the
+    persistent kernel for grouped launches of their own (with 2^10 samples and 0 = the
+    default 32 MB, then 1 MB, most items of the larger graphs do; with 2^40, none)."""
+    gs, handles = graphs
+    reqs = _requests(handles, 24, 5)
+    ref = [_alone(q) for q in reqs]
+    moss.moss_set_tuning(0, 0, 0, 0, lg, mb)
+    try:
+        t = moss.moss_get_tuning()
+        assert (t.group_min_samples_log2, t.group_min_footprint_mb) == (lg, mb)
+        got = moss.moss_estimate_batch(reqs)
+    finally:
+        moss.moss_set_tuning(0, 0, 0)
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a.hits_np, b.hits_np)
+        np.testing.assert_array_equal(a.estimate_np, b.estimate_np)
+
+
 def test_autotune_keeps_results(graphs):
     gs, handles = graphs
     reqs = _requests(handles, 16, 3)
     best, ms = moss.moss_autotune(reqs)
-    assert best.tile_samples > 0 and ms > 0
+    assert best.tile_samples > 0 and ms > 0 and best.group_min_samples_log2 in range(17, 23)
     got = moss.moss_estimate_batch(reqs)
     for q, b in zip(reqs, got):
         np.testing.assert_array_equal(_alone(q).hits_np, b.hits_np)

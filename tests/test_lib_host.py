@@ -209,3 +209,18 @@ def test_probe_library_exports_and_rejects_bad_arguments():
     assert L.moss_probe_gather(fake, 10, 1, (1 << 20) + 1, 1, fake, None) == -1
     for chains in (0, 3, 5, 16):
         assert L.moss_probe_gather(fake, 10, 1, 1, chains, fake, None) == -1
+
+def test_tuning_knobs_round_trip_and_bounds():
+    """The launch knobs are host state: set, read back, and bad values refused."""
+    try:
+        moss.moss_set_tuning(4096, 6, 256, moss.MOSS_SCHEDULE_XCD, 19, 8)
+        t = moss.moss_get_tuning()
+        assert (t.tile_samples, t.blocks_per_cu, t.threads_per_block, t.schedule, t.group_min_samples_log2,
+                t.group_min_footprint_mb) == (4096, 6, 256, moss.MOSS_SCHEDULE_XCD, 19, 8)
+        for bad in ((0, 0, 96, 0, 0, 0), (0, 65, 0, 0, 0, 0), (0, 0, 0, 3, 0, 0), (0, 0, 0, 0, 41, 0),
+                    (0, 0, 0, 0, 0, (1 << 20) + 1)):
+            with pytest.raises(moss.MossError):
+                moss.moss_set_tuning(*bad)
+    finally:
+        moss.moss_set_tuning(0, 0, 0)
+    assert moss.moss_get_tuning().group_min_samples_log2 == 0
