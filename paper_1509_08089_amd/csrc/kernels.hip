@@ -1679,22 +1679,31 @@ __device__ void draw_lane_sorted(const SamplerView& a, const uint8_t* lut, uint6
   }
 }
 
+// Plain sampling: block b draws chunks b, b + grid, ... of `chunk` consecutive samples
+// (chunk <= kLaneChunk), each in lane order.
 template <int S>
 __global__ __launch_bounds__(256, 8) void k_sample(SamplerView a, uint64_t seed, uint64_t k0, uint64_t k1,
-                                                unsigned long long* __restrict__ hits, uint8_t* __restrict__ class_out) {
+                                                uint32_t chunk, unsigned long long* __restrict__ hits,
+                                                uint8_t* __restrict__ class_out) {
   __shared__ uint32_t bins[kMaxWaves][kBins + 2];
   __shared__ uint8_t lut[64];
+  __shared__ LaneSort<kLaneChunk> ls;
   const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
   for (int i = tid; i < nw * (kBins + 2); i += blockDim.x) bins[i / (kBins + 2)][i % (kBins + 2)] = 0;
   load_lut<S>(lut);
   __syncthreads();
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t k = k0 + (uint64_t)blockIdx.x * blockDim.x + tid; k < k1; k += stride) {
-    const int c = draw<S>(a, lut, seed, k, nullptr);
-    count_sample(bins[wave], c);
-    if (class_out) class_out[k - k0] = (uint8_t)c;
+  const uint64_t stride = (uint64_t)gridDim.x * chunk;
+  for (uint64_t s0 = k0 + (uint64_t)blockIdx.x * chunk; s0 < k1; s0 += stride) {
+    const uint32_t n = (uint32_t)min((uint64_t)chunk, k1 - s0);
+    lane_sort<S>(ls, seed, [&](uint32_t j) { return s0 + j; }, n, 56);
+    for (uint32_t j = tid; j < n; j += blockDim.x) {
+      const uint64_t k = s0 + ls.order[j];
+      const int c = draw<S>(a, lut, seed, k, nullptr);
+      count_sample(bins[wave], c);
+      if (class_out) class_out[k - k0] = (uint8_t)c;
+    }
+    __syncthreads();  // the next chunk reuses ls
   }
-  __syncthreads();
   if (tid < kBins) {
     uint64_t s = 0;
     for (int w = 0; w < nw; ++w) s += bins[w][tid];
@@ -1704,18 +1713,27 @@ __global__ __launch_bounds__(256, 8) void k_sample(SamplerView a, uint64_t seed,
 
 hipError_t launch_sample(int sampler, const SamplerView& v, uint64_t seed, uint64_t k0, uint64_t k1,
                          unsigned long long* hits, uint8_t* class_out, int grid, int block, hipStream_t s) {
-  // per-wave LDS counters are 32-bit: keep each launch below 2^31 samples per wave
+  if (grid < 1 || block < 64 || block > 256 || block % 64) return hipErrorInvalidValue;
+  // a chunk per block and round that spreads the samples over the whole grid, between
+  // one sample per thread and kLaneChunk; per-wave LDS counters are 32-bit, so each
+  // launch stays below 2^31 samples per wave
+  const uint64_t per_round = (k1 - k0 + (uint64_t)grid - 1) / (uint64_t)grid;
+  const uint32_t chunk = (uint32_t)std::min<uint64_t>(kLaneChunk, std::max<uint64_t>((uint64_t)block, per_round));
   const uint64_t max_chunk = (uint64_t)grid * (uint64_t)block * (1ull << 24);
   for (uint64_t a = k0; a < k1;) {
     const uint64_t b = k1 - a > max_chunk ? a + max_chunk : k1;
     uint8_t* co = class_out ? class_out + (a - k0) : nullptr;
     switch (sampler) {
-      case kMoss4: hipLaunchKernelGGL(k_sample<kMoss4>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co); break;
-      case kMoss4Min:
-        hipLaunchKernelGGL(k_sample<kMoss4Min>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co);
+      case kMoss4:
+        hipLaunchKernelGGL(k_sample<kMoss4>, dim3(grid), dim3(block), 0, s, v, seed, a, b, chunk, hits, co);
         break;
-      case kT5: hipLaunchKernelGGL(k_sample<kT5>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co); break;
-      case kPath5: hipLaunchKernelGGL(k_sample<kPath5>, dim3(grid), dim3(block), 0, s, v, seed, a, b, hits, co); break;
+      case kMoss4Min:
+        hipLaunchKernelGGL(k_sample<kMoss4Min>, dim3(grid), dim3(block), 0, s, v, seed, a, b, chunk, hits, co);
+        break;
+      case kT5: hipLaunchKernelGGL(k_sample<kT5>, dim3(grid), dim3(block), 0, s, v, seed, a, b, chunk, hits, co); break;
+      case kPath5:
+        hipLaunchKernelGGL(k_sample<kPath5>, dim3(grid), dim3(block), 0, s, v, seed, a, b, chunk, hits, co);
+        break;
       default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
