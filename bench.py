@@ -87,8 +87,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", default="", help="comma list of c4,c2,c3,c5,acc5,probe,cpu; or c4-step, c2-step, "
-                                               "c3-step (just the timed steps, for counter runs)")
+    ap.add_argument("--only", default="", help="comma list of c4,c2,c3,c5,acc5,probe,cpu,c2min,c3min; or c4-step, "
+                                               "c2-step, c3-step, c2min-step, c3min-step (just the timed steps, for "
+                                               "counter runs)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0, help="table memory budget of the server")
     ap.add_argument("--probe-only", type=int, default=0, metavar="BYTES",
@@ -450,10 +451,13 @@ def run_c4(moss, gg, args, step_only=False):
 
 def plain_steps(moss, gg, args, name, with_min=False):
     """Whole-path steps of a plain workload: create over the device CSR, build the tables,
-    estimate, destroy."""
+    estimate, destroy.  With with_min, the graph of `name` with MOSS-4 and MOSS-4Min on
+    half of 1e7 samples each (their rank tables built in the step) and the 4-node mix."""
     import numpy as np
     import torch
-    cfg = gg.CONFIGS[name]
+    cfg = dict(gg.CONFIGS[name])
+    if with_min:
+        cfg.update(k=4, samples=10_000_000)
     log(f"[bench] {name}: generating the graph")
     t = time.perf_counter()
     csr = cfg["graph"].build()
@@ -488,14 +492,18 @@ def plain_steps(moss, gg, args, name, with_min=False):
     r0 = results[0]
     dev_ms = sum(r.device_ms for r in results) / len(results)
     lc = line_counts()[name]
-    if k == 4:
+    if with_min:
+        alg = 64.0 * (r0.K[0] * lc["moss4"] + r0.K[1] * lc["moss4min"]) if "moss4min" in lc else None
+    elif k == 4:
         alg = 64.0 * K * lc["moss4"]
     else:
         alg = 64.0 * (r0.K[0] * lc["t5"] + r0.K[1] * lc["path5"])
-    out = {"workload": f"{name}: {WORKLOAD_TEXT[name]}", "n": csr.n, "m": csr.m, "k": k, "samples": K,
+    text = (f"{name} graph with MOSS-4 + MOSS-4Min (5e6 + 5e6 samples, rank tables built in the step), 4-node "
+            f"mix, seed 1" if with_min else f"{name}: {WORKLOAD_TEXT[name]}")
+    out = {"workload": text, "n": csr.n, "m": csr.m, "k": k, "samples": K,
            "graph_sha256": csr.sha256()[:16], "ms_per_step": ms, "samples_per_s": K / (ms / 1e3),
            "sampling_launch_ms": dev_ms, "lines_per_sample": {s: lc[s] for s in ("moss4", "t5", "path5") if s in lc}}
-    out["roofline"] = roofline(name, dev_ms, alg, K)
+    out["roofline"] = roofline(name + ("MIN" if with_min else ""), dev_ms, alg, K)
     out.update(errors(r0, exact_counts(name, csr.sha256(), "n4" if k == 4 else "eta5")))
     info_h = moss.moss_graph_create_device(csr.n, csr.nnz, d_rp, d_col, 0, stream)
     try:
@@ -642,13 +650,12 @@ def main():
 
     torch.cuda.init()
     only = set(x for x in args.only.split(",") if x)
-    if only & {"c4-step", "c2-step", "c3-step"}:
+    if only & {"c4-step", "c2-step", "c3-step", "c2min-step", "c3min-step"}:
         name = next(iter(only))
         if name == "c4-step":
             res, _ = run_c4(moss, gg, args, step_only=True)
         else:
-            cfg = gg.CONFIGS[name[:2].upper()]
-            res, _ = plain_steps(moss, gg, args, name[:2].upper())
+            res, _ = plain_steps(moss, gg, args, name[:2].upper(), with_min="min" in name)
             res = {k: res[k] for k in ("ms_per_step", "samples_per_s", "sampling_launch_ms")}
         print(json.dumps({"step_only": name, "kernel_source_sha": kernel_source_sha(), **res}), flush=True)
         return 0
@@ -669,6 +676,9 @@ def main():
     for name in ("C2", "C3"):
         if name.lower() in parts:
             plain[name], _ = plain_steps(moss, gg, args, name)
+    for name in ("C2", "C3"):  # MOSS-4 + MOSS-4Min on the plain graphs (only when asked)
+        if name.lower() + "min" in parts:
+            plain[name + "MIN"], _ = plain_steps(moss, gg, args, name, with_min=True)
     if plain:
         line["plain"] = plain
     if "acc5" in parts:

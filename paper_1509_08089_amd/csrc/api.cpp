@@ -448,7 +448,7 @@ void free_tables(moss_graph* g, uint32_t mask) {
     g->total[3] = 0;
   }
   g->built &= ~mask;
-  if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5))) {
+  if (!(g->built & (MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN))) {
     dev_free(g->stream, g->mem_sig);
     g->acc_sigma = nullptr;
     g->sig_guide = nullptr;
@@ -767,8 +767,9 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   DeviceScope scope(g->device);
   if (!scope.ok()) return MOSS_E_DEVICE;
   const bool want4 = need & MOSS_TABLES_K4, want5 = need & MOSS_TABLES_K5, want_min = need & MOSS_TABLES_K4MIN;
-  // ACC_sigma and its companions come with the first MOSS-4 or 5-node set
-  const bool want_sig = (want4 || want5) && !g->mem_sig;
+  // ACC_sigma and its companions come with the first MOSS-4, 5-node or MOSS-4Min set
+  // (MOSS-4Min's rank passes read the neighbours' degrees from it)
+  const bool want_sig = (want4 || want5 || want_min) && !g->mem_sig;
   moss_status st = MOSS_OK;
   if (want_sig) {
     const SigLayout L = sig_layout(g);
@@ -869,8 +870,8 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
     // ranks (the row prefix array serves as their key scratch), the prefix of
     // d_{v,x} d_{x,v} with its row guides, check-Gamma_v, its scan and guide
     if (e == hipSuccess)
-      e = launch_rank_tables(g->n_items, g->items, g->nnz, g->span_row, g->rp, g->col, g->rec, g->acc_check, g->rank,
-                             g->col_rank, s);
+      e = launch_rank_tables(g->n_items, g->items, g->nnz, g->span_row, g->rp, g->col, g->rec, g->acc_sigma,
+                             g->acc_check, g->rank, g->col_rank, s);
     if (e == hipSuccess) {
       t.rank = g->rank;
       t.acc_check = g->acc_check;
@@ -924,7 +925,7 @@ void moss::free_graph_tables(moss_graph* g, uint32_t mask) {
 uint64_t moss::table_bytes_needed(const moss_graph* g, uint32_t mask) {
   const uint64_t sig = sig_layout(g).bytes, k4 = node_layout(g, false).bytes, k5 = node_layout(g, true).bytes;
   const uint32_t have = g->built, add = mask == 0 ? have : (mask & ~have);
-  const uint32_t sig_sets = MOSS_TABLES_K4 | MOSS_TABLES_K5;  // ACC_sigma comes with either
+  const uint32_t sig_sets = MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN;  // ACC_sigma comes with any
   uint64_t b = 0;
   if ((add & sig_sets) && (mask == 0 || !(have & sig_sets))) b += sig;
   if (add & MOSS_TABLES_K4) b += k4;

@@ -166,11 +166,12 @@ hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStr
 
 // MOSS-4Min rank tables (Section 4.2.1, order of Section 3.2): for every entry (v, x),
 // rank[e] = {d_{v,x}, d_{x,v}}, and col_rank holds each row in descending order.
-// `keys` (nnz u64) is scratch: each piece's keys, sorted.  Needs the node records and
-// the first row of every 256-entry span of the CSR (`span_row`, spans + 1 entries).
+// `keys` (nnz u64) is scratch: each piece's keys, sorted.  Needs the node records, the
+// row prefix ACC_sigma (for the neighbours' degrees) and the first row of every
+// 256-entry span of the CSR (`span_row`, spans + 1 entries).
 hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, int64_t nnz, const int32_t* span_row,
-                              const int32_t* rp, const int32_t* col, const uint4* rec, uint64_t* keys, uint2* rank,
-                              int32_t* col_rank, hipStream_t s);
+                              const int32_t* rp, const int32_t* col, const uint4* rec, const uint32_t* acc_sigma,
+                              uint64_t* keys, uint2* rank, int32_t* col_rank, hipStream_t s);
 // w[v] = the last entry of v's row prefix `acc` (0 for an empty row).
 hipError_t launch_row_totals(int32_t n, const int32_t* rp, const uint64_t* acc, uint64_t* w, hipStream_t s);
 

@@ -868,19 +868,26 @@ hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStr
 // N_{v,x} is its first d_{v,x} entries.  The passes over the work items:
 //   local    each piece ranks its entries among themselves, one wave per piece: every
 //            lane compares its keys with each key of the piece, broadcast from the lane
-//            that holds it (a bitonic sort of the piece in LDS by a block of 256 threads
+//            that holds it; a neighbour's degree comes from the row's ACC_sigma
+//            (consecutive differences, read in order) rather than its record (a bitonic sort of the piece in LDS by a block of 256 threads
 //            measured slower: it spends more instructions in all, 0.87 against 0.78 ms
 //            at n = 1e6, m = 1e7).  A row of one piece is finished here; a longer row's
 //            piece writes its keys in descending order (scratch) and its local ranks
 //   merge    one block per piece of a longer row: the row's other pieces' sorted keys
 //            go through LDS, eight pieces at a time, and each thread adds the keys
 //            above its entry (a binary search in LDS)
-//   mirror   d_{x,v} is read at the entry (x, v), found by a binary search of row x
-//            (the upper levels of the searches in a hub row are shared and stay cached;
-//            exchanging the ranks through the edge hash set's slots measured only 15%
-//            faster at n = 1e6, m = 1e7, for a scratch block the size of the set, and
-//            running a lane's four searches side by side 14% slower: the pass is bound
-//            by the L2's request rate, not by latency)
+//   mirror   d_{x,v} is read at the entry (x, v): each upper entry (v, x), x > v,
+//            binary-searches row x for v and writes both entries' mirror ranks.  A
+//            wave takes a 256-entry span of the CSR, four entries a lane, and runs the
+//            lane's four searches in step so their loads go out together (one wave per
+//            row piece: 105 us at n = 1e5, m = 1e6; spans: 79 us; 1.20 ms at n = 1e6,
+//            m = 1e7).  Id guides for the long rows (the bucket starts of their ids, so
+//            a search in a hub row is a guide pair and a window of about four entries)
+//            cut the pass to 1.05 ms at n = 1e6, m = 1e7 but cost 0.13 ms to build, so
+//            they are not used; exchanging the ranks through the edge hash set's slots
+//            measured 15% faster for a scratch block the size of the set.  What is left
+//            is the random exchange itself, two reads and a write per pair in a
+//            working set past the MALL
 // Equal keys (a repeated neighbour, possible only in an unchecked CSR) are ranked by
 // their place in the row, so the ranks of a row are always a permutation of 0..d-1 and
 // every place of col_rank is written exactly once.  A missing mirror (also only in an
@@ -888,6 +895,13 @@ hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStr
 // ---------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t order_key(const uint4* __restrict__ rec, int32_t x) {
   return ((uint64_t)row_of(rec, x).y << 32) | (uint64_t)(uint32_t)x;
+}
+
+// The same key for the neighbour x at entry e of a row that starts at r0, with d_x taken
+// from the row's prefix of d_x - 1 (ACC_sigma), read in order, instead of x's record.
+__device__ __forceinline__ uint64_t entry_key(const uint32_t* __restrict__ sig, int32_t e, int32_t r0, int32_t x) {
+  const uint32_t d1 = sig[e] - (e > r0 ? sig[e - 1] : 0u);
+  return ((uint64_t)(d1 + 1u) << 32) | (uint64_t)(uint32_t)x;
 }
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
@@ -898,7 +912,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
 
 __global__ __launch_bounds__(256) void k_rank_local(int64_t n_items, const uint64_t* __restrict__ items,
                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                    const uint4* __restrict__ rec, uint64_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ sig, uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
   const int lane = lane_id();
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -913,7 +927,7 @@ __global__ __launch_bounds__(256) void k_rank_local(int64_t n_items, const uint6
     for (int c = 0; c < kItem / 64; ++c) {
       const int32_t e = it.e0 + c * 64 + lane;
       x[c] = e < it.e1 ? col[e] : 0;
-      k[c] = e < it.e1 ? order_key(rec, x[c]) : 0ull;
+      k[c] = e < it.e1 ? entry_key(sig, e, it.r0, x[c]) : 0ull;
       above[c] = 0;
     }
 #pragma unroll
@@ -944,7 +958,7 @@ constexpr int kMergeBatch = 8;  // pieces staged in LDS at a time
 
 __global__ __launch_bounds__(256) void k_rank_merge(int64_t n_items, const uint64_t* __restrict__ items,
                                                     const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                    const uint4* __restrict__ rec, const uint64_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ sig, const uint64_t* __restrict__ keys,
                                                     uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
   __shared__ uint64_t sk[kMergeBatch][kItem];
   const int tid = threadIdx.x;  // blockDim.x == kItem: one thread per entry of the piece
@@ -955,7 +969,7 @@ __global__ __launch_bounds__(256) void k_rank_merge(int64_t n_items, const uint6
     const int32_t e = it.e0 + tid;
     const bool in = e < it.e1;
     const int32_t x = in ? col[e] : 0;
-    const uint64_t key = in ? order_key(rec, x) : 0ull;
+    const uint64_t key = in ? entry_key(sig, e, it.r0, x) : 0ull;
     uint32_t r = in ? rank32[2 * (int64_t)e] : 0u;
     for (int32_t p0 = 0; p0 < pieces; p0 += kMergeBatch) {
       __syncthreads();  // the previous batch's searches are done
@@ -1053,15 +1067,15 @@ __global__ __launch_bounds__(256) void k_rank_mirror(int64_t nnz, const int32_t*
 }
 
 hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, int64_t nnz, const int32_t* span_row,
-                              const int32_t* rp, const int32_t* col, const uint4* rec, uint64_t* keys, uint2* rank,
-                              int32_t* col_rank, hipStream_t s) {
+                              const int32_t* rp, const int32_t* col, const uint4* rec, const uint32_t* acc_sigma,
+                              uint64_t* keys, uint2* rank, int32_t* col_rank, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   const dim3 grid(item_grid(n_items)), block(256);
   uint32_t* rank32 = reinterpret_cast<uint32_t*>(rank);
-  hipLaunchKernelGGL(k_rank_local, grid, block, 0, s, n_items, items, rp, col, rec, keys, rank32, col_rank);
+  hipLaunchKernelGGL(k_rank_local, grid, block, 0, s, n_items, items, rp, col, acc_sigma, keys, rank32, col_rank);
   const int merge_grid = (int)std::min<int64_t>(n_items, 65536);
-  hipLaunchKernelGGL(k_rank_merge, dim3(merge_grid), dim3(kItem), 0, s, n_items, items, rp, col, rec, keys, rank32,
-                     col_rank);
+  hipLaunchKernelGGL(k_rank_merge, dim3(merge_grid), dim3(kItem), 0, s, n_items, items, rp, col, acc_sigma, keys,
+                     rank32, col_rank);
   hipLaunchKernelGGL(k_rank_mirror, dim3(spans_grid(nnz)), block, 0, s, nnz, span_row, rp, col, rec, rank32);
   return hipGetLastError();
 }
