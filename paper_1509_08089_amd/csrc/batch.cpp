@@ -105,7 +105,14 @@ void BatchRunner::release() {
   if (ev0_) (void)hipEventDestroy(ev0_);
   if (ev1_) (void)hipEventDestroy(ev1_);
   if (ev_wait_) (void)hipEventDestroy(ev_wait_);
-  ev0_ = ev1_ = ev_wait_ = nullptr;
+  if (ev_clear_) (void)hipEventDestroy(ev_clear_);
+  if (ev_side_) (void)hipEventDestroy(ev_side_);
+  ev0_ = ev1_ = ev_wait_ = ev_clear_ = ev_side_ = nullptr;
+  if (side_) {
+    (void)hipStreamSynchronize(side_);
+    (void)hipStreamDestroy(side_);
+  }
+  side_ = nullptr;
   if (stream_) (void)hipStreamDestroy(stream_);
   stream_ = nullptr;
 }
@@ -168,9 +175,10 @@ moss_status BatchRunner::reserve(size_t views, size_t items, size_t slots) {
   return MOSS_OK;
 }
 
-// Captures: clear all histogram slots and the tile counter (fill kernels), then the
-// persistent kernel.  Its arguments are the fixed buffers above, so one capture
-// serves every batch until a buffer is reallocated or the launch shape changes.
+// Captures: clear the tile counter (a fill kernel), then the persistent kernel.  Its
+// arguments are the fixed buffers above, so one capture serves every batch until a
+// buffer is reallocated or the launch shape changes.  (The histogram slots are cleared
+// before the graph, so that the grouped launches on the side stream can start with it.)
 moss_status BatchRunner::capture(int grid, int block) {
   if (exec_ && grid == graph_grid_ && block == graph_block_) return MOSS_OK;
   if (exec_) {
@@ -181,8 +189,7 @@ moss_status BatchRunner::capture(int grid, int block) {
   }
   hipError_t e = hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return status_of(e);
-  hipError_t e1 = launch_fill_u64((uint64_t*)d_bins_, 0, (int64_t)cap_slots_ * 22, stream_);
-  if (e1 == hipSuccess) e1 = launch_fill_u32(d_ctl_ + kCtlCounter, 0, 1, stream_);
+  hipError_t e1 = launch_fill_u32(d_ctl_ + kCtlCounter, 0, 1, stream_);
   if (e1 == hipSuccess) e1 = launch_batch(d_views_, d_items_, d_ctl_, d_bins_, grid, block, stream_);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(stream_, &g);
@@ -208,9 +215,13 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   DeviceScope scope(device_);
   if (!scope.ok()) return MOSS_E_DEVICE;
   if (!stream_) {
-    if (hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess) return MOSS_E_DEVICE;
+    if (hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&side_, hipStreamNonBlocking) != hipSuccess)
+      return MOSS_E_DEVICE;
     if (hipEventCreate(&ev0_) != hipSuccess || hipEventCreate(&ev1_) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_wait_, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&ev_wait_, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_clear_, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming) != hipSuccess)
       return MOSS_E_DEVICE;
   }
   const Tuning tune = current_tuning();
@@ -337,19 +348,30 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   if (e == hipSuccess && ibytes) e = hipMemcpyAsync(d_items_, p + vbytes, ibytes, hipMemcpyHostToDevice, stream_);
   if (e == hipSuccess) e = hipMemcpyAsync(d_ctl_, np, 4 * sizeof(uint32_t), hipMemcpyHostToDevice, stream_);
   if (e == hipSuccess) e = hipEventRecord(ev0_, stream_);
-  if (e == hipSuccess) e = hipGraphLaunch(exec_, stream_);  // clears every slot first
+  if (e == hipSuccess) e = launch_fill_u64((uint64_t*)d_bins_, 0, (int64_t)n_slots * 22, stream_);
+  // the grouped launches run on the side stream, beside the persistent kernel (whose
+  // latency-bound waves leave block slots and memory bandwidth free), from the clear on
+  const bool side = !chunks.empty();
+  if (e == hipSuccess && side) e = hipEventRecord(ev_clear_, stream_);
+  if (e == hipSuccess && side) e = hipStreamWaitEvent(side_, ev_clear_, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(exec_, stream_);
   for (const SortChunk& c : chunks) {
     if (e != hipSuccess) break;
-    e = launch_group_chunk(c.sampler, c.seed, c.a, c.n, sort_scratch_block, max_chunk, stream_);
+    e = launch_group_chunk(c.sampler, c.seed, c.a, c.n, sort_scratch_block, max_chunk, side_);
     if (e == hipSuccess)
       e = launch_sample_chunk(c.sampler, c.view, c.seed, c.a, c.n, sort_scratch_block, max_chunk, c.window,
-                              d_bins_ + (uint64_t)c.slot * 22, nullptr, c.grid, c.block, stream_);
+                              d_bins_ + (uint64_t)c.slot * 22, nullptr, c.grid, c.block, side_);
   }
+  if (e == hipSuccess && side) e = hipEventRecord(ev_side_, side_);
+  if (e == hipSuccess && side) e = hipStreamWaitEvent(stream_, ev_side_, 0);
   if (e == hipSuccess) e = hipEventRecord(ev1_, stream_);
   if (e == hipSuccess && n_slots)
     e = hipMemcpyAsync(h_bins_, d_bins_, (size_t)n_slots * 22 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream_);
   if (e == hipSuccess) e = hipStreamSynchronize(stream_);
-  if (e != hipSuccess) return status_of(e);
+  if (e != hipSuccess) {
+    if (side) (void)hipStreamSynchronize(side_);  // nothing of this batch left running
+    return status_of(e);
+  }
   std::memcpy(bins_out, h_bins_, (size_t)n_slots * 22 * sizeof(uint64_t));
   if (device_ms) {
     float ms = 0.f;

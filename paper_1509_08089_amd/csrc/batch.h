@@ -46,7 +46,8 @@ class BatchRunner {
 
   int device_;
   hipStream_t stream_ = nullptr;
-  hipEvent_t ev0_ = nullptr, ev1_ = nullptr, ev_wait_ = nullptr;
+  hipStream_t side_ = nullptr;  // the grouped launches, beside the persistent kernel
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr, ev_wait_ = nullptr, ev_clear_ = nullptr, ev_side_ = nullptr;
   SamplerView* d_views_ = nullptr;
   BatchItem* d_items_ = nullptr;
   uint32_t* d_ctl_ = nullptr;  // control words (kCtl*)
