@@ -339,9 +339,10 @@ struct NodeLayout {
 };
 
 // MOSS-4Min: rank pairs, rows in descending order, the row prefix of d_{v,x} d_{x,v}
-// (also the rank passes' key scratch) with its row guides, the node prefix and guide
+// (also the rank passes' scratch) with its row guides, the node prefix and guide, and
+// the counts of the mirror sort
 struct MinLayout {
-  size_t rank, col_rank, acc_check, check_guide, acc, guide, bytes;
+  size_t rank, col_rank, acc_check, check_guide, acc, guide, work, bytes;
 };
 
 MinLayout min_layout(const moss_graph* g) {
@@ -354,6 +355,7 @@ MinLayout min_layout(const moss_graph* g) {
   L.check_guide = c.take<uint32_t>((size_t)g->row_guide_len);
   L.acc = c.take<uint64_t>(n);
   L.guide = c.take<uint32_t>(G);
+  L.work = c.take<uint32_t>((size_t)mirror_work_words(g->nnz));
   L.bytes = c.off;
   return L;
 }
@@ -867,11 +869,27 @@ moss_status moss::build_tables(moss_graph* g, uint32_t k_mask) {
   if (e == hipSuccess) e = launch_scans(scans, g->n, err, s);
   if (e == hipSuccess) e = launch_guides(guides, g->n, g->gbits, s);
   if (want_min) {
-    // ranks (the row prefix array serves as their key scratch), the prefix of
+    // ranks (the row prefix array serves as their scratch), the prefix of
     // d_{v,x} d_{x,v} with its row guides, check-Gamma_v, its scan and guide
-    if (e == hipSuccess)
-      e = launch_rank_tables(g->n_items, g->items, g->nnz, g->span_row, g->rp, g->col, g->rec, g->acc_sigma,
-                             g->acc_check, g->rank, g->col_rank, s);
+    if (e == hipSuccess) {
+      RankTables rt{};
+      rt.n_items = g->n_items;
+      rt.items = g->items;
+      rt.n = g->n;
+      rt.nnz = g->nnz;
+      rt.max_degree = g->max_degree;
+      rt.validated = !(g->flags & MOSS_TRUST_CSR);
+      rt.span_row = g->span_row;
+      rt.rp = g->rp;
+      rt.col = g->col;
+      rt.rec = g->rec;
+      rt.acc_sigma = g->acc_sigma;
+      rt.scratch = g->acc_check;
+      rt.work = at<uint32_t>(g->mem_min, min_layout(g).work);
+      rt.rank = g->rank;
+      rt.col_rank = g->col_rank;
+      e = launch_rank_tables(rt, s);
+    }
     if (e == hipSuccess) {
       t.rank = g->rank;
       t.acc_check = g->acc_check;

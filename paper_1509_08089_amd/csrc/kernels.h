@@ -165,13 +165,32 @@ struct RowTables {
 hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStream_t s);
 
 // MOSS-4Min rank tables (Section 4.2.1, order of Section 3.2): for every entry (v, x),
-// rank[e] = {d_{v,x}, d_{x,v}}, and col_rank holds each row in descending order.
-// `keys` (nnz u64) is scratch: each piece's keys, sorted.  Needs the node records, the
-// row prefix ACC_sigma (for the neighbours' degrees) and the first row of every
-// 256-entry span of the CSR (`span_row`, spans + 1 entries).
-hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, int64_t nnz, const int32_t* span_row,
-                              const int32_t* rp, const int32_t* col, const uint4* rec, const uint32_t* acc_sigma,
-                              uint64_t* keys, uint2* rank, int32_t* col_rank, hipStream_t s);
+// rank[e] = {d_{v,x}, d_{x,v}}, and col_rank holds each row in descending order.  Needs
+// the node records, the row prefix ACC_sigma (for the neighbours' degrees), the first
+// row of every 256-entry span of the CSR (`span_row`, spans + 1 entries) and, for the
+// per-piece passes, the work items.  `scratch` (nnz u64) and `work`
+// (mirror_work_words(nnz) u32) are working memory; `validated`: the CSR passed the
+// creation checks (symmetric, sorted, no repeats), which the sort-based mirror pass
+// relies on.
+struct RankTables {
+  int64_t n_items;
+  const uint64_t* items;
+  int32_t n;
+  int64_t nnz;
+  int32_t max_degree;
+  bool validated;
+  const int32_t* span_row;
+  const int32_t* rp;
+  const int32_t* col;
+  const uint4* rec;
+  const uint32_t* acc_sigma;
+  uint64_t* scratch;
+  uint32_t* work;
+  uint2* rank;
+  int32_t* col_rank;
+};
+hipError_t launch_rank_tables(const RankTables& t, hipStream_t s);
+int64_t mirror_work_words(int64_t nnz);
 // w[v] = the last entry of v's row prefix `acc` (0 for an empty row).
 hipError_t launch_row_totals(int32_t n, const int32_t* rp, const uint64_t* acc, uint64_t* w, hipStream_t s);
 

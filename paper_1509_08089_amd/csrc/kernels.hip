@@ -1066,18 +1066,707 @@ __global__ __launch_bounds__(256) void k_rank_mirror(int64_t nnz, const int32_t*
   }
 }
 
-hipError_t launch_rank_tables(int64_t n_items, const uint64_t* items, int64_t nnz, const int32_t* span_row,
-                              const int32_t* rp, const int32_t* col, const uint4* rec, const uint32_t* acc_sigma,
-                              uint64_t* keys, uint2* rank, int32_t* col_rank, hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  const dim3 grid(item_grid(n_items)), block(256);
-  uint32_t* rank32 = reinterpret_cast<uint32_t*>(rank);
-  hipLaunchKernelGGL(k_rank_local, grid, block, 0, s, n_items, items, rp, col, acc_sigma, keys, rank32, col_rank);
-  const int merge_grid = (int)std::min<int64_t>(n_items, 65536);
-  hipLaunchKernelGGL(k_rank_merge, dim3(merge_grid), dim3(kItem), 0, s, n_items, items, rp, col, acc_sigma, keys,
-                     rank32, col_rank);
-  hipLaunchKernelGGL(k_rank_mirror, dim3(spans_grid(nnz)), block, 0, s, nnz, span_row, rp, col, rec, rank32);
+// ---------------------------------------------------------------------------------
+// The rank passes used when every degree is below 2^16 (a degree and a place within a
+// row then fit 16-bit fields).  They replace the per-piece passes above by passes that
+// read each entry a fixed number of times:
+//   short rows (d <= kItem)   one wave per 256-entry span ranks the rows that start in
+//                             the span (at most 511 entries, staged with their keys in
+//                             LDS): rows of up to kPairMax entries by counting, for each
+//                             entry, the keys of its row above its own; longer ones by a
+//                             bitonic sort of the row in registers (64, 128 or 256 keys)
+//   long rows                 one block per row: a stable LSD radix sort of the row by
+//                             degree, 8 bits a pass, over the places in descending order;
+//                             rows up to kLongMid entries sort with a small block, longer
+//                             ones with a full one, both in LDS (beyond kLongBig entries
+//                             in the row's own scratch)
+//   mirror ranks              in a validated CSR, sorting the entries stably by column
+//                             puts the entry (v, x) at the index of (x, v): the entries
+//                             of column x come in row order, i.e. in the order of row x,
+//                             and symmetry gives column x exactly d_x places from
+//                             row_ptr[x] on.  Two LSD radix passes over the column's bits
+//                             (one block per 8192-entry tile: count, exclusive scan of the
+//                             digit-major counts, stable scatter) carry d_{v,x} along, so
+//                             the second pass writes it straight into rank[mirror].y
+// Within a row, entries of equal degree rank by descending place, which is descending id
+// in a sorted row (the order of Section 3.2's example); repeated neighbours (possible
+// only in an unchecked CSR) get distinct ranks in some order.
+// ---------------------------------------------------------------------------------
+constexpr uint32_t kPairMax = 32;     // short rows up to this length rank by pairwise counts
+constexpr int32_t kLongMid = 2048;    // rows up to this length sort within one wave (64 x 32 keys)
+constexpr int32_t kLongBig = 32768;   // longer rows up to this length sort in LDS with 1024 threads
+
+// Lanes among `act` whose `bits`-bit digit equals this lane's (uniform control flow).
+__device__ __forceinline__ uint64_t wave_match(uint32_t digit, int bits, uint64_t act) {
+  uint64_t m = act;
+  for (int b = 0; b < bits; ++b) {
+    const bool one = (digit >> b) & 1u;
+    const uint64_t y = __ballot(one);
+    m &= one ? y : ~y;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return (uint32_t)__popcll(m & ((1ull << lane_id()) - 1ull));
+}
+
+__device__ __forceinline__ uint32_t wave_max_exclusive(uint32_t x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
+    if (lane >= off) x = max(x, y);
+  }
+  const uint32_t e = (uint32_t)__shfl_up((int)x, 1, 64);
+  return lane ? e : 0u;
+}
+
+// Ascending bitonic sort of the wave's 64 K values, lane l holding places l K .. l K + K - 1.
+template <int K>
+__device__ __forceinline__ void wave_bitonic(uint32_t (&a)[K]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= 64 * K; size <<= 1) {
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      if (j >= K) {  // the partner is in lane ^ (j / K), same slot
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const int i = lane * K + t;
+          const uint32_t b = (uint32_t)__shfl_xor((int)a[t], j / K, 64);
+          const bool low = (i & j) == 0, asc = (i & size) == 0;
+          a[t] = low == asc ? min(a[t], b) : max(a[t], b);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          if (t & j) continue;
+          const bool asc = ((lane * K + t) & size) == 0;
+          const uint32_t x = a[t], y = a[t | j];
+          a[t] = asc ? min(x, y) : max(x, y);
+          a[t | j] = asc ? max(x, y) : min(x, y);
+        }
+      }
+    }
+  }
+}
+
+// One row of d <= 64 K entries whose keys (degree << 32 | id) sit at key[os ..]: sorted on
+// ((0xFFFF - degree) << 8 | (255 - place)), so its q-th value is the entry of rank q.
+template <int K>
+__device__ void rank_row_wave(const uint64_t* key, uint32_t os, uint32_t d, int64_t r0, int zero_mirror,
+                              uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
+  const int lane = lane_id();
+  uint32_t a[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const uint32_t q = lane * K + t;
+    a[t] = q < d ? (0xFFFFu - (uint32_t)(key[os + q] >> 32)) << 8 | (255u - q) : 0xFFFFFFFFu;
+  }
+  wave_bitonic<K>(a);
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const uint32_t q = lane * K + t;
+    if (q >= d) continue;
+    const uint32_t place = 255u - (a[t] & 255u);
+    const int64_t e = r0 + place;
+    if (zero_mirror) reinterpret_cast<uint2*>(rank32)[e] = make_uint2(q, 0u);
+    else rank32[2 * e] = q;
+    col_rank[r0 + q] = (int32_t)(uint32_t)key[os + place];
+  }
+}
+
+// Short rows.  seg[o] marks a row starting at offset o of the span with
+// ((o + 1) << 16 | d); a running maximum over the offsets then gives every offset the
+// start and length of the last row starting at or before it, and the offset belongs to
+// that row iff it lies within its d entries.
+constexpr int kShortWin = 2 * (int)kSpan;
+constexpr int kShortSorted = 8;  // rows longer than kPairMax starting in one span (at most 256 / 33 + 1)
+
+__global__ __launch_bounds__(256) void k_rank_short(int64_t nnz, const int32_t* __restrict__ span_row,
+                                                    const uint4* __restrict__ rec, const int32_t* __restrict__ col,
+                                                    const uint32_t* __restrict__ sig, int zero_mirror,
+                                                    uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
+  __shared__ uint64_t s_key[4][kShortWin];
+  __shared__ __align__(16) uint32_t s_seg[4][kShortWin];
+  __shared__ uint32_t s_sorted[4][kShortSorted];
+  constexpr int kPer = kShortWin / 64;
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  uint64_t* key = s_key[w];
+  uint32_t* seg = s_seg[w];
+  uint32_t* sorted = s_sorted[w];
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t spans = (nnz + kSpan - 1) / kSpan;
+  for (int64_t sp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; sp < spans; sp += nwaves) {
+    const int64_t S = sp * kSpan;
+    const int32_t v0 = span_row[sp], last = span_row[sp + 1];
+#pragma unroll
+    for (int c = 0; c < kPer; ++c) seg[lane + 64 * c] = 0;
+    wave_lds_sync();
+    uint32_t end = 0, n_sorted = 0;  // one past the owned rows' last offset; rows to sort
+    for (int64_t j0 = v0; j0 <= (int64_t)last; j0 += 64) {  // wave-uniform
+      const int64_t j = j0 + lane;
+      bool to_sort = false;
+      uint32_t mark = 0;
+      if (j <= (int64_t)last) {
+        const uint2 rr = row_of(rec, (int32_t)j);
+        const int64_t o = (int64_t)rr.x - S;
+        if (o >= 0 && o < kSpan && rr.y >= 1u && rr.y <= (uint32_t)kItem) {
+          mark = (uint32_t)(o + 1) << 16 | rr.y;
+          seg[o] = mark;
+          end = max(end, (uint32_t)o + rr.y);
+          to_sort = rr.y > kPairMax;
+        }
+      }
+      const uint64_t sb = __ballot(to_sort);
+      if (to_sort) sorted[n_sorted + lanes_below(sb)] = mark;
+      n_sorted += (uint32_t)__popcll(sb);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, off, 64));
+    if (end == 0) continue;  // wave-uniform: no short row starts here
+    wave_lds_sync();
+    {  // running maximum over the offsets, eight consecutive offsets a lane
+      uint4 a = reinterpret_cast<const uint4*>(seg)[2 * lane], b = reinterpret_cast<const uint4*>(seg)[2 * lane + 1];
+      a.y = max(a.y, a.x);
+      a.z = max(a.z, a.y);
+      a.w = max(a.w, a.z);
+      b.x = max(b.x, a.w);
+      b.y = max(b.y, b.x);
+      b.z = max(b.z, b.y);
+      b.w = max(b.w, b.z);
+      const uint32_t before = wave_max_exclusive(b.w);
+      a = make_uint4(max(a.x, before), max(a.y, before), max(a.z, before), max(a.w, before));
+      b = make_uint4(max(b.x, before), max(b.y, before), max(b.z, before), max(b.w, before));
+      wave_lds_sync();
+      reinterpret_cast<uint4*>(seg)[2 * lane] = a;
+      reinterpret_cast<uint4*>(seg)[2 * lane + 1] = b;
+    }
+    wave_lds_sync();
+    {  // keys of the owned entries: all loads issued before the first is used
+      uint32_t xs[kPer], s1[kPer], s0[kPer];
+      bool own[kPer];
+#pragma unroll
+      for (int c = 0; c < kPer; ++c) {
+        const uint32_t o = lane + 64 * c, g = seg[o], os = (g >> 16) - 1u;
+        own[c] = g != 0 && o < os + (g & 0xFFFFu);
+        const int64_t e = own[c] ? S + o : S;  // S itself is a real entry
+        xs[c] = (uint32_t)col[e];
+        s1[c] = sig[e];
+        s0[c] = own[c] && o > os ? sig[e - 1] : 0u;
+      }
+#pragma unroll
+      for (int c = 0; c < kPer; ++c)
+        if (own[c]) key[lane + 64 * c] = (uint64_t)(s1[c] - s0[c] + 1u) << 32 | xs[c];
+    }
+    wave_lds_sync();
+#pragma unroll 1
+    for (int c = 0; c < kPer; ++c) {  // rows of up to kPairMax entries: pairwise counts
+      if (64u * c >= end) break;  // wave-uniform
+      const uint32_t o = lane + 64 * c, g = seg[o], os = (g >> 16) - 1u;
+      const uint32_t d = g != 0 && o < os + (g & 0xFFFFu) && (g & 0xFFFFu) <= kPairMax ? g & 0xFFFFu : 0u;
+      const bool own = d != 0;
+      const uint64_t k = own ? key[o] : 0ull;
+      uint32_t above = 0;
+      for (uint32_t t = os, t1 = os + d; t < t1; ++t) {
+        const uint64_t kt = key[t];
+        above += (kt > k || (kt == k && t > o)) ? 1u : 0u;
+      }
+      if (own) {
+        const int64_t e = S + o;
+        if (zero_mirror) reinterpret_cast<uint2*>(rank32)[e] = make_uint2(above, 0u);
+        else rank32[2 * e] = above;
+        col_rank[S + os + above] = (int32_t)(uint32_t)k;
+      }
+    }
+    for (uint32_t r = 0; r < n_sorted; ++r) {  // wave-uniform: the longer rows, sorted
+      const uint32_t g = sorted[r], os = (g >> 16) - 1u, d = g & 0xFFFFu;
+      if (d <= 64) rank_row_wave<1>(key, os, d, S + os, zero_mirror, rank32, col_rank);
+      else if (d <= 128) rank_row_wave<2>(key, os, d, S + os, zero_mirror, rank32, col_rank);
+      else rank_row_wave<4>(key, os, d, S + os, zero_mirror, rank32, col_rank);
+    }
+    wave_lds_sync();  // the LDS is reused by the wave's next span
+  }
+}
+
+// One long row [r0, r0 + d) by a block of kWaves waves: kv[i] = the degree of the
+// neighbour at place i (LDS, or the row's own scratch beyond the LDS size); perm holds
+// the order after the first pass.  Source position j of the first pass is place d - 1 - j.
+// Called by the whole block; returns synchronised.
+template <int kWaves>
+__device__ void rank_row_block(int32_t r0, int32_t d, int passes, const int32_t* __restrict__ col,
+                               const uint32_t* __restrict__ sig, uint16_t* kv, uint16_t* perm,
+                               uint32_t (*hist)[256], uint32_t* wave_tot, int zero_mirror,
+                               uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
+  const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+  for (int32_t i = tid; i < d; i += kWaves * 64) {
+    const uint32_t s1 = sig[r0 + i], s0 = i > 0 ? sig[r0 + i - 1] : 0u;
+    kv[i] = (uint16_t)(s1 - s0 + 1u);
+  }
+  const int32_t iters = (d + kWaves * 64 - 1) / (kWaves * 64);  // 64-entry groups per wave
+  const int32_t j0 = w * iters * 64;
+  for (int p = 0; p < passes; ++p) {
+    for (int i = lane; i < 256; i += 64) hist[w][i] = 0;
+    __syncthreads();  // kv, or the previous pass's perm, complete
+    for (int sweep = 0; sweep < 2; ++sweep) {  // 0: count, 1: scatter
+      for (int32_t it = 0; it < iters; ++it) {
+        const int32_t j = j0 + it * 64 + lane;
+        const bool valid = j < d;
+        const uint64_t act = __ballot(valid);
+        if (act == 0) break;  // wave-uniform
+        const int32_t i = !valid ? 0 : (p == 0 ? d - 1 - j : (int32_t)perm[j]);
+        const uint32_t dg = valid ? 255u - (((uint32_t)kv[i] >> (8 * p)) & 255u) : 0u;
+        const uint64_t m = wave_match(dg, 8, act);
+        const uint32_t below = lanes_below(m);
+        if (sweep == 0) {
+          if (valid && below == 0) hist[w][dg] += (uint32_t)__popcll(m);
+          continue;
+        }
+        const uint32_t base = valid ? hist[w][dg] : 0u;
+        if (valid && below == 0) hist[w][dg] = base + (uint32_t)__popcll(m);
+        const uint32_t pos = base + below;
+        if (!valid || pos >= (uint32_t)d) continue;  // never, with exact counts
+        if (p + 1 < passes) {
+          perm[pos] = (uint16_t)i;
+        } else {
+          const int64_t e = (int64_t)r0 + i;
+          if (zero_mirror) reinterpret_cast<uint2*>(rank32)[e] = make_uint2(pos, 0u);
+          else rank32[2 * e] = pos;
+        }
+      }
+      if (sweep == 1) break;
+      __syncthreads();  // every wave's counts are in
+      // digit t's first place: the counts of all smaller digits, then of the waves before
+      const int t = tid;
+      uint32_t tot = 0;
+      if (t < 256)
+        for (int q = 0; q < kWaves; ++q) tot += hist[q][t];
+      bool unused = false;
+      const uint32_t incl = (uint32_t)wave_inclusive_scan((uint64_t)tot, unused);
+      if (t < 256 && lane == 63) wave_tot[w] = incl;
+      __syncthreads();
+      if (t < 256) {
+        uint32_t run = incl - tot;
+        for (int q = 0; q < w; ++q) run += wave_tot[q];
+        for (int q = 0; q < kWaves; ++q) {
+          const uint32_t c = hist[q][t];
+          hist[q][t] = run;
+          run += c;
+        }
+      }
+      __syncthreads();
+    }
+    __syncthreads();  // this pass's perm (read by the next pass) and hist reads complete
+  }
+  // col_rank from the ranks just written (visible to the block after the barrier), with
+  // independent loads rather than one per step of the scatter
+#pragma unroll 4
+  for (int32_t i = tid; i < d; i += kWaves * 64) col_rank[r0 + (int32_t)rank32[2 * ((int64_t)r0 + i)]] = col[r0 + i];
+  __syncthreads();
+}
+
+// One row of kLongMid / 64 / 4 < d <= 64 K entries by one wave: its keys
+// ((0xFFFF - degree) << 16 | (0xFFFF - place)) sorted in registers, so that the q-th is
+// the entry of rank q.
+template <int K>
+__device__ void rank_row_wave_g(int32_t r0, int32_t d, const int32_t* __restrict__ col,
+                                const uint32_t* __restrict__ sig, int zero_mirror, uint32_t* __restrict__ rank32,
+                                int32_t* __restrict__ col_rank) {
+  const int lane = lane_id();
+  uint32_t a[K];
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const int32_t q = lane * K + t;
+    a[t] = 0xFFFFFFFFu;
+    if (q < d) {
+      const uint32_t s1 = sig[r0 + q], s0 = q > 0 ? sig[r0 + q - 1] : 0u;
+      a[t] = (0xFFFFu - (s1 - s0 + 1u)) << 16 | (0xFFFFu - (uint32_t)q);
+    }
+  }
+  wave_bitonic<K>(a);
+#pragma unroll
+  for (int t = 0; t < K; ++t) {
+    const int32_t q = lane * K + t;
+    if (q >= d) continue;
+    const int64_t e = (int64_t)r0 + (0xFFFFu - (a[t] & 0xFFFFu));
+    if (zero_mirror) reinterpret_cast<uint2*>(rank32)[e] = make_uint2((uint32_t)q, 0u);
+    else rank32[2 * e] = (uint32_t)q;
+    col_rank[r0 + q] = col[e];
+  }
+}
+
+// Rows with d_lo < d <= 64 K, one wave a row.  The grid's W waves check the rows
+// round-robin (wave g: rows g + k W), so that rows of any id pattern spread over them.
+template <int K>
+__global__ __launch_bounds__(256) void k_rank_rows_wave(int32_t n, const int32_t* __restrict__ rp, int32_t d_lo,
+                                                        const int32_t* __restrict__ col,
+                                                        const uint32_t* __restrict__ sig, int zero_mirror,
+                                                        uint32_t* __restrict__ rank32,
+                                                        int32_t* __restrict__ col_rank) {
+  const int lane = lane_id();
+  const int64_t W = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t v0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v0 < n; v0 += W * 64) {  // wave-uniform
+    const int64_t v = v0 + (int64_t)lane * W;
+    int32_t r0 = 0, d = 0;
+    if (v < n) {
+      r0 = rp[v];
+      d = rp[v + 1] - r0;
+    }
+    uint64_t m = __ballot(d > d_lo && d <= 64 * K);
+    while (m) {  // wave-uniform
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      rank_row_wave_g<K>(__shfl(r0, l, 64), __shfl(d, l, 64), col, sig, zero_mirror, rank32, col_rank);
+    }
+  }
+}
+
+// Rows longer than kLongMid, one block a row (found round-robin like the waves above),
+// sorted by rank_row_block in LDS up to kCap entries.
+template <int kCap, int kWaves>
+__global__ __launch_bounds__(kWaves * 64) void k_rank_long(int32_t n, const int32_t* __restrict__ rp,
+                                                           int32_t d_lo, const int32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ sig, int passes,
+                                                           int zero_mirror, uint32_t* __restrict__ rank32,
+                                                           int32_t* __restrict__ col_rank, uint64_t* scratch) {
+  constexpr int kT = kWaves * 64;
+  __shared__ uint16_t s_kv[kCap], s_perm[kCap];
+  __shared__ uint32_t hist[kWaves][256];
+  __shared__ uint32_t wave_tot[4];
+  __shared__ int32_t s_rows[kT];
+  __shared__ uint32_t s_count;
+  const int64_t G = gridDim.x;
+  for (int64_t v0 = blockIdx.x; v0 < n; v0 += G * kT) {  // block-uniform
+    if (threadIdx.x == 0) s_count = 0;
+    __syncthreads();
+    const int64_t v = v0 + (int64_t)threadIdx.x * G;
+    if (v < n) {
+      const int32_t d = rp[v + 1] - rp[v];
+      if (d > d_lo) s_rows[atomicAdd(&s_count, 1u)] = (int32_t)v;
+    }
+    __syncthreads();
+    const uint32_t rows = s_count;
+    for (uint32_t r = 0; r < rows; ++r) {  // block-uniform
+      const int32_t u = s_rows[r], r0 = rp[u], d = rp[u + 1] - r0;
+      if (d <= kCap) {
+        rank_row_block<kWaves>(r0, d, passes, col, sig, s_kv, s_perm, hist, wave_tot, zero_mirror, rank32, col_rank);
+      } else {  // the row's own d words of scratch hold its 2d u16
+        uint16_t* g = reinterpret_cast<uint16_t*>(scratch + r0);
+        rank_row_block<kWaves>(r0, d, passes, col, sig, g, g + d, hist, wave_tot, zero_mirror, rank32, col_rank);
+      }
+    }
+    __syncthreads();  // s_count and s_rows are reused
+  }
+}
+
+// Mirror sort: LSD passes of 8-bit digits over the column (three cover ids below
+// 2^24).  The first pass reads the entry's column and d_{v,x} (rank[e].x) and writes
+// (column >> 8) << 16 | d_{v,x}; later passes read those words, their digit being the
+// word's bits 16 + 8 (p - 1) on.  The last pass writes d_{v,x} into rank[place].y: the
+// entry at that place in column order is the mirror of the entry the word came from.
+constexpr int kMirWaves = 8;                         // waves per block (tile)
+constexpr int kMirWaveTile = 1024;                   // entries per wave: 16 groups of 64
+constexpr int kMirTile = kMirWaves * kMirWaveTile;   // entries per tile
+constexpr int kMirD = 256;                           // digits per pass
+
+template <bool First>
+__device__ __forceinline__ void mirror_item(const int32_t* __restrict__ col, const uint32_t* __restrict__ rank32,
+                                            const uint32_t* __restrict__ in, int64_t e, int64_t e1, int shift,
+                                            uint32_t& digit, uint32_t& word) {
+  digit = 0;
+  word = 0;
+  if (e >= e1) return;
+  if (First) {
+    const uint32_t c = (uint32_t)col[e];
+    digit = c & 255u;
+    word = (c >> 8) << 16 | (rank32[2 * e] & 0xFFFFu);
+  } else {
+    word = in[e];
+    digit = (word >> (16 + shift)) & 255u;
+  }
+}
+
+// counts[tile * 256 + digit]: the tile's entries with that digit (one block a tile)
+template <bool First>
+__global__ __launch_bounds__(kMirWaves * 64) void k_mirror_count(int64_t nnz, const int32_t* __restrict__ col,
+                                                                 const uint32_t* __restrict__ rank32,
+                                                                 const uint32_t* __restrict__ in, int shift,
+                                                                 uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_hist[kMirD];
+  constexpr int kT = kMirWaves * 64, kPer = kMirTile / kT;
+  const int64_t t = blockIdx.x, e0 = t * kMirTile, e1 = min(nnz, e0 + kMirTile);
+  if (threadIdx.x < kMirD) s_hist[threadIdx.x] = 0;
+  uint32_t dg[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    uint32_t word;
+    mirror_item<First>(col, rank32, in, e0 + u * kT + threadIdx.x, e1, shift, dg[u], word);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (e0 + u * kT + threadIdx.x < e1) atomicAdd(&s_hist[dg[u]], 1u);
+  __syncthreads();
+  if (threadIdx.x < kMirD) counts[t * kMirD + threadIdx.x] = s_hist[threadIdx.x];
+}
+
+// Stable scatter by the digit, one block a tile and each wave an eighth of it in order.
+// The tile is first put in digit order in LDS (words and digits at their places within
+// the tile), then written out in that order: each digit's run of a tile is about
+// kMirTile / 256 = 32 consecutive places, a full line per store instead of one place
+// per lane.
+template <bool First, bool Last>
+__global__ __launch_bounds__(kMirWaves * 64) void k_mirror_scatter(int64_t nnz, const int32_t* __restrict__ col,
+                                                                   uint32_t* __restrict__ rank32,
+                                                                   const uint32_t* __restrict__ in,
+                                                                   uint32_t* __restrict__ out, int shift,
+                                                                   const uint32_t* __restrict__ offsets) {
+  __shared__ uint32_t hist[kMirWaves][kMirD];  // each wave's next place per digit
+  __shared__ uint32_t delta[kMirD];            // place in the output - place in the tile
+  __shared__ uint32_t tw[kMirTile];            // words in tile order
+  __shared__ uint8_t td[kMirTile];             // their digits
+  __shared__ uint32_t wave_tot[kMirWaves];
+  constexpr int kIt = kMirWaveTile / 64, kT = kMirWaves * 64;
+  const int lane = lane_id(), w = threadIdx.x >> 6, tid = threadIdx.x;
+  const int64_t t = blockIdx.x, t0 = t * kMirTile, e1 = min(nnz, t0 + kMirTile);
+  const int32_t n_t = (int32_t)(e1 - t0);
+  const int64_t b = t0 + (int64_t)w * kMirWaveTile;  // this wave's part
+  uint32_t dg[kIt], word[kIt];
+#pragma unroll
+  for (int u = 0; u < kIt; ++u) mirror_item<First>(col, rank32, in, b + 64 * u + lane, e1, shift, dg[u], word[u]);
+  for (int i = lane; i < kMirD; i += 64) hist[w][i] = 0;
+  wave_lds_sync();
+#pragma unroll
+  for (int u = 0; u < kIt; ++u)  // column digits are spread evenly: plain atomics rarely collide
+    if (b + 64 * u + lane < e1) atomicAdd(&hist[w][dg[u]], 1u);
+  __syncthreads();
+  {  // places within the tile: digit-major, then wave (threads below 256: one digit each)
+    const int i = tid;
+    uint32_t sum = 0;
+    if (i < kMirD)
+      for (int q = 0; q < kMirWaves; ++q) sum += hist[q][i];
+    bool unused = false;
+    const uint32_t incl = (uint32_t)wave_inclusive_scan((uint64_t)sum, unused);
+    if (lane == 63) wave_tot[w] = incl;
+    __syncthreads();
+    if (i < kMirD) {
+      uint32_t run = incl - sum;
+      for (int q = 0; q < w; ++q) run += wave_tot[q];
+      delta[i] = offsets[t * kMirD + i] - run;
+      for (int q = 0; q < kMirWaves; ++q) {
+        const uint32_t c = hist[q][i];
+        hist[q][i] = run;
+        run += c;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kIt; ++u) {
+    const bool valid = b + 64 * u + lane < e1;
+    const uint64_t act = __ballot(valid);
+    if (act == 0) break;  // wave-uniform
+    const uint64_t m = wave_match(dg[u], 8, act);
+    const uint32_t below = lanes_below(m);
+    const uint32_t base = valid ? hist[w][dg[u]] : 0u;
+    if (valid && below == 0) hist[w][dg[u]] = base + (uint32_t)__popcll(m);
+    const uint32_t q = base + below;
+    if (!valid || q >= (uint32_t)n_t) continue;  // never, with exact counts
+    tw[q] = word[u];
+    td[q] = (uint8_t)dg[u];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int32_t q = tid; q < n_t; q += kT) {
+    const int64_t pos = (int64_t)q + delta[td[q]];
+    if (pos >= nnz) continue;  // never, with exact counts
+    if (Last) rank32[2 * pos + 1] = tw[q] & 0xFFFFu;
+    else out[pos] = tw[q];
+  }
+}
+
+// Exclusive scan over a block of 256 threads; `total` gets the block's sum.  Uses
+// wave_tot[4]; returns synchronised.
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t x, uint32_t* wave_tot, uint32_t& total) {
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  bool unused = false;
+  const uint32_t incl = (uint32_t)wave_inclusive_scan((uint64_t)x, unused);
+  if (lane == 63) wave_tot[w] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  total = 0;
+  for (int q = 0; q < 4; ++q) {
+    if (q < w) before += wave_tot[q];
+    total += wave_tot[q];
+  }
+  __syncthreads();  // wave_tot may be reused
+  return before + incl - x;
+}
+
+// The mirror sort's offsets: for tile-major counts c[t D + i], replace each by
+// base(i) + sum of c[t' D + i] over the tiles t' < t, base(i) being the count of all
+// entries with a smaller digit (the exclusive scan in digit-major order).  Chunks of
+// kCntChunk tiles: their per-digit sums S, the exclusive scan of S over the chunks of
+// each digit with the digit totals, the digits' bases, then each chunk's tiles in order.
+constexpr int kCntChunk = 64;
+
+__global__ __launch_bounds__(256) void k_cnt_chunk_sums(int64_t tiles, uint32_t D, const uint32_t* __restrict__ c,
+                                                        uint32_t* __restrict__ S) {
+  const uint32_t i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= D) return;
+  const int64_t t0 = (int64_t)blockIdx.x * kCntChunk, t1 = min(tiles, t0 + kCntChunk);
+  uint32_t sum = 0;
+#pragma unroll 8
+  for (int64_t t = t0; t < t1; ++t) sum += c[t * D + i];
+  S[(int64_t)blockIdx.x * D + i] = sum;
+}
+
+__global__ __launch_bounds__(256) void k_cnt_chunk_scan(int64_t chunks, uint32_t D, uint32_t* __restrict__ S,
+                                                        uint32_t* __restrict__ total) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= D) return;
+  uint32_t run = 0;
+  for (int64_t k0 = 0; k0 < chunks; k0 += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = k0 + u < chunks ? S[(k0 + u) * D + i] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (k0 + u < chunks) S[(k0 + u) * D + i] = run;
+      run += v[u];
+    }
+  }
+  total[i] = run;
+}
+
+__global__ __launch_bounds__(256) void k_cnt_digit_base(uint32_t D, uint32_t* __restrict__ total) {
+  __shared__ uint32_t wave_tot[4];
+  const uint32_t per = (D + 255) / 256, i0 = min(D, threadIdx.x * per), i1 = min(D, i0 + per);
+  uint32_t sum = 0;
+  for (uint32_t i = i0; i < i1; ++i) sum += total[i];
+  uint32_t all = 0;
+  uint32_t run = block_exclusive_256(sum, wave_tot, all);
+  for (uint32_t i = i0; i < i1; ++i) {
+    const uint32_t v = total[i];
+    total[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cnt_offsets(int64_t tiles, uint32_t D, uint32_t* __restrict__ c,
+                                                     const uint32_t* __restrict__ S, const uint32_t* __restrict__ base) {
+  const uint32_t i = blockIdx.y * 256 + threadIdx.x;
+  if (i >= D) return;
+  const int64_t t0 = (int64_t)blockIdx.x * kCntChunk, t1 = min(tiles, t0 + kCntChunk);
+  uint32_t run = base[i] + S[(int64_t)blockIdx.x * D + i];
+  for (int64_t q0 = t0; q0 < t1; q0 += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = q0 + u < t1 ? c[(q0 + u) * D + i] : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (q0 + u < t1) c[(q0 + u) * D + i] = run;
+      run += v[u];
+    }
+  }
+}
+
+// words of the mirror sort's counts and their scan: tiles x 256 counts, then S (chunks x
+// 256) and the 256 totals
+int64_t mirror_work_words(int64_t nnz) {
+  const int64_t tiles = (nnz + kMirTile - 1) / kMirTile;
+  return (tiles + (tiles + kCntChunk - 1) / kCntChunk + 1) * kMirD;
+}
+
+static hipError_t cnt_scan(int64_t tiles, uint32_t D, uint32_t* c, uint32_t* work, hipStream_t s) {
+  const int64_t chunks = (tiles + kCntChunk - 1) / kCntChunk;
+  uint32_t* S = work;
+  uint32_t* total = work + chunks * D;
+  const dim3 g2((unsigned)chunks, (D + 255) / 256);
+  hipLaunchKernelGGL(k_cnt_chunk_sums, g2, dim3(256), 0, s, tiles, D, c, S);
+  hipLaunchKernelGGL(k_cnt_chunk_scan, dim3((D + 255) / 256), dim3(256), 0, s, chunks, D, S, total);
+  hipLaunchKernelGGL(k_cnt_digit_base, dim3(1), dim3(256), 0, s, D, total);
+  hipLaunchKernelGGL(k_cnt_offsets, g2, dim3(256), 0, s, tiles, D, c, S, total);
   return hipGetLastError();
+}
+
+hipError_t launch_rank_tables(const RankTables& t, hipStream_t s) {
+  if (t.nnz <= 0) return hipSuccess;
+  const dim3 block(256);
+  uint32_t* rank32 = reinterpret_cast<uint32_t*>(t.rank);
+  const bool fast_local = t.max_degree < 65536;
+  int bits = 1;  // of the largest column id
+  while (bits < 31 && ((int64_t)1 << bits) < (int64_t)t.n) ++bits;
+  const int passes_m = (bits + 7) / 8;
+  // the words of alternate passes fill the two halves of `scratch`; they hold d_{v,x} <
+  // 2^16 and the column's bits above the first digit (below 2^16 for ids below 2^24)
+  const bool sort_mirror = fast_local && t.validated && passes_m <= 3 && t.work != nullptr;
+  const int zero_mirror = sort_mirror ? 0 : 1;
+  if (fast_local) {
+    hipLaunchKernelGGL(k_rank_short, dim3(spans_grid(t.nnz)), block, 0, s, t.nnz, t.span_row, t.rec, t.col,
+                       t.acc_sigma, zero_mirror, rank32, t.col_rank);
+    const int passes = t.max_degree < 256 ? 1 : 2;
+    if (t.max_degree > kItem) {
+      hipLaunchKernelGGL(k_rank_rows_wave<8>, dim3(2048), block, 0, s, t.n, t.rp, kItem, t.col, t.acc_sigma,
+                         zero_mirror, rank32, t.col_rank);
+    }
+    if (t.max_degree > 512) {
+      hipLaunchKernelGGL(k_rank_rows_wave<16>, dim3(2048), block, 0, s, t.n, t.rp, 512, t.col, t.acc_sigma,
+                         zero_mirror, rank32, t.col_rank);
+    }
+    if (t.max_degree > 1024) {
+      hipLaunchKernelGGL(k_rank_rows_wave<32>, dim3(2048), block, 0, s, t.n, t.rp, 1024, t.col, t.acc_sigma,
+                         zero_mirror, rank32, t.col_rank);
+    }
+    if (t.max_degree > kLongMid) {
+      hipLaunchKernelGGL((k_rank_long<kLongBig, 16>), dim3(256), dim3(1024), 0, s, t.n, t.rp, kLongMid, t.col,
+                         t.acc_sigma, passes, zero_mirror, rank32, t.col_rank, t.scratch);
+    }
+  } else if (t.n_items > 0) {
+    hipLaunchKernelGGL(k_rank_local, dim3(item_grid(t.n_items)), block, 0, s, t.n_items, t.items, t.rp, t.col,
+                       t.acc_sigma, t.scratch, rank32, t.col_rank);
+    const int merge_grid = (int)std::min<int64_t>(t.n_items, 65536);
+    hipLaunchKernelGGL(k_rank_merge, dim3(merge_grid), dim3(kItem), 0, s, t.n_items, t.items, t.rp, t.col,
+                       t.acc_sigma, t.scratch, rank32, t.col_rank);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (!sort_mirror) {
+    hipLaunchKernelGGL(k_rank_mirror, dim3(spans_grid(t.nnz)), block, 0, s, t.nnz, t.span_row, t.rp, t.col, t.rec,
+                       rank32);
+    return hipGetLastError();
+  }
+  const int64_t tiles = (t.nnz + kMirTile - 1) / kMirTile;
+  uint32_t* half[2] = {reinterpret_cast<uint32_t*>(t.scratch), reinterpret_cast<uint32_t*>(t.scratch) + t.nnz};
+  uint32_t* counts = t.work;
+  const dim3 mgrid((unsigned)tiles), mblock(kMirWaves * 64);
+  for (int p = 0; p < passes_m; ++p) {
+    const int shift = p ? 8 * (p - 1) : 0;
+    const bool first = p == 0, last = p + 1 == passes_m;
+    const uint32_t* in = first ? nullptr : half[(p - 1) & 1];
+    uint32_t* out = last ? nullptr : half[p & 1];
+    if (first) hipLaunchKernelGGL(k_mirror_count<true>, mgrid, mblock, 0, s, t.nnz, t.col, rank32, in, shift, counts);
+    else hipLaunchKernelGGL(k_mirror_count<false>, mgrid, mblock, 0, s, t.nnz, t.col, rank32, in, shift, counts);
+    e = cnt_scan(tiles, kMirD, counts, counts + tiles * kMirD, s);
+    if (e != hipSuccess) return e;
+    if (first && last) {
+      hipLaunchKernelGGL((k_mirror_scatter<true, true>), mgrid, mblock, 0, s, t.nnz, t.col, rank32, in, out, shift,
+                         counts);
+    } else if (first) {
+      hipLaunchKernelGGL((k_mirror_scatter<true, false>), mgrid, mblock, 0, s, t.nnz, t.col, rank32, in, out, shift,
+                         counts);
+    } else if (last) {
+      hipLaunchKernelGGL((k_mirror_scatter<false, true>), mgrid, mblock, 0, s, t.nnz, t.col, rank32, in, out, shift,
+                         counts);
+    } else {
+      hipLaunchKernelGGL((k_mirror_scatter<false, false>), mgrid, mblock, 0, s, t.nnz, t.col, rank32, in, out, shift,
+                         counts);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 __global__ void k_row_totals(int32_t n, const int32_t* __restrict__ rp, const uint64_t* __restrict__ acc,

@@ -2,9 +2,10 @@
 
 Rank tables, check-Gamma prefixes, per-sample classes and nodes, and the reach-count
 bins of the diamonds must be identical to the oracle's; the mixed 4-node finals within
-1e-12 relative.  Graphs include rows of several 256-entry pieces (the merge pass),
-rows past the row-guide threshold, many equal degrees (ties broken by id) and graphs
-with check-Gamma = 0."""
+1e-12 relative.  Graphs include rows of every rank pass (short rows ranked per span, long rows sorted
+per block in LDS or in their own scratch, degrees of 2^16 and more ranked per piece),
+rows past the row-guide threshold, many equal degrees (ties broken by id), CSRs created
+without the checks (searched mirrors) and graphs with check-Gamma = 0."""
 import numpy as np
 import pytest
 import torch
@@ -65,6 +66,47 @@ def test_mixed_estimate_matches_oracle(g, K, seed, mix):
     r = G.estimate(4, K, seed, mix | moss.MOSS_K4_MIN)
     assert r.gamma[1] == og.totals()["gamma_min"]
     assert_result_matches(r, og.estimate4min(K, seed, mix, threads=8), float(og.totals()["lambda3"]))
+
+
+def _hub_graph(leaves, extra=600, seed=3):
+    # node 0 joined to `leaves` nodes, with a sprinkle of edges among them (so that the
+    # hub's neighbours have different degrees) and a second, smaller hub
+    rng = np.random.default_rng(seed)
+    n = leaves + 1
+    edges = {(0, j) for j in range(1, n)}
+    edges |= {(1, j) for j in range(2, min(n, 3000))}
+    while len(edges) < leaves + min(n, 3000) - 2 + extra:
+        a, b = sorted(int(x) for x in rng.integers(1, n, 2))
+        if a != b:
+            edges.add((a, b))
+    return gg.from_edges(n, sorted(edges), f"hub {leaves}")
+
+
+def _check_min_tables(g, flags=0):
+    G = moss.Graph(g, flags=flags)
+    G.build_tables(moss.MOSS_TABLES_K4MIN)
+    og = oracle.Graph(g)
+    assert G.info().gamma_min == og.totals()["gamma_min"]
+    rank = G.table(moss.MOSS_TAB_RANK)
+    np.testing.assert_array_equal(rank[:, 0], og.table(oracle.TAB_RANK))
+    np.testing.assert_array_equal(rank[:, 1], og.table(oracle.TAB_RANK_MIRROR))
+    np.testing.assert_array_equal(G.table(moss.MOSS_TAB_COL_RANK), og.table(oracle.TAB_COL_RANK))
+    np.testing.assert_array_equal(G.table(moss.MOSS_TAB_ACC_CHECK), og.table(oracle.TAB_ACC_CHECK))
+    np.testing.assert_array_equal(G.table(moss.MOSS_TAB_ACC_GAMMA_MIN), og.table(oracle.TAB_ACC_GAMMA_MIN))
+
+
+@pytest.mark.parametrize("leaves", [5000, 40000, 70000], ids=["lds-block", "row-scratch", "degree-2^16"])
+def test_min_tables_hub_rows(leaves):
+    """A hub row sorted by the full block in LDS (d = 5000), in its own scratch (d = 40000,
+    beyond the LDS sort), and a degree of 2^16 or more (70000), where the per-piece rank
+    passes and the searched mirrors take over."""
+    _check_min_tables(_hub_graph(leaves))
+
+
+@pytest.mark.parametrize("g", [gg.chung_lu(5000, 40000, 2.1, 900, 12), _ties(), gg.complete(70)], ids=ids)
+def test_min_tables_trusted_csr(g):
+    """A CSR created without the checks takes the searched mirror pass; same tables."""
+    _check_min_tables(g, moss.MOSS_TRUST_CSR)
 
 
 def test_min_tables_after_other_sets():
