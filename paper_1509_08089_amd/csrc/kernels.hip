@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(256) void k_rank_mirror(int64_t nnz, const int32_t*
 // only in an unchecked CSR) get distinct ranks in some order.
 // ---------------------------------------------------------------------------------
 constexpr uint32_t kPairMax = 32;     // short rows up to this length rank by pairwise counts
-constexpr int32_t kLongMid = 2048;    // rows up to this length sort within one wave (64 x 32 keys)
+constexpr int32_t kLongMid = 2048;    // rows up to this length sort with a 256-thread block
 constexpr int32_t kLongBig = 32768;   // longer rows up to this length sort in LDS with 1024 threads
 
 // Lanes among `act` whose `bits`-bit digit equals this lane's (uniform control flow).
@@ -1300,6 +1300,7 @@ __device__ void rank_row_block(int32_t r0, int32_t d, int passes, const int32_t*
                                uint32_t (*hist)[256], uint32_t* wave_tot, int zero_mirror,
                                uint32_t* __restrict__ rank32, int32_t* __restrict__ col_rank) {
   const int tid = threadIdx.x, lane = lane_id(), w = tid >> 6;
+#pragma unroll 8
   for (int32_t i = tid; i < d; i += kWaves * 64) {
     const uint32_t s1 = sig[r0 + i], s0 = i > 0 ? sig[r0 + i - 1] : 0u;
     kv[i] = (uint16_t)(s1 - s0 + 1u);
@@ -1317,12 +1318,12 @@ __device__ void rank_row_block(int32_t r0, int32_t d, int passes, const int32_t*
         if (act == 0) break;  // wave-uniform
         const int32_t i = !valid ? 0 : (p == 0 ? d - 1 - j : (int32_t)perm[j]);
         const uint32_t dg = valid ? 255u - (((uint32_t)kv[i] >> (8 * p)) & 255u) : 0u;
-        const uint64_t m = wave_match(dg, 8, act);
-        const uint32_t below = lanes_below(m);
         if (sweep == 0) {
-          if (valid && below == 0) hist[w][dg] += (uint32_t)__popcll(m);
+          if (valid) atomicAdd(&hist[w][dg], 1u);
           continue;
         }
+        const uint64_t m = wave_match(dg, 8, act);
+        const uint32_t below = lanes_below(m);
         const uint32_t base = valid ? hist[w][dg] : 0u;
         if (valid && below == 0) hist[w][dg] = base + (uint32_t)__popcll(m);
         const uint32_t pos = base + below;
@@ -1366,97 +1367,58 @@ __device__ void rank_row_block(int32_t r0, int32_t d, int passes, const int32_t*
   __syncthreads();
 }
 
-// One row of kLongMid / 64 / 4 < d <= 64 K entries by one wave: its keys
-// ((0xFFFF - degree) << 16 | (0xFFFF - place)) sorted in registers, so that the q-th is
-// the entry of rank q.
-template <int K>
-__device__ void rank_row_wave_g(int32_t r0, int32_t d, const int32_t* __restrict__ col,
-                                const uint32_t* __restrict__ sig, int zero_mirror, uint32_t* __restrict__ rank32,
-                                int32_t* __restrict__ col_rank) {
-  const int lane = lane_id();
-  uint32_t a[K];
-#pragma unroll
-  for (int t = 0; t < K; ++t) {
-    const int32_t q = lane * K + t;
-    a[t] = 0xFFFFFFFFu;
-    if (q < d) {
-      const uint32_t s1 = sig[r0 + q], s0 = q > 0 ? sig[r0 + q - 1] : 0u;
-      a[t] = (0xFFFFu - (s1 - s0 + 1u)) << 16 | (0xFFFFu - (uint32_t)q);
-    }
+// Rows longer than kItem into two lists: up to kLongMid entries (mid) and longer (big).
+// Block b takes the rows [b c, (b + 1) c) in two coalesced sweeps, counting first so
+// that it reserves its places with one atomic per list.  counters[0..1] must be zero.
+__global__ __launch_bounds__(256) void k_long_rows(int32_t n, const int32_t* __restrict__ rp,
+                                                   int32_t* __restrict__ mid, int32_t* __restrict__ big,
+                                                   uint32_t* __restrict__ counters) {
+  __shared__ uint32_t s_cnt[2], s_base[2];
+  const int64_t chunk = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+  const int64_t v_begin = (int64_t)blockIdx.x * chunk, v_end = min((int64_t)n, v_begin + chunk);
+  if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t v = v_begin + threadIdx.x; v < v_end; v += 256) {
+    const int32_t d = rp[v + 1] - rp[v];
+    if (d > kItem) atomicAdd(&s_cnt[d <= kLongMid ? 0 : 1], 1u);
   }
-  wave_bitonic<K>(a);
-#pragma unroll
-  for (int t = 0; t < K; ++t) {
-    const int32_t q = lane * K + t;
-    if (q >= d) continue;
-    const int64_t e = (int64_t)r0 + (0xFFFFu - (a[t] & 0xFFFFu));
-    if (zero_mirror) reinterpret_cast<uint2*>(rank32)[e] = make_uint2((uint32_t)q, 0u);
-    else rank32[2 * e] = (uint32_t)q;
-    col_rank[r0 + q] = col[e];
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    s_base[threadIdx.x] = s_cnt[threadIdx.x] ? atomicAdd(&counters[threadIdx.x], s_cnt[threadIdx.x]) : 0u;
+    s_cnt[threadIdx.x] = 0;
   }
-}
-
-// Rows with d_lo < d <= 64 K, one wave a row.  The grid's W waves check the rows
-// round-robin (wave g: rows g + k W), so that rows of any id pattern spread over them.
-template <int K>
-__global__ __launch_bounds__(256) void k_rank_rows_wave(int32_t n, const int32_t* __restrict__ rp, int32_t d_lo,
-                                                        const int32_t* __restrict__ col,
-                                                        const uint32_t* __restrict__ sig, int zero_mirror,
-                                                        uint32_t* __restrict__ rank32,
-                                                        int32_t* __restrict__ col_rank) {
-  const int lane = lane_id();
-  const int64_t W = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t v0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; v0 < n; v0 += W * 64) {  // wave-uniform
-    const int64_t v = v0 + (int64_t)lane * W;
-    int32_t r0 = 0, d = 0;
-    if (v < n) {
-      r0 = rp[v];
-      d = rp[v + 1] - r0;
-    }
-    uint64_t m = __ballot(d > d_lo && d <= 64 * K);
-    while (m) {  // wave-uniform
-      const int l = __ffsll((unsigned long long)m) - 1;
-      m &= m - 1;
-      rank_row_wave_g<K>(__shfl(r0, l, 64), __shfl(d, l, 64), col, sig, zero_mirror, rank32, col_rank);
-    }
+  __syncthreads();
+  for (int64_t v = v_begin + threadIdx.x; v < v_end; v += 256) {
+    const int32_t d = rp[v + 1] - rp[v];
+    if (d <= kItem) continue;
+    const int which = d <= kLongMid ? 0 : 1;
+    const uint32_t at = s_base[which] + atomicAdd(&s_cnt[which], 1u);
+    (which ? big : mid)[at] = (int32_t)v;
   }
 }
 
-// Rows longer than kLongMid, one block a row (found round-robin like the waves above),
-// sorted by rank_row_block in LDS up to kCap entries.
+// The rows of a list, one block a row (block b: entries b, b + G, ...), sorted by
+// rank_row_block in LDS up to kCap entries.
 template <int kCap, int kWaves>
-__global__ __launch_bounds__(kWaves * 64) void k_rank_long(int32_t n, const int32_t* __restrict__ rp,
-                                                           int32_t d_lo, const int32_t* __restrict__ col,
+__global__ __launch_bounds__(kWaves * 64) void k_rank_long(const int32_t* __restrict__ list,
+                                                           const uint32_t* __restrict__ count,
+                                                           const int32_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
                                                            const uint32_t* __restrict__ sig, int passes,
                                                            int zero_mirror, uint32_t* __restrict__ rank32,
                                                            int32_t* __restrict__ col_rank, uint64_t* scratch) {
-  constexpr int kT = kWaves * 64;
   __shared__ uint16_t s_kv[kCap], s_perm[kCap];
   __shared__ uint32_t hist[kWaves][256];
   __shared__ uint32_t wave_tot[4];
-  __shared__ int32_t s_rows[kT];
-  __shared__ uint32_t s_count;
-  const int64_t G = gridDim.x;
-  for (int64_t v0 = blockIdx.x; v0 < n; v0 += G * kT) {  // block-uniform
-    if (threadIdx.x == 0) s_count = 0;
-    __syncthreads();
-    const int64_t v = v0 + (int64_t)threadIdx.x * G;
-    if (v < n) {
-      const int32_t d = rp[v + 1] - rp[v];
-      if (d > d_lo) s_rows[atomicAdd(&s_count, 1u)] = (int32_t)v;
+  const uint32_t rows = *count;
+  for (uint32_t r = blockIdx.x; r < rows; r += gridDim.x) {  // block-uniform
+    const int32_t v = list[r], r0 = rp[v], d = rp[v + 1] - r0;
+    if (d <= kCap) {
+      rank_row_block<kWaves>(r0, d, passes, col, sig, s_kv, s_perm, hist, wave_tot, zero_mirror, rank32, col_rank);
+    } else {  // the row's own d words of scratch hold its 2d u16
+      uint16_t* g = reinterpret_cast<uint16_t*>(scratch + r0);
+      rank_row_block<kWaves>(r0, d, passes, col, sig, g, g + d, hist, wave_tot, zero_mirror, rank32, col_rank);
     }
-    __syncthreads();
-    const uint32_t rows = s_count;
-    for (uint32_t r = 0; r < rows; ++r) {  // block-uniform
-      const int32_t u = s_rows[r], r0 = rp[u], d = rp[u + 1] - r0;
-      if (d <= kCap) {
-        rank_row_block<kWaves>(r0, d, passes, col, sig, s_kv, s_perm, hist, wave_tot, zero_mirror, rank32, col_rank);
-      } else {  // the row's own d words of scratch hold its 2d u16
-        uint16_t* g = reinterpret_cast<uint16_t*>(scratch + r0);
-        rank_row_block<kWaves>(r0, d, passes, col, sig, g, g + d, hist, wave_tot, zero_mirror, rank32, col_rank);
-      }
-    }
-    __syncthreads();  // s_count and s_rows are reused
   }
 }
 
@@ -1701,27 +1663,26 @@ hipError_t launch_rank_tables(const RankTables& t, hipStream_t s) {
   const int passes_m = (bits + 7) / 8;
   // the words of alternate passes fill the two halves of `scratch`; they hold d_{v,x} <
   // 2^16 and the column's bits above the first digit (below 2^16 for ids below 2^24)
-  const bool sort_mirror = fast_local && t.validated && passes_m <= 3 && t.work != nullptr;
+  const bool sort_mirror = fast_local && t.validated && passes_m <= 3;
   const int zero_mirror = sort_mirror ? 0 : 1;
+  hipError_t e = hipSuccess;
   if (fast_local) {
     hipLaunchKernelGGL(k_rank_short, dim3(spans_grid(t.nnz)), block, 0, s, t.nnz, t.span_row, t.rec, t.col,
                        t.acc_sigma, zero_mirror, rank32, t.col_rank);
     const int passes = t.max_degree < 256 ? 1 : 2;
-    if (t.max_degree > kItem) {
-      hipLaunchKernelGGL(k_rank_rows_wave<8>, dim3(2048), block, 0, s, t.n, t.rp, kItem, t.col, t.acc_sigma,
-                         zero_mirror, rank32, t.col_rank);
-    }
-    if (t.max_degree > 512) {
-      hipLaunchKernelGGL(k_rank_rows_wave<16>, dim3(2048), block, 0, s, t.n, t.rp, 512, t.col, t.acc_sigma,
-                         zero_mirror, rank32, t.col_rank);
-    }
-    if (t.max_degree > 1024) {
-      hipLaunchKernelGGL(k_rank_rows_wave<32>, dim3(2048), block, 0, s, t.n, t.rp, 1024, t.col, t.acc_sigma,
-                         zero_mirror, rank32, t.col_rank);
-    }
-    if (t.max_degree > kLongMid) {
-      hipLaunchKernelGGL((k_rank_long<kLongBig, 16>), dim3(256), dim3(1024), 0, s, t.n, t.rp, kLongMid, t.col,
+    if (t.max_degree > kItem) {  // the lists and their counters live in `work` until the mirror sort
+      uint32_t* counters = t.work;
+      int32_t* mid = reinterpret_cast<int32_t*>(t.work + 2);
+      int32_t* big = mid + t.nnz / (kItem + 1) + 1;
+      e = launch_fill_u32(counters, 0u, 2, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_long_rows, dim3(256), block, 0, s, t.n, t.rp, mid, big, counters);
+      hipLaunchKernelGGL((k_rank_long<kLongMid, 4>), dim3(2048), block, 0, s, mid, counters, t.rp, t.col,
                          t.acc_sigma, passes, zero_mirror, rank32, t.col_rank, t.scratch);
+      if (t.max_degree > kLongMid) {
+        hipLaunchKernelGGL((k_rank_long<kLongBig, 16>), dim3(256), dim3(1024), 0, s, big, counters + 1, t.rp, t.col,
+                           t.acc_sigma, passes, zero_mirror, rank32, t.col_rank, t.scratch);
+      }
     }
   } else if (t.n_items > 0) {
     hipLaunchKernelGGL(k_rank_local, dim3(item_grid(t.n_items)), block, 0, s, t.n_items, t.items, t.rp, t.col,
@@ -1730,7 +1691,7 @@ hipError_t launch_rank_tables(const RankTables& t, hipStream_t s) {
     hipLaunchKernelGGL(k_rank_merge, dim3(merge_grid), dim3(kItem), 0, s, t.n_items, t.items, t.rp, t.col,
                        t.acc_sigma, t.scratch, rank32, t.col_rank);
   }
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!sort_mirror) {
     hipLaunchKernelGGL(k_rank_mirror, dim3(spans_grid(t.nnz)), block, 0, s, t.nnz, t.span_row, t.rp, t.col, t.rec,
