@@ -865,7 +865,9 @@ hipError_t launch_row_tables(int mode, const RowTables& t, uint32_t* err, hipStr
 // node by degree, then id: with key(x) = d_x * 2^32 + x, x is above y exactly when
 // key(x) > key(y).  d_{v,x} = |{y in N_v : y above x}| is then x's place in row v
 // sorted by key, largest first, and col_rank lists the row in that order, so that
-// N_{v,x} is its first d_{v,x} entries.  The passes over the work items:
+// N_{v,x} is its first d_{v,x} entries.  The passes below serve when a degree reaches
+// 2^16, the CSR was not validated or ids reach 2^24 (the passes further down, which sort
+// instead of searching, take every other graph); they go over the work items:
 //   local    each piece ranks its entries among themselves, one wave per piece: every
 //            lane compares its keys with each key of the piece, broadcast from the lane
 //            that holds it; a neighbour's degree comes from the row's ACC_sigma
