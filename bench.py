@@ -511,7 +511,34 @@ def plain_steps(moss, gg, args, name, with_min=False):
         out["sampling_bytes"] = int(moss.moss_graph_get_info(info_h).sampling_bytes)
     finally:
         moss.moss_graph_destroy(info_h)
+    if not with_min:
+        out["table_build_ms"] = table_builds(moss, csr, d_rp, d_col, stream)
     return out, csr
+
+
+def table_builds(moss, csr, d_rp, d_col, stream, reps=5):
+    """Wall time of moss_build_tables on a freshly created graph (median of `reps` after
+    one warm-up each), per table set; "moss4min_part" = (4-node + MOSS-4Min) - 4-node."""
+    import torch
+    sets = {"k4": moss.MOSS_TABLES_K4, "k4+moss4min": moss.MOSS_TABLES_K4 | moss.MOSS_TABLES_K4MIN,
+            "k5": moss.MOSS_TABLES_K5}
+    out = {}
+    for label, mask in sets.items():
+        times = []
+        for i in range(reps + 1):
+            h = moss.moss_graph_create_device(csr.n, csr.nnz, d_rp, d_col, 0, stream)
+            try:
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                moss.moss_build_tables(h, mask)
+                torch.cuda.synchronize()
+                if i:
+                    times.append((time.perf_counter() - t) * 1e3)
+            finally:
+                moss.moss_graph_destroy(h)
+        out[label] = sorted(times)[len(times) // 2]
+    out["moss4min_part"] = out["k4+moss4min"] - out["k4"]
+    return out
 
 
 def accuracy5(moss, gg):
