@@ -12,6 +12,7 @@ import torch
 
 import graphgen as gg
 import oracle
+from graphgen.csr import CSR
 from gpu_util import assert_result_matches
 from paper_1509_08089_amd import moss
 
@@ -101,6 +102,33 @@ def test_min_tables_hub_rows(leaves):
     beyond the LDS sort), and a degree of 2^16 or more (70000), where the per-piece rank
     passes and the searched mirrors take over."""
     _check_min_tables(_hub_graph(leaves))
+
+
+def _boundary_graph(n, seed=5):
+    # 3000 nodes at the top of the id range (a hub among them) plus 50 low ids joined to
+    # them, in an otherwise empty graph of n nodes; the CSR is assembled with numpy
+    rng = np.random.default_rng(seed)
+    hi = np.arange(n - 3000, n)
+    e = {(int(x), n - 1) for x in hi[:2900]}
+    while len(e) < 2900 + 15000:
+        a, b = rng.choice(hi, 2)
+        if a != b:
+            e.add((int(min(a, b)), int(max(a, b))))
+    e |= {(lo, int(hi[lo * 7])) for lo in range(50)}
+    E = np.array(sorted(e), dtype=np.int64)
+    src, dst = np.concatenate([E[:, 0], E[:, 1]]), np.concatenate([E[:, 1], E[:, 0]])
+    o = np.lexsort((dst, src))
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, src[o] + 1, 1)
+    return CSR(np.cumsum(rp).astype(np.int32), dst[o].astype(np.int32), f"ids up to {n - 1}")
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n", [2**24, 2**24 + 1], ids=["ids-below-2^24", "ids-to-2^24"])
+def test_min_tables_id_boundary(n):
+    """Ids up to 2^24 - 1: the mirror sort's three 8-bit passes, the words holding the
+    column's top 16 bits; one more id: the searched mirrors take over."""
+    _check_min_tables(_boundary_graph(n))
 
 
 @pytest.mark.parametrize("g", [gg.chung_lu(5000, 40000, 2.1, 900, 12), _ties(), gg.complete(70)], ids=ids)
