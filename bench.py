@@ -92,6 +92,8 @@ def parse():
                                                "counter runs)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0, help="table memory budget of the server")
+    ap.add_argument("--serve-chunk", type=int, default=0, help="server: samples per request per iteration (0: 2^25)")
+    ap.add_argument("--serve-iteration", type=int, default=0, help="server: samples per iteration (0: 2^25)")
     ap.add_argument("--probe-only", type=int, default=0, metavar="BYTES",
                     help="only run the gather probe over a buffer of BYTES (for its counters)")
     ap.add_argument("--probe-chains", type=int, default=8)
@@ -562,7 +564,7 @@ def run_serving(moss, gg, args):
     torch.cuda.synchronize()
     log("[bench] C5: graphs ready")
     budget = int(args.serve_budget_gib * (1 << 30))
-    srv = moss.moss_server_create(budget, 256, 1 << 22)
+    srv = moss.moss_server_create(budget, 256, args.serve_chunk, iteration_samples=args.serve_iteration)
     results = {}
     try:
         ids = [moss.moss_server_add_graph(srv, g.h) for g in graphs]
@@ -595,6 +597,7 @@ def run_serving(moss, gg, args):
             "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "samples_per_s": st.samples_per_s,
             "offered_samples_per_s": offered, "wall_s": wall, "iterations": st.iterations,
             "mem_budget_bytes": budget, "evictions": int(st.evictions),
+            "chunk_samples": args.serve_chunk or 1 << 25, "iteration_samples": args.serve_iteration or 1 << 25,
             "checked_against_alone": len(results), "identical_results": bool(same)}
 
 

@@ -360,7 +360,12 @@ typedef struct {
   uint64_t mem_budget_bytes;   /* device bytes for sampling tables (0 = unlimited) */
   uint32_t max_slots;          /* requests in flight at once (0 = 256) */
   uint32_t reserved;
-  uint64_t chunk_samples;      /* samples per request per iteration (0 = 2^22) */
+  uint64_t chunk_samples;      /* at most this many samples per request per iteration (0 = 2^25) */
+  uint64_t iteration_samples;  /* samples per iteration in all (0 = 2^25): the requests with
+                                  the fewest samples left go first, each still gets at least
+                                  iteration_samples / 16 (within chunk_samples), so short
+                                  requests finish in the next launch and long ones take the
+                                  rest; no setting changes any result */
 } moss_server_config;
 
 typedef struct {

@@ -6,8 +6,11 @@
 //      (least recently used first) to stay within the memory budget; a request
 //      whose tables can never fit fails with MOSS_E_ADMISSION, one that must wait for
 //      running requests to finish stays queued;
-//   2. one batched launch runs the next chunk of samples of every admitted request
-//      (requests that arrived during the previous launch are in it);
+//   2. one batched launch runs the next samples of the admitted requests (requests
+//      that arrived during the previous launch are in it): about iteration_samples in
+//      all, the requests with the fewest samples left first, every request at least a
+//      sixteenth of that and at most chunk_samples, so a short request is done after
+//      the next launch while long ones take what is left;
 //   3. finished requests get their finals and wake their waiters.
 // Each request's samples keep their global indices, so its result does not depend on
 // how its work was chunked or what ran beside it.
@@ -205,18 +208,36 @@ void moss_server::loop() {
       }
       continue;
     }
-    // 2. next chunk of every admitted request
+    // 2. the next samples of the admitted requests, fewest left first
     std::vector<moss::WorkItem> work;
     std::vector<std::shared_ptr<Req>> batch = active;
     std::vector<uint64_t> upto(batch.size() * 2);
-    const uint64_t chunk = cfg.chunk_samples;
+    std::vector<uint64_t> left_of(batch.size());
+    std::vector<size_t> order(batch.size());
     for (size_t i = 0; i < batch.size(); ++i) {
+      const Req& r = *batch[i];
+      left_of[i] = (r.K[0] - r.next[0]) + (r.K[1] - r.next[1]);
+      order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return left_of[x] < left_of[y]; });
+    uint64_t budget = cfg.iteration_samples;
+    const uint64_t floor_share = std::max<uint64_t>(1, cfg.iteration_samples / 16);
+    for (size_t i : order) {
       Req& r = *batch[i];
       moss_graph* g = graphs[(size_t)r.graph_id].g;
       moss::EstimatePlan plan;
       (void)moss::plan_estimate(r.k, r.n, r.flags, &plan);
+      const uint64_t left = left_of[i];
+      const uint64_t give = std::min({left, cfg.chunk_samples, std::max(budget, floor_share)});
+      budget -= std::min(budget, give);
+      // the two samplers advance in proportion to what each has left
+      const uint64_t left0 = r.K[0] - r.next[0];
+      uint64_t g0 = left ? (uint64_t)(((unsigned __int128)give * left0 + left - 1) / left) : 0;
+      g0 = std::min(g0, left0);
+      const uint64_t g1 = std::min(r.K[1] - r.next[1], give - std::min(give, g0));
+      const uint64_t add[2] = {g0, g1};
       for (int s = 0; s < 2; ++s) {
-        const uint64_t b = s < plan.count ? std::min(r.K[s], r.next[s] + chunk) : r.next[s];
+        const uint64_t b = s < plan.count ? r.next[s] + add[s] : r.next[s];
         upto[2 * i + s] = b;
         if (b > r.next[s]) work.push_back({g, plan.sampler[s], r.seed, r.next[s], b, (uint32_t)(2 * i + s)});
       }
@@ -280,7 +301,8 @@ moss_status moss_server_create(const moss_server_config* cfg, void* hip_stream, 
   if (!s) return MOSS_E_NOMEM;
   if (cfg) s->cfg = *cfg;
   if (!s->cfg.max_slots) s->cfg.max_slots = 256;
-  if (!s->cfg.chunk_samples) s->cfg.chunk_samples = 1ull << 22;
+  if (!s->cfg.chunk_samples) s->cfg.chunk_samples = 1ull << 25;
+  if (!s->cfg.iteration_samples) s->cfg.iteration_samples = 1ull << 25;
   s->device = dev;
   s->runner = std::make_unique<BatchRunner>(dev);
   s->worker = std::thread([s] {

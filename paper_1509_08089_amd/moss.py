@@ -93,7 +93,8 @@ class moss_tuning(ctypes.Structure):
 
 class moss_server_config(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("chunk_samples", ctypes.c_uint64)]
+                ("reserved", ctypes.c_uint32), ("chunk_samples", ctypes.c_uint64),
+                ("iteration_samples", ctypes.c_uint64)]
 
 
 class moss_server_stats(ctypes.Structure):
@@ -330,8 +331,9 @@ def moss_autotune(requests):
     return best, ms.value
 
 
-def moss_server_create(mem_budget_bytes: int = 0, max_slots: int = 0, chunk_samples: int = 0, stream=None):
-    cfg = moss_server_config(mem_budget_bytes, max_slots, 0, chunk_samples)
+def moss_server_create(mem_budget_bytes: int = 0, max_slots: int = 0, chunk_samples: int = 0, stream=None,
+                       iteration_samples: int = 0):
+    cfg = moss_server_config(mem_budget_bytes, max_slots, 0, chunk_samples, iteration_samples)
     h = ctypes.c_void_p()
     _check(lib().moss_server_create(ctypes.byref(cfg), ctypes.c_void_p(0), ctypes.byref(h)), "moss_server_create")
     return h
