@@ -353,7 +353,9 @@ moss_status moss_autotune(const moss_request *reqs, int32_t n, moss_tuning *best
  * every admitted request into one tile list and runs it with the batched kernel, so
  * requests that arrive while others run join at the next iteration.  A request is
  * admitted when a slot is free and its graph's tables fit the memory budget (tables of
- * idle graphs are evicted, least recently used first). */
+ * idle graphs are evicted, the largest first, least recently used among equal sizes).
+ * Missing tables of a graph with no running request are built by a second server
+ * thread while launches go on; the request joins the iteration after they are in. */
 typedef struct moss_server moss_server;
 
 typedef struct {

@@ -1,11 +1,14 @@
 // Estimation server: continuous batching over resident graphs.
 //
 // A worker thread repeats one scheduling iteration:
-//   1. admission: while a slot is free, take the oldest waiting request; make sure
-//      its graph's tables for its k are resident, evicting the tables of idle graphs
-//      (least recently used first) to stay within the memory budget; a request
+//   1. admission: while a slot is free, take the waiting requests oldest first; make
+//      sure each one's graph has the tables for its k, evicting the tables of idle
+//      graphs (the largest first) to stay within the memory budget; a request
 //      whose tables can never fit fails with MOSS_E_ADMISSION, one that must wait for
-//      running requests to finish stays queued;
+//      running requests to finish stays queued (and so do the ones behind it).  The
+//      tables of an idle graph are built by a second thread while the launches go on
+//      (the request joins once they are in, its reserved bytes counted meanwhile); a
+//      graph with running requests gets its missing sets between two launches;
 //   2. one batched launch runs the next samples of the admitted requests (requests
 //      that arrived during the previous launch are in it): about iteration_samples in
 //      all, the requests with the fewest samples left first, every request at least a
@@ -50,6 +53,14 @@ struct GraphEntry {
   moss_graph* g = nullptr;
   uint64_t last_use = 0;
   int active = 0;
+  bool building = false;          // the builder thread owns g until it is done
+  uint64_t bytes_before = 0;      // g's table bytes when its build started
+  uint64_t build_need = 0;        // bytes the build adds (reserved meanwhile)
+};
+
+struct BuildJob {
+  int32_t graph_id;
+  uint32_t mask;
 };
 
 }  // namespace
@@ -58,9 +69,11 @@ struct moss_server {
   moss_server_config cfg{};
   int device = 0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::thread worker;
+  std::condition_variable cv_work, cv_done, cv_build;
+  std::thread worker, builder;
   bool stop = false;
+  std::deque<BuildJob> jobs;
+  uint64_t arrivals = 0, builds_done = 0, cancels = 0;  // what wakes an idle worker
   std::deque<std::shared_ptr<Req>> pending;
   std::vector<std::shared_ptr<Req>> active;
   std::unordered_map<uint64_t, std::shared_ptr<Req>> by_ticket;
@@ -84,18 +97,20 @@ struct moss_server {
     }
   }
 
+  // Table bytes held, a graph under construction at what it will hold.
   uint64_t resident_bytes() const {
     uint64_t b = 0;
-    for (const GraphEntry& e : graphs) b += e.g->table_bytes;
+    for (const GraphEntry& e : graphs) b += e.building ? e.bytes_before + e.build_need : e.g->table_bytes;
     return b;
   }
 
   enum class Room { kOk, kWait, kNever };
 
   // Makes room within the memory budget for building `mask` on ge's graph, with mu
-  // held: evicts the tables of idle graphs other than ge's (least recently used
-  // first), then, if ge's graph is idle, its own table sets that `mask` does not
-  // name.  kOk: the tables now fit.  kWait: what still stands in the way is held by
+  // held: evicts the tables of idle graphs other than ge's (the largest first, least
+  // recently used among equal sizes: one large eviction frees what several small ones
+  // would, and the small graphs it spares are cheap to keep), then, if ge's graph is
+  // idle, its own table sets that `mask` does not name.  kOk: the tables now fit.  kWait: what still stands in the way is held by
   // running requests, or by a call of another caller on an idle graph (its claim
   // failed), and will be released.  kNever: nothing left to evict.
   Room make_room(GraphEntry& ge, uint32_t mask) {
@@ -108,7 +123,9 @@ struct moss_server {
       GraphEntry* victim = nullptr;
       for (size_t i = 0; i < graphs.size(); ++i) {
         GraphEntry& e = graphs[i];
-        if (&e != &ge && !held[i] && e.active == 0 && e.g->built && (!victim || e.last_use < victim->last_use))
+        if (&e != &ge && !held[i] && !e.building && e.active == 0 && e.g->built &&
+            (!victim || e.g->table_bytes > victim->g->table_bytes ||
+             (e.g->table_bytes == victim->g->table_bytes && e.last_use < victim->last_use)))
           victim = &e;
       }
       uint32_t drop = MOSS_TABLES_K4 | MOSS_TABLES_K5 | MOSS_TABLES_K4MIN;
@@ -127,12 +144,13 @@ struct moss_server {
       moss::free_graph_tables(victim->g, drop);
       ++evictions;
     }
-    for (const GraphEntry& e : graphs)
-      if (e.active > 0 && e.g->table_bytes) waiting = true;
+    for (const GraphEntry& e : graphs)  // running requests, and builds, end
+      if (e.building || (e.active > 0 && e.g->table_bytes)) waiting = true;
     return waiting ? Room::kWait : Room::kNever;
   }
 
   void loop();
+  void build_loop();
 };
 
 void moss_server::loop() {
@@ -148,47 +166,60 @@ void moss_server::loop() {
       return;
     }
     // 1. admission
-    bool blocked = false;  // the oldest waiting request waits for memory to be released
-    while (active.size() < cfg.max_slots && !pending.empty()) {
-      std::shared_ptr<Req> r = pending.front();
+    bool blocked = false;  // a waiting request waits for memory to be released
+    for (auto it = pending.begin(); it != pending.end() && active.size() < cfg.max_slots;) {
+      std::shared_ptr<Req> r = *it;
       if (r->cancelled) {
-        pending.pop_front();
         finish(r, MOSS_E_CANCELLED);
+        it = pending.erase(it);
         continue;
       }
       GraphEntry& ge = graphs[(size_t)r->graph_id];
+      if (ge.building) {  // joins once its graph's tables are in
+        ++it;
+        continue;
+      }
       moss::EstimatePlan plan;
       (void)moss::plan_estimate(r->k, r->n, r->flags, &plan);  // checked at submission
       const uint32_t mask = plan.tables;
       if ((ge.g->built & mask) != mask) {
         const uint64_t need = moss::table_bytes_needed(ge.g, mask);
         if (cfg.mem_budget_bytes && need > cfg.mem_budget_bytes) {
-          pending.pop_front();
           finish(r, MOSS_E_ADMISSION);
+          it = pending.erase(it);
           continue;
         }
         const Room room = make_room(ge, mask);
         if (room == Room::kNever) {
-          pending.pop_front();
           finish(r, MOSS_E_ADMISSION);
+          it = pending.erase(it);
           continue;
         }
-        if (room == Room::kWait) {  // running requests (or another caller) will release memory
+        if (room == Room::kWait) {  // running requests, builds (or another caller) will release memory
           blocked = true;
           break;
         }
-        moss_status st;
+        if (ge.active == 0) {  // an idle graph: its tables are built beside the launches
+          ge.building = true;
+          ge.bytes_before = ge.g->table_bytes;
+          ge.build_need = need;
+          jobs.push_back({r->graph_id, mask});
+          cv_build.notify_one();
+          ++it;
+          continue;
+        }
+        moss_status st;  // a graph with running requests: its missing sets go in now
         {
           moss::GraphClaim claim(ge.g);
           st = claim.ok() ? moss::build_tables(ge.g, mask) : MOSS_E_BUSY;
         }
         if (st != MOSS_OK) {
-          pending.pop_front();
           finish(r, st);
+          it = pending.erase(it);
           continue;
         }
       }
-      pending.pop_front();
+      it = pending.erase(it);
       moss_result hdr;
       moss::result_header(ge.g, r->k, r->n, r->flags, &hdr);
       r->K[0] = hdr.K[0];
@@ -199,12 +230,14 @@ void moss_server::loop() {
     cv_done.notify_all();
     if (active.empty()) {
       if (blocked) {
-        // only a call of another caller on an idle graph holds the memory; its end is
-        // not signalled here, so look again shortly (the wait releases mu)
+        // only a call of another caller on an idle graph (or a build) holds the memory;
+        // the former's end is not signalled here, so look again shortly (the wait
+        // releases mu)
         cv_work.wait_for(lk, std::chrono::milliseconds(1), [&] { return stop; });
       } else {
-        // nothing waiting: wait for a new arrival or a stop
-        cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+        // nothing admissible: wait for a new arrival, a finished build, a cancel or a stop
+        const uint64_t a0 = arrivals, b0 = builds_done, c0 = cancels;
+        cv_work.wait(lk, [&] { return stop || arrivals != a0 || builds_done != b0 || cancels != c0; });
       }
       continue;
     }
@@ -286,6 +319,43 @@ void moss_server::loop() {
   }
 }
 
+// The builder thread: builds the tables of an idle graph (claimed meanwhile) while the
+// worker's launches go on, then lets the worker admit the requests that waited for them;
+// a failed build fails them with its status.
+void moss_server::build_loop() {
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv_build.wait(lk, [&] { return stop || !jobs.empty(); });
+    if (stop) return;  // builds not started are dropped: the worker cancelled their requests
+    const BuildJob job = jobs.front();
+    jobs.pop_front();
+    moss_graph* g = graphs[(size_t)job.graph_id].g;
+    lk.unlock();
+    moss_status st;
+    {
+      moss::GraphClaim claim(g);
+      st = claim.ok() ? moss::build_tables(g, job.mask) : MOSS_E_BUSY;
+    }
+    lk.lock();
+    graphs[(size_t)job.graph_id].building = false;
+    ++builds_done;
+    if (st != MOSS_OK) {
+      for (auto it = pending.begin(); it != pending.end();) {
+        moss::EstimatePlan plan;
+        (void)moss::plan_estimate((*it)->k, (*it)->n, (*it)->flags, &plan);
+        if ((*it)->graph_id == job.graph_id && (plan.tables & job.mask)) {
+          finish(*it, st);
+          it = pending.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      cv_done.notify_all();
+    }
+    cv_work.notify_all();
+  }
+}
+
 using namespace moss;
 
 extern "C" {
@@ -308,6 +378,10 @@ moss_status moss_server_create(const moss_server_config* cfg, void* hip_stream, 
   s->worker = std::thread([s] {
     DeviceScope scope(s->device);
     s->loop();
+  });
+  s->builder = std::thread([s] {
+    DeviceScope scope(s->device);
+    s->build_loop();
   });
   *out = s;
   return MOSS_OK;
@@ -347,6 +421,7 @@ moss_status moss_server_submit(moss_server* s, int32_t graph_id, int32_t k, uint
     s->pending.push_back(r);
     s->by_ticket[r->ticket] = r;
     *ticket = r->ticket;
+    ++s->arrivals;
   }
   s->cv_work.notify_one();
   return MOSS_OK;
@@ -374,6 +449,7 @@ moss_status moss_server_cancel(moss_server* s, uint64_t ticket) {
   auto it = s->by_ticket.find(ticket);
   if (it == s->by_ticket.end()) return MOSS_E_ARG;
   it->second->cancelled = true;
+  ++s->cancels;
   s->cv_work.notify_one();
   return MOSS_OK;
 }
@@ -412,7 +488,9 @@ moss_status moss_server_destroy(moss_server* s) {
     s->stop = true;
   }
   s->cv_work.notify_all();
+  s->cv_build.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  if (s->builder.joinable()) s->builder.join();  // a build under way finishes first
   s->runner->release();
   delete s;
   return MOSS_OK;

@@ -228,6 +228,36 @@ def test_server_evicts_own_idle_tables():
         moss.moss_server_destroy(srv)
 
 
+def test_server_evicts_largest_idle_tables_first():
+    """Two small graphs and a large one, used small, large, then the other small one,
+    under a budget that holds the large tables and one small set but not a second small
+    set beside them: the third request must evict the large graph's tables (the largest
+    idle ones) and keep the first small graph's, though that one was used longer ago."""
+    small = [gg.chung_lu(2000, 12000, 2.2, 200, 60 + i) for i in range(2)]
+    large = gg.chung_lu(12000, 90000, 2.2, 800, 62)
+    bs = max(_table_bytes(g, moss.MOSS_TABLES_K4) for g in small)
+    bl = _table_bytes(large, moss.MOSS_TABLES_K4)
+    budget = bl + bs + bs // 2
+    assert bl > bs and bl + 2 * bs > budget
+    hs = [moss.Graph(g) for g in small]
+    hl = moss.Graph(large)
+    base = [h.info().device_bytes for h in hs], hl.info().device_bytes
+    srv = moss.moss_server_create(budget, 4, 10_000)
+    try:
+        ids = [moss.moss_server_add_graph(srv, h.h) for h in (hs[0], hl, hs[1])]
+        for i, (gid, g) in enumerate(zip(ids, (small[0], large, small[1]))):
+            r = moss.moss_server_wait(srv, moss.moss_server_submit(srv, gid, 4, 30_000, i + 1),
+                                      60_000)
+            np.testing.assert_array_equal(r.hits_np, moss.Graph(g).estimate(4, 30_000, i + 1).hits_np)
+        st = moss.moss_server_stats_get(srv)
+        assert st.evictions == 1 and st.table_bytes <= budget
+        assert hl.info().device_bytes == base[1]            # large tables evicted
+        assert hs[0].info().device_bytes > base[0][0]       # first small graph's kept
+        assert hs[1].info().device_bytes > base[0][1]
+    finally:
+        moss.moss_server_destroy(srv)
+
+
 def test_server_refuses_sets_that_never_fit_together():
     """MOSS-4 + MOSS-4Min needs the 4-node and the MOSS-4Min tables at once; with a budget
     below their sum and the 4-node tables already resident, the request is refused with
