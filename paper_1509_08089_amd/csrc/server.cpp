@@ -110,9 +110,10 @@ struct moss_server {
   // held: evicts the tables of idle graphs other than ge's (the largest first, least
   // recently used among equal sizes: one large eviction frees what several small ones
   // would, and the small graphs it spares are cheap to keep), then, if ge's graph is
-  // idle, its own table sets that `mask` does not name.  kOk: the tables now fit.  kWait: what still stands in the way is held by
-  // running requests, or by a call of another caller on an idle graph (its claim
-  // failed), and will be released.  kNever: nothing left to evict.
+  // idle, its own table sets that `mask` does not name.  kOk: the tables now fit.
+  // kWait: what still stands in the way is held by running requests, by a build under
+  // way, or by a call of another caller on an idle graph (its claim failed), and will
+  // be released.  kNever: nothing left to evict.
   Room make_room(GraphEntry& ge, uint32_t mask) {
     const uint64_t budget = cfg.mem_budget_bytes;
     if (!budget) return Room::kOk;
