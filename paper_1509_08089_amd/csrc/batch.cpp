@@ -238,6 +238,7 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
 
   // views: one per distinct (graph, sampler)
   std::vector<SamplerView> views;
+  std::vector<const moss_graph*> view_graph;  // the graph of each view
   std::map<std::pair<const moss_graph*, int>, uint32_t> view_of;
   std::vector<BatchItem> items;
   std::vector<uint64_t> item_cost;
@@ -288,6 +289,7 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     if (it == view_of.end()) {
       vi = (uint32_t)views.size();
       views.push_back(sampler_view(w.g, w.sampler));
+      view_graph.push_back(w.g);
       view_of[key] = vi;
     } else {
       vi = it->second;
@@ -305,15 +307,23 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
   // Graph-major order: the items of one (graph, sampler) view run together, so at any
   // moment the chip works on one graph's tables and they stay in L2 and the MALL
   // (interleaving the graphs of a batch measured about 15% slower per sample).  The
-  // views with the most work go first, and the largest items first within a view.  The
-  // kernel cuts each item into tiles itself; the host hands over the item list only.
-  std::vector<uint64_t> view_cost(views.size(), 0);
+  // views of the graphs with the largest sampled footprint go first, then those with
+  // the most work, and the largest items first within a view: the large graphs' items
+  // then run while the grouped launches on the side stream read the same tables (0.8%
+  // faster on a 256-request batch than most work first; smallest graphs first was 1%
+  // slower).  The kernel cuts each item into tiles itself; the host hands over the
+  // item list only.
+  std::vector<uint64_t> view_cost(views.size(), 0), view_fp(views.size(), 0);
   for (size_t i = 0; i < items.size(); ++i) view_cost[items[i].view] += item_cost[i];
+  for (size_t vi = 0; vi < views.size(); ++vi) view_fp[vi] = sampling_footprint(view_graph[vi]);
   std::vector<size_t> order(items.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
     const uint32_t vx = items[x].view, vy = items[y].view;
-    if (vx != vy) return view_cost[vx] != view_cost[vy] ? view_cost[vx] > view_cost[vy] : vx < vy;
+    if (vx != vy) {
+      if (view_fp[vx] != view_fp[vy]) return view_fp[vx] > view_fp[vy];
+      return view_cost[vx] != view_cost[vy] ? view_cost[vx] > view_cost[vy] : vx < vy;
+    }
     return item_cost[x] > item_cost[y];
   });
   uint64_t n_tiles = 0;
