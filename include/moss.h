@@ -353,7 +353,8 @@ moss_status moss_autotune(const moss_request *reqs, int32_t n, moss_tuning *best
  * every admitted request into one tile list and runs it with the batched kernel, so
  * requests that arrive while others run join at the next iteration.  A request is
  * admitted when a slot is free and its graph's tables fit the memory budget (tables of
- * idle graphs are evicted, the largest first, least recently used among equal sizes).
+ * idle graphs are evicted, the largest first, least recently used among equal sizes);
+ * small requests (express_samples) take an express path beside the iterations.
  * Missing tables of a graph with no running request are built by a second server
  * thread while launches go on; the request joins the iteration after they are in. */
 typedef struct moss_server moss_server;
@@ -361,13 +362,17 @@ typedef struct moss_server moss_server;
 typedef struct {
   uint64_t mem_budget_bytes;   /* device bytes for sampling tables (0 = unlimited) */
   uint32_t max_slots;          /* requests in flight at once (0 = 256) */
-  uint32_t reserved;
+  uint32_t express_off;        /* non-zero: every request goes through the iterations */
   uint64_t chunk_samples;      /* at most this many samples per request per iteration (0 = 2^25) */
   uint64_t iteration_samples;  /* samples per iteration in all (0 = 2^25): the requests with
                                   the fewest samples left go first, each still gets at least
                                   iteration_samples / 16 (within chunk_samples), so short
                                   requests finish in the next launch and long ones take the
                                   rest; no setting changes any result */
+  uint64_t express_samples;    /* requests of at most this many samples (0 = 2^20) are
+                                  launched whole by an express thread with a runner of its
+                                  own as soon as their tables are in, beside the iteration
+                                  under way, instead of waiting for it to end */
 } moss_server_config;
 
 typedef struct {
@@ -380,6 +385,7 @@ typedef struct {
   double samples_per_s;        /* samples of completed requests / wall time since first submit */
   uint64_t table_bytes;        /* device bytes of resident tables now */
   uint64_t evictions;
+  uint64_t express_launches;   /* launches of the express thread */
 } moss_server_stats;
 
 moss_status moss_server_create(const moss_server_config *cfg, void *hip_stream, moss_server **out);

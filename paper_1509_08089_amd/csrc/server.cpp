@@ -15,6 +15,10 @@
 //      sixteenth of that and at most chunk_samples, so a short request is done after
 //      the next launch while long ones take what is left;
 //   3. finished requests get their finals and wake their waiters.
+// Requests of at most express_samples samples skip the iterations: once their graph's
+// tables are in, an express thread with a runner of its own launches all of them that
+// wait, whole, beside the iteration under way (the persistent kernels leave block
+// slots free), so a small request does not wait for a long launch to end.
 // Each request's samples keep their global indices, so its result does not depend on
 // how its work was chunked or what ran beside it.
 #include <algorithm>
@@ -69,8 +73,8 @@ struct moss_server {
   moss_server_config cfg{};
   int device = 0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done, cv_build;
-  std::thread worker, builder;
+  std::condition_variable cv_work, cv_done, cv_build, cv_express;
+  std::thread worker, builder, express;
   bool stop = false;
   std::deque<BuildJob> jobs;
   uint64_t arrivals = 0, builds_done = 0, cancels = 0;  // what wakes an idle worker
@@ -79,11 +83,11 @@ struct moss_server {
   std::unordered_map<uint64_t, std::shared_ptr<Req>> by_ticket;
   std::vector<GraphEntry> graphs;
   uint64_t next_ticket = 1;
-  uint64_t iterations = 0, completed = 0, samples_done = 0, evictions = 0;
+  uint64_t iterations = 0, completed = 0, samples_done = 0, evictions = 0, express_launches = 0;
   std::vector<double> latencies_ms;
   bool have_first = false;
   Clock::time_point t_first, t_last;
-  std::unique_ptr<moss::BatchRunner> runner;
+  std::unique_ptr<moss::BatchRunner> runner, express_runner;
 
   void finish(const std::shared_ptr<Req>& r, moss_status st) {
     r->status = st;
@@ -102,6 +106,21 @@ struct moss_server {
     uint64_t b = 0;
     for (const GraphEntry& e : graphs) b += e.building ? e.bytes_before + e.build_need : e.g->table_bytes;
     return b;
+  }
+
+  // A request the express thread takes (when its graph's tables are in).
+  bool express_size(const Req& r) const { return !cfg.express_off && r.n <= cfg.express_samples; }
+
+  // The table sets of r's request, and whether they are resident and usable now.
+  static uint32_t tables_of(const Req& r) {
+    moss::EstimatePlan plan;
+    (void)moss::plan_estimate(r.k, r.n, r.flags, &plan);  // checked at submission
+    return plan.tables;
+  }
+  bool tables_ready(const Req& r) const {
+    const GraphEntry& ge = graphs[(size_t)r.graph_id];
+    const uint32_t mask = tables_of(r);
+    return !ge.building && (ge.g->built & mask) == mask;
   }
 
   enum class Room { kOk, kWait, kNever };
@@ -152,6 +171,7 @@ struct moss_server {
 
   void loop();
   void build_loop();
+  void express_loop();
 };
 
 void moss_server::loop() {
@@ -180,9 +200,12 @@ void moss_server::loop() {
         ++it;
         continue;
       }
-      moss::EstimatePlan plan;
-      (void)moss::plan_estimate(r->k, r->n, r->flags, &plan);  // checked at submission
-      const uint32_t mask = plan.tables;
+      const uint32_t mask = tables_of(*r);
+      const bool small = express_size(*r);
+      if (small && (ge.g->built & mask) == mask) {  // the express thread takes it
+        ++it;
+        continue;
+      }
       if ((ge.g->built & mask) != mask) {
         const uint64_t need = moss::table_bytes_needed(ge.g, mask);
         if (cfg.mem_budget_bytes && need > cfg.mem_budget_bytes) {
@@ -219,6 +242,11 @@ void moss_server::loop() {
           it = pending.erase(it);
           continue;
         }
+        if (small) {  // its tables are in: the express thread takes it
+          cv_express.notify_one();
+          ++it;
+          continue;
+        }
       }
       it = pending.erase(it);
       moss_result hdr;
@@ -236,9 +264,13 @@ void moss_server::loop() {
         // releases mu)
         cv_work.wait_for(lk, std::chrono::milliseconds(1), [&] { return stop; });
       } else {
-        // nothing admissible: wait for a new arrival, a finished build, a cancel or a stop
-        const uint64_t a0 = arrivals, b0 = builds_done, c0 = cancels;
-        cv_work.wait(lk, [&] { return stop || arrivals != a0 || builds_done != b0 || cancels != c0; });
+        // nothing admissible: wait for a new arrival, a finished build, a cancel, an
+        // express launch (its graphs went idle; a waiting request may need their
+        // tables rebuilt or their memory) or a stop
+        const uint64_t a0 = arrivals, b0 = builds_done, c0 = cancels, x0 = express_launches;
+        cv_work.wait(lk, [&] {
+          return stop || arrivals != a0 || builds_done != b0 || cancels != c0 || express_launches != x0;
+        });
       }
       continue;
     }
@@ -354,6 +386,75 @@ void moss_server::build_loop() {
       cv_done.notify_all();
     }
     cv_work.notify_all();
+    cv_express.notify_one();
+  }
+}
+
+// The express thread: launches every waiting request of at most express_samples
+// samples whose tables are in, each whole, with a runner of its own; the graphs it
+// uses count as active meanwhile, so their tables are not evicted under it.
+void moss_server::express_loop() {
+  std::unique_lock<std::mutex> lk(mu);
+  auto ready = [&](const Req& r) { return !r.cancelled && express_size(r) && tables_ready(r); };
+  for (;;) {
+    cv_express.wait(lk, [&] {
+      if (stop) return true;
+      for (const auto& r : pending)
+        if (ready(*r)) return true;
+      return false;
+    });
+    if (stop) return;  // the worker cancels what is still pending
+    std::vector<std::shared_ptr<Req>> batch;
+    for (auto it = pending.begin(); it != pending.end() && batch.size() < cfg.max_slots;) {
+      const std::shared_ptr<Req> r = *it;
+      if (!ready(*r)) {
+        ++it;
+        continue;
+      }
+      it = pending.erase(it);
+      GraphEntry& ge = graphs[(size_t)r->graph_id];
+      moss_result hdr;
+      moss::result_header(ge.g, r->k, r->n, r->flags, &hdr);
+      r->K[0] = hdr.K[0];
+      r->K[1] = hdr.K[1];
+      ge.active += 1;
+      batch.push_back(r);
+    }
+    std::vector<moss::WorkItem> work;
+    for (size_t i = 0; i < batch.size(); ++i) {
+      const Req& r = *batch[i];
+      moss::EstimatePlan plan;
+      (void)moss::plan_estimate(r.k, r.n, r.flags, &plan);
+      for (int s = 0; s < plan.count; ++s)
+        if (r.K[s]) work.push_back({graphs[(size_t)r.graph_id].g, plan.sampler[s], r.seed, 0, r.K[s], (uint32_t)(2 * i + s)});
+    }
+    lk.unlock();
+    std::vector<uint64_t> bins(batch.size() * 2 * 22, 0);
+    const moss_status st = work.empty() ? MOSS_OK
+                                        : express_runner->run(work, (uint32_t)(batch.size() * 2), bins.data(),
+                                                              nullptr, nullptr, 0, 0, true);
+    lk.lock();
+    ++express_launches;
+    for (size_t i = 0; i < batch.size(); ++i) {
+      const std::shared_ptr<Req>& r = batch[i];
+      GraphEntry& ge = graphs[(size_t)r->graph_id];
+      ge.last_use = iterations;
+      ge.active -= 1;
+      if (st != MOSS_OK) {
+        finish(r, st);
+      } else if (r->cancelled) {
+        finish(r, MOSS_E_CANCELLED);
+      } else {
+        moss_result res;
+        moss::result_header(ge.g, r->k, r->n, r->flags, &res);
+        for (int s = 0; s < 2; ++s)
+          for (int c = 0; c < 22; ++c) res.hits[s][c] = bins[(2 * i + s) * 22 + c];
+        r->result = res;
+        finish(r, moss_finals(&r->result));
+      }
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();  // graphs went idle: their memory may be what a request waits for
   }
 }
 
@@ -374,8 +475,10 @@ moss_status moss_server_create(const moss_server_config* cfg, void* hip_stream, 
   if (!s->cfg.max_slots) s->cfg.max_slots = 256;
   if (!s->cfg.chunk_samples) s->cfg.chunk_samples = 1ull << 25;
   if (!s->cfg.iteration_samples) s->cfg.iteration_samples = 1ull << 25;
+  if (!s->cfg.express_samples) s->cfg.express_samples = 1ull << 20;
   s->device = dev;
   s->runner = std::make_unique<BatchRunner>(dev);
+  s->express_runner = std::make_unique<BatchRunner>(dev);
   s->worker = std::thread([s] {
     DeviceScope scope(s->device);
     s->loop();
@@ -383,6 +486,10 @@ moss_status moss_server_create(const moss_server_config* cfg, void* hip_stream, 
   s->builder = std::thread([s] {
     DeviceScope scope(s->device);
     s->build_loop();
+  });
+  s->express = std::thread([s] {
+    DeviceScope scope(s->device);
+    s->express_loop();
   });
   *out = s;
   return MOSS_OK;
@@ -425,6 +532,7 @@ moss_status moss_server_submit(moss_server* s, int32_t graph_id, int32_t k, uint
     ++s->arrivals;
   }
   s->cv_work.notify_one();
+  s->cv_express.notify_one();
   return MOSS_OK;
 }
 
@@ -465,6 +573,7 @@ moss_status moss_server_stats_get(moss_server* s, moss_server_stats* out) {
   r.queued = s->pending.size();
   r.active = s->active.size();
   r.evictions = s->evictions;
+  r.express_launches = s->express_launches;
   r.table_bytes = s->resident_bytes();
   if (!s->latencies_ms.empty()) {
     std::vector<double> v = s->latencies_ms;
@@ -490,9 +599,12 @@ moss_status moss_server_destroy(moss_server* s) {
   }
   s->cv_work.notify_all();
   s->cv_build.notify_all();
+  s->cv_express.notify_all();
   if (s->worker.joinable()) s->worker.join();
-  if (s->builder.joinable()) s->builder.join();  // a build under way finishes first
+  if (s->express.joinable()) s->express.join();  // a launch under way finishes first
+  if (s->builder.joinable()) s->builder.join();  // and so does a build
   s->runner->release();
+  s->express_runner->release();
   delete s;
   return MOSS_OK;
 }

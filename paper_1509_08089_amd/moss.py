@@ -93,15 +93,15 @@ class moss_tuning(ctypes.Structure):
 
 class moss_server_config(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("max_slots", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("chunk_samples", ctypes.c_uint64),
-                ("iteration_samples", ctypes.c_uint64)]
+                ("express_off", ctypes.c_uint32), ("chunk_samples", ctypes.c_uint64),
+                ("iteration_samples", ctypes.c_uint64), ("express_samples", ctypes.c_uint64)]
 
 
 class moss_server_stats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("samples", ctypes.c_uint64), ("iterations", ctypes.c_uint64),
                 ("queued", ctypes.c_uint64), ("active", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("samples_per_s", ctypes.c_double), ("table_bytes", ctypes.c_uint64),
-                ("evictions", ctypes.c_uint64)]
+                ("evictions", ctypes.c_uint64), ("express_launches", ctypes.c_uint64)]
 
 
 _lock = threading.Lock()
@@ -332,8 +332,9 @@ def moss_autotune(requests):
 
 
 def moss_server_create(mem_budget_bytes: int = 0, max_slots: int = 0, chunk_samples: int = 0, stream=None,
-                       iteration_samples: int = 0):
-    cfg = moss_server_config(mem_budget_bytes, max_slots, 0, chunk_samples, iteration_samples)
+                       iteration_samples: int = 0, express_samples: int = 0, express: bool = True):
+    cfg = moss_server_config(mem_budget_bytes, max_slots, 0 if express else 1, chunk_samples, iteration_samples,
+                             express_samples)
     h = ctypes.c_void_p()
     _check(lib().moss_server_create(ctypes.byref(cfg), ctypes.c_void_p(0), ctypes.byref(h)), "moss_server_create")
     return h

@@ -140,10 +140,11 @@ def test_autotune_keeps_results(graphs):
     moss.moss_set_tuning(0, 0, 0)
 
 
-def test_server_alone_and_in_mix(graphs):
+@pytest.mark.parametrize("express", [True, False])
+def test_server_alone_and_in_mix(graphs, express):
     gs, handles = graphs
     reqs = _requests(handles, 80, 4)
-    srv = moss.moss_server_create(0, 16, 50_000)
+    srv = moss.moss_server_create(0, 16, 50_000, express_samples=20_000, express=express)
     try:
         ids = [moss.moss_server_add_graph(srv, h.h) for h in handles]
         gid = {h.h.value: i for i, h in enumerate(handles)}
@@ -158,7 +159,40 @@ def test_server_alone_and_in_mix(graphs):
             np.testing.assert_array_equal(a.hits_np, r.hits_np)
             np.testing.assert_array_equal(a.estimate_np, r.estimate_np)
         st = moss.moss_server_stats_get(srv)
-        assert st.completed == len(reqs) and st.iterations >= 1 and st.p99_ms >= st.p50_ms > 0
+        assert st.completed == len(reqs) and st.p99_ms >= st.p50_ms > 0
+        small = sum(1 for q in reqs if q[2] <= 20_000)
+        assert 0 < small < len(reqs)
+        if express:
+            assert st.express_launches >= 1 and st.iterations >= 1
+        else:
+            assert st.express_launches == 0 and st.iterations >= 1
+    finally:
+        moss.moss_server_destroy(srv)
+
+
+def test_server_express_beside_a_long_request(graphs):
+    """Small requests submitted while a long request runs in the iterations take the
+    express path: they finish while it is still running, with the results they have
+    alone, and so does the long request."""
+    gs, handles = graphs
+    srv = moss.moss_server_create(0, 16, 1 << 20, iteration_samples=1 << 20)
+    try:
+        gid = moss.moss_server_add_graph(srv, handles[5].h)
+        sid = moss.moss_server_add_graph(srv, handles[1].h)
+        t_long = moss.moss_server_submit(srv, gid, 5, 200_000_000, 7)
+        small = [(sid, 4 + (i % 2), 50_000 + 1000 * i, 100 + i) for i in range(6)]
+        ts = [moss.moss_server_submit(srv, *q) for q in small]
+        for q, t in zip(small, ts):
+            r = moss.moss_server_wait(srv, t, 60_000)
+            a = moss.moss_estimate(handles[1].h, q[1], q[2], q[3], 0)
+            np.testing.assert_array_equal(a.hits_np, r.hits_np)
+            np.testing.assert_array_equal(a.estimate_np, r.estimate_np)
+        st = moss.moss_server_stats_get(srv)
+        assert st.express_launches >= 1
+        assert st.active == 1  # the long request is still in its iterations
+        r = moss.moss_server_wait(srv, t_long, 120_000)
+        a = moss.moss_estimate(handles[5].h, 5, 200_000_000, 7, 0)
+        np.testing.assert_array_equal(a.hits_np, r.hits_np)
     finally:
         moss.moss_server_destroy(srv)
 
