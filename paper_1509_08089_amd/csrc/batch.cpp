@@ -326,6 +326,21 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     }
     return item_cost[x] > item_cost[y];
   });
+  // A batch too small to give every block of the grid a tile gets smaller tiles (a
+  // multiple of the block's threads, about its samples over the blocks): otherwise a
+  // few blocks draw their lanes' samples one after another while the rest idle, and
+  // a 10^4-sample request took 0.1-0.2 ms of kernel time instead of a few tens of µs.
+  // The tiling does not change which samples are drawn, only which lanes draw them.
+  uint64_t persistent = 0, tiles_at_T = 0;
+  for (const BatchItem& b : items) {
+    persistent += b.k1 - b.k0;
+    tiles_at_T += (b.k1 - b.k0 + T - 1) / T;
+  }
+  if (tiles_at_T < (uint64_t)grid) {
+    const uint64_t per_block = (persistent + (uint64_t)grid - 1) / (uint64_t)grid;
+    const uint64_t t = std::max<uint64_t>((uint64_t)block, (per_block + block - 1) / block * block);
+    if (t < T) T = (uint32_t)t;
+  }
   uint64_t n_tiles = 0;
   for (size_t i : order) {
     items[i].first_tile = (uint32_t)n_tiles;
