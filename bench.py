@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--serve-chunk", type=int, default=0, help="server: samples per request per iteration (0: 2^25)")
     ap.add_argument("--serve-iteration", type=int, default=0, help="server: samples per iteration (0: 2^25)")
     ap.add_argument("--serve-express", type=int, default=0,
-                    help="server: requests of at most this many samples take the express path (0: 2^20; "
+                    help="server: requests of at most this many samples take the express path (0: 2^22; "
                          "negative: none)")
     ap.add_argument("--probe-only", type=int, default=0, metavar="BYTES",
                     help="only run the gather probe over a buffer of BYTES (for its counters)")
@@ -610,7 +610,7 @@ def run_serving(moss, gg, args):
             "offered_samples_per_s": offered, "wall_s": wall, "iterations": st.iterations,
             "mem_budget_bytes": budget, "evictions": int(st.evictions),
             "chunk_samples": args.serve_chunk or 1 << 25, "iteration_samples": args.serve_iteration or 1 << 25,
-            "express_samples": (args.serve_express or 1 << 20) if args.serve_express >= 0 else None,
+            "express_samples": (args.serve_express or 1 << 22) if args.serve_express >= 0 else None,
             "express_launches": int(st.express_launches),
             "checked_against_alone": len(results), "identical_results": bool(same)}
 

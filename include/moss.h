@@ -369,7 +369,7 @@ typedef struct {
                                   iteration_samples / 16 (within chunk_samples), so short
                                   requests finish in the next launch and long ones take the
                                   rest; no setting changes any result */
-  uint64_t express_samples;    /* requests of at most this many samples (0 = 2^20) are
+  uint64_t express_samples;    /* requests of at most this many samples (0 = 2^22) are
                                   launched whole by an express thread with a runner of its
                                   own as soon as their tables are in, beside the iteration
                                   under way, instead of waiting for it to end */

@@ -475,7 +475,7 @@ moss_status moss_server_create(const moss_server_config* cfg, void* hip_stream, 
   if (!s->cfg.max_slots) s->cfg.max_slots = 256;
   if (!s->cfg.chunk_samples) s->cfg.chunk_samples = 1ull << 25;
   if (!s->cfg.iteration_samples) s->cfg.iteration_samples = 1ull << 25;
-  if (!s->cfg.express_samples) s->cfg.express_samples = 1ull << 20;
+  if (!s->cfg.express_samples) s->cfg.express_samples = 1ull << 22;
   s->device = dev;
   s->runner = std::make_unique<BatchRunner>(dev);
   s->express_runner = std::make_unique<BatchRunner>(dev);
