@@ -30,7 +30,7 @@ class BatchRunner {
   // first.  tile_samples / blocks_per_cu of 0 use the current tuning.  With
   // `sort_large`, items with many samples on graphs past the L2s run instead as grouped
   // launches of their own (the plain path's grouping passes and sorted sampling
-  // kernel), after the persistent kernel, adding into their histogram slots.
+  // kernel), beside the persistent kernel, adding into their histogram slots.
   moss_status run(const std::vector<WorkItem>& work, uint32_t n_slots, uint64_t* bins_out, double* device_ms,
                   hipStream_t wait_on, uint32_t tile_samples = 0, uint32_t blocks_per_cu = 0,
                   bool sort_large = false);
@@ -46,8 +46,8 @@ class BatchRunner {
 
   int device_;
   hipStream_t stream_ = nullptr;
-  hipStream_t side_ = nullptr;  // the grouped launches, beside the persistent kernel
-  hipEvent_t ev0_ = nullptr, ev1_ = nullptr, ev_wait_ = nullptr, ev_clear_ = nullptr, ev_side_ = nullptr;
+  hipStream_t side_[2] = {};  // the grouped launches in two chains, beside the persistent kernel
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr, ev_wait_ = nullptr, ev_clear_ = nullptr, ev_side_[2] = {};
   SamplerView* d_views_ = nullptr;
   BatchItem* d_items_ = nullptr;
   uint32_t* d_ctl_ = nullptr;  // control words (kCtl*)

@@ -430,9 +430,10 @@ void moss_server::express_loop() {
     }
     lk.unlock();
     std::vector<uint64_t> bins(batch.size() * 2 * 22, 0);
+    // all in the persistent kernel: at these sizes the grouping passes do not pay
     const moss_status st = work.empty() ? MOSS_OK
                                         : express_runner->run(work, (uint32_t)(batch.size() * 2), bins.data(),
-                                                              nullptr, nullptr, 0, 0, true);
+                                                              nullptr, nullptr, 0, 0, false);
     lk.lock();
     ++express_launches;
     for (size_t i = 0; i < batch.size(); ++i) {
