@@ -380,7 +380,7 @@ typedef struct {
   uint64_t samples;            /* samples drawn by completed requests */
   uint64_t iterations;         /* scheduler iterations (batched launches) */
   uint64_t queued;             /* requests waiting for admission now */
-  uint64_t active;             /* requests admitted and running now */
+  uint64_t active;             /* requests admitted and running now (express path included) */
   double p50_ms, p99_ms;       /* submit-to-result latency over completed requests */
   double samples_per_s;        /* samples of completed requests / wall time since first submit */
   uint64_t table_bytes;        /* device bytes of resident tables now */

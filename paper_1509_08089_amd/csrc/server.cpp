@@ -84,6 +84,7 @@ struct moss_server {
   std::vector<GraphEntry> graphs;
   uint64_t next_ticket = 1;
   uint64_t iterations = 0, completed = 0, samples_done = 0, evictions = 0, express_launches = 0;
+  uint64_t express_running = 0;  // requests in the express launch under way
   std::vector<double> latencies_ms;
   bool have_first = false;
   Clock::time_point t_first, t_last;
@@ -428,6 +429,7 @@ void moss_server::express_loop() {
       for (int s = 0; s < plan.count; ++s)
         if (r.K[s]) work.push_back({graphs[(size_t)r.graph_id].g, plan.sampler[s], r.seed, 0, r.K[s], (uint32_t)(2 * i + s)});
     }
+    express_running = batch.size();
     lk.unlock();
     std::vector<uint64_t> bins(batch.size() * 2 * 22, 0);
     // all in the persistent kernel: at these sizes the grouping passes do not pay
@@ -436,6 +438,7 @@ void moss_server::express_loop() {
                                                               nullptr, nullptr, 0, 0, false);
     lk.lock();
     ++express_launches;
+    express_running = 0;
     for (size_t i = 0; i < batch.size(); ++i) {
       const std::shared_ptr<Req>& r = batch[i];
       GraphEntry& ge = graphs[(size_t)r->graph_id];
@@ -572,7 +575,7 @@ moss_status moss_server_stats_get(moss_server* s, moss_server_stats* out) {
   r.samples = s->samples_done;
   r.iterations = s->iterations;
   r.queued = s->pending.size();
-  r.active = s->active.size();
+  r.active = s->active.size() + s->express_running;
   r.evictions = s->evictions;
   r.express_launches = s->express_launches;
   r.table_bytes = s->resident_bytes();
