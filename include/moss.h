@@ -361,7 +361,8 @@ typedef struct moss_server moss_server;
 
 typedef struct {
   uint64_t mem_budget_bytes;   /* device bytes for sampling tables (0 = unlimited) */
-  uint32_t max_slots;          /* requests in flight at once (0 = 256) */
+  uint32_t max_slots;          /* requests in the iterations at once, and in one express
+                                  launch (0 = 256) */
   uint32_t express_off;        /* non-zero: every request goes through the iterations */
   uint64_t chunk_samples;      /* at most this many samples per request per iteration (0 = 2^25) */
   uint64_t iteration_samples;  /* samples per iteration in all (0 = 2^25): the requests with
