@@ -90,9 +90,10 @@ def parse():
     ap.add_argument("--only", default="", help="comma list of c4,c2,c3,c5,acc5,probe,cpu,c2min,c3min; or c4-step, "
                                                "c2-step, c3-step, c2min-step, c3min-step (just the timed steps, for "
                                                "counter runs)")
-    ap.add_argument("--tuning", default="", metavar="T,B,G,F",
-                    help="c4-step: the batched launch's tiles, blocks per CU and grouping thresholds (2^G samples, "
-                         "F MB) as the full run's autotuner picked them (default: the library's)")
+    ap.add_argument("--tuning", default="", metavar="T,B,G,F[,W]",
+                    help="c4-step: the batched launch's tiles, blocks per CU, grouping thresholds (2^G samples, "
+                         "F MB) and sorted window W as the full run's autotuner picked them (default: the "
+                         "library's)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gib", type=float, default=4.0, help="table memory budget of the server")
     ap.add_argument("--serve-chunk", type=int, default=0, help="server: samples per request per iteration (0: 2^25)")
@@ -414,15 +415,16 @@ def run_c4(moss, gg, args, step_only=False):
     log(f"[bench] C4: tables built ({build_s:.2f} s)")
     out = {"requests": len(q), "graphs": len(graphs), "samples": total, "table_build_s": build_s}
     if step_only and args.tuning:
-        tile, bpc, gs, gf = (int(x) for x in args.tuning.split(","))
-        moss.moss_set_tuning(tile, bpc, 0, 0, gs, gf)
+        tile, bpc, gs, gf, win = ([int(x) for x in args.tuning.split(",")] + [0])[:5]
+        moss.moss_set_tuning(tile, bpc, 0, 0, gs, gf, win)
         out["tuning"] = {"tile_samples": tile, "blocks_per_cu": bpc, "group_min_samples_log2": gs,
-                         "group_min_footprint_mb": gf}
+                         "group_min_footprint_mb": gf, "sort_window": win}
     if not step_only:
         best, tune_ms = moss.moss_autotune(q)
         out["tuning"] = {"tile_samples": best.tile_samples, "blocks_per_cu": best.blocks_per_cu,
                          "group_min_samples_log2": best.group_min_samples_log2,
-                         "group_min_footprint_mb": best.group_min_footprint_mb, "autotune_best_ms": tune_ms}
+                         "group_min_footprint_mb": best.group_min_footprint_mb, "sort_window": best.sort_window,
+                         "autotune_best_ms": tune_ms}
         log(f"[bench] C4: autotuned ({best.tile_samples} samples per tile, {best.blocks_per_cu} blocks/CU, grouping "
             f"thresholds {best.group_min_samples_log2 or 'default'} / {best.group_min_footprint_mb or 'default'})")
     for i in range(args.warmup):

@@ -334,6 +334,9 @@ typedef struct {
   uint32_t schedule;
   uint32_t group_min_samples_log2;  /* <= 40 */
   uint32_t group_min_footprint_mb;  /* <= 2^20 */
+  uint32_t sort_window;             /* samples a block of the sorted sampling kernel takes at
+                                       a time (a multiple of 64, <= 512; 0 = 256 on graphs
+                                       past 256 MB of sampled bytes, else 512) */
 } moss_tuning;
 
 moss_status moss_set_tuning(const moss_tuning *t);
@@ -343,8 +346,8 @@ moss_status moss_get_tuning(moss_tuning *t);
    staging included; best of two calls) first for each tile size {2048, 4096, 16384,
    65536} and occupancy {2, 3, 4, 5, 6, 8} blocks per CU, then, with the best of those,
    for each grouping threshold (items of at least 2^{17..22} samples on graphs of at
-   least {4, 8, 16, 32, 64} MB of sampled bytes); results are identical for every
-   candidate (checked).  Keeps the fastest as the process-wide tuning (the schedule knob
+   least {4, 8, 16, 32, 64} MB of sampled bytes), then for each sorted window {128, 256,
+   512} of the grouped launches; results are identical for every candidate (checked).  Keeps the fastest as the process-wide tuning (the schedule knob
    is left as it was); best_ms receives its wall time. */
 moss_status moss_autotune(const moss_request *reqs, int32_t n, moss_tuning *best, double *best_ms);
 

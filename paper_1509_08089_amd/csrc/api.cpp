@@ -982,7 +982,7 @@ moss_status run_samplers(moss_graph* g, const int* samplers, const uint64_t* k0,
     }
   }
   // (with a scratch block, every launch below runs grouped; chunks of at most max_n)
-  const uint32_t window = sort_window(sampling_footprint(g));
+  const uint32_t window = sort_window_for(g);
   hipError_t e = launch_fill_u64(g->small + kWHits, 0, 2 * 22, s);
   if (e == hipSuccess) e = hipEventRecord(g->ev0, s);
   for (int i = 0; i < count && e == hipSuccess; ++i) {

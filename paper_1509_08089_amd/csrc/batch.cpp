@@ -41,6 +41,11 @@ Tuning current_tuning() {
   return g_tuning;
 }
 
+uint32_t sort_window_for(const moss_graph* g) {
+  const uint32_t w = current_tuning().sort_window;
+  return w ? w : sort_window(sampling_footprint(g));
+}
+
 BatchRunner* batch_runner(int device) {
   std::lock_guard<std::mutex> lk(g_runner_mu);
   auto it = g_runners.find(device);
@@ -259,7 +264,7 @@ moss_status BatchRunner::run(const std::vector<WorkItem>& work, uint32_t n_slots
     if (!sort_large || w.k1 <= w.k0 || w.g->total[sampler_slot(w.sampler)] == 0) continue;
     if (!batch_sorted(w.g, w.k1 - w.k0, tune)) continue;
     const SamplerView view = sampler_view(w.g, w.sampler);
-    const uint32_t window = sort_window(sampling_footprint(w.g));
+    const uint32_t window = sort_window_for(w.g);
     for (uint64_t a = w.k0; a < w.k1; a += kBatchSortChunk) {
       const uint64_t n = std::min<uint64_t>(kBatchSortChunk, w.k1 - a);
       SortChunk c{w.sampler, w.seed, a, n, w.slot, window, 0, 0, view};
@@ -501,6 +506,7 @@ moss_status moss_set_tuning(const moss_tuning* t) {
   if (t->threads_per_block && (t->threads_per_block % 64 != 0 || t->threads_per_block > 256)) return MOSS_E_ARG;
   if (t->blocks_per_cu > 64 || t->schedule > MOSS_SCHEDULE_XCD) return MOSS_E_ARG;
   if (t->group_min_samples_log2 > 40 || t->group_min_footprint_mb > (1u << 20)) return MOSS_E_ARG;
+  if (t->sort_window % 64 != 0 || t->sort_window > 512) return MOSS_E_ARG;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuning.tile_samples = t->tile_samples;
   g_tuning.blocks_per_cu = t->blocks_per_cu;
@@ -508,6 +514,7 @@ moss_status moss_set_tuning(const moss_tuning* t) {
   g_tuning.schedule = t->schedule;
   g_tuning.group_min_samples_log2 = t->group_min_samples_log2;
   g_tuning.group_min_footprint_mb = t->group_min_footprint_mb;
+  g_tuning.sort_window = t->sort_window;
   return MOSS_OK;
 }
 
@@ -520,6 +527,7 @@ moss_status moss_get_tuning(moss_tuning* t) {
   t->schedule = g_tuning.schedule;
   t->group_min_samples_log2 = g_tuning.group_min_samples_log2;
   t->group_min_footprint_mb = g_tuning.group_min_footprint_mb;
+  t->sort_window = g_tuning.sort_window;
   return MOSS_OK;
 }
 
@@ -529,6 +537,7 @@ moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best
   static const uint32_t kBpc[] = {2, 3, 4, 5, 6, 8};
   static const uint32_t kGroupLog2[] = {17, 18, 19, 20, 21, 22};
   static const uint32_t kGroupMb[] = {4, 8, 16, 32, 64};
+  static const uint32_t kWindows[] = {128, 256, 512};
   const moss_tuning before = [] {
     moss_tuning t{};
     (void)moss_get_tuning(&t);
@@ -556,7 +565,7 @@ moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best
   b.threads_per_block = 256;
   // 1. tile size and occupancy of the persistent kernel, at the default grouping
   moss_tuning c = b;
-  c.group_min_samples_log2 = c.group_min_footprint_mb = 0;
+  c.group_min_samples_log2 = c.group_min_footprint_mb = c.sort_window = 0;
   for (uint32_t T : kTiles) {
     for (uint32_t bpc : kBpc) {
       c.tile_samples = T;
@@ -586,6 +595,19 @@ moss_status moss_autotune(const moss_request* reqs, int32_t n, moss_tuning* best
         best_t = ms;
         b = c;
       }
+    }
+  }
+  // 3. the window of the grouped launches' sorted kernel (by footprint, or fixed)
+  for (uint32_t w : kWindows) {
+    if (st != MOSS_OK) break;
+    c = b;
+    c.sort_window = w;
+    if ((st = moss_set_tuning(&c)) != MOSS_OK) break;
+    double ms;
+    if ((st = timed(c.tile_samples, c.blocks_per_cu, &ms)) != MOSS_OK) break;
+    if (ms < best_t) {
+      best_t = ms;
+      b = c;
     }
   }
   if (st != MOSS_OK) {

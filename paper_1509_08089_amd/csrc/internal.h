@@ -144,7 +144,11 @@ struct Tuning {
   uint32_t schedule = 0;  // MOSS_SCHEDULE_*
   uint32_t group_min_samples_log2 = 0;  // batched items drawn grouped: at least 2^x samples (0 = default)
   uint32_t group_min_footprint_mb = 0;  // ... on graphs whose sampled bytes reach x MB (0 = default)
+  uint32_t sort_window = 0;             // samples per window of the sorted kernel (0 = by footprint)
 };
+
+// The sorted sampling kernel's window on g: the tuning's, else by the sampled bytes.
+uint32_t sort_window_for(const moss_graph* g);
 Tuning current_tuning();
 
 // RAII claim on a graph for the duration of a call (MOSS_E_BUSY when taken).

@@ -88,7 +88,8 @@ class moss_request(ctypes.Structure):
 class moss_tuning(ctypes.Structure):
     _fields_ = [("tile_samples", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("threads_per_block", ctypes.c_uint32), ("schedule", ctypes.c_uint32),
-                ("group_min_samples_log2", ctypes.c_uint32), ("group_min_footprint_mb", ctypes.c_uint32)]
+                ("group_min_samples_log2", ctypes.c_uint32), ("group_min_footprint_mb", ctypes.c_uint32),
+                ("sort_window", ctypes.c_uint32)]
 
 
 class moss_server_config(ctypes.Structure):
@@ -310,9 +311,9 @@ def _requests(requests):
 
 
 def moss_set_tuning(tile_samples: int = 0, blocks_per_cu: int = 0, threads_per_block: int = 0, schedule: int = 0,
-                    group_min_samples_log2: int = 0, group_min_footprint_mb: int = 0):
+                    group_min_samples_log2: int = 0, group_min_footprint_mb: int = 0, sort_window: int = 0):
     t = moss_tuning(tile_samples, blocks_per_cu, threads_per_block, schedule, group_min_samples_log2,
-                    group_min_footprint_mb)
+                    group_min_footprint_mb, sort_window)
     _check(lib().moss_set_tuning(ctypes.byref(t)), "moss_set_tuning")
 
 

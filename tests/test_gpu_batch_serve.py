@@ -129,6 +129,29 @@ def test_grouping_thresholds_do_not_change_results(graphs, lg, mb):
         np.testing.assert_array_equal(a.estimate_np, b.estimate_np)
 
 
+@pytest.mark.parametrize("window", [64, 128, 512])
+def test_sort_window_does_not_change_results(graphs, window):
+    """The sorted kernel's window (samples a block takes at a time) only changes which
+    lanes draw which samples: batched items sent to grouped launches (every item of
+    2^10 samples or more on graphs of 1 MB or more) and a plain estimate on the largest
+    graph, drawn grouped, give the results they give alone with the default window."""
+    gs, handles = graphs
+    reqs = _requests(handles, 24, 6)
+    ref = [_alone(q) for q in reqs]
+    plain_ref = moss.moss_estimate(handles[5].h, 4, 3_000_000, 9, 0)
+    moss.moss_set_tuning(0, 0, 0, moss.MOSS_SCHEDULE_XCD, 10, 1, window)
+    try:
+        assert moss.moss_get_tuning().sort_window == window
+        got = moss.moss_estimate_batch(reqs)
+        plain = moss.moss_estimate(handles[5].h, 4, 3_000_000, 9, 0)
+    finally:
+        moss.moss_set_tuning(0, 0, 0)
+    for a, b in zip(ref, got):
+        np.testing.assert_array_equal(a.hits_np, b.hits_np)
+        np.testing.assert_array_equal(a.estimate_np, b.estimate_np)
+    np.testing.assert_array_equal(plain_ref.hits_np, plain.hits_np)
+
+
 def test_autotune_keeps_results(graphs):
     gs, handles = graphs
     reqs = _requests(handles, 16, 3)

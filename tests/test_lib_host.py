@@ -213,14 +213,14 @@ def test_probe_library_exports_and_rejects_bad_arguments():
 def test_tuning_knobs_round_trip_and_bounds():
     """The launch knobs are host state: set, read back, and bad values refused."""
     try:
-        moss.moss_set_tuning(4096, 6, 256, moss.MOSS_SCHEDULE_XCD, 19, 8)
+        moss.moss_set_tuning(4096, 6, 256, moss.MOSS_SCHEDULE_XCD, 19, 8, 256)
         t = moss.moss_get_tuning()
         assert (t.tile_samples, t.blocks_per_cu, t.threads_per_block, t.schedule, t.group_min_samples_log2,
-                t.group_min_footprint_mb) == (4096, 6, 256, moss.MOSS_SCHEDULE_XCD, 19, 8)
+                t.group_min_footprint_mb, t.sort_window) == (4096, 6, 256, moss.MOSS_SCHEDULE_XCD, 19, 8, 256)
         for bad in ((0, 0, 96, 0, 0, 0), (0, 65, 0, 0, 0, 0), (0, 0, 0, 3, 0, 0), (0, 0, 0, 0, 41, 0),
-                    (0, 0, 0, 0, 0, (1 << 20) + 1)):
+                    (0, 0, 0, 0, 0, (1 << 20) + 1), (0, 0, 0, 0, 0, 0, 100), (0, 0, 0, 0, 0, 0, 576)):
             with pytest.raises(moss.MossError):
                 moss.moss_set_tuning(*bad)
     finally:
         moss.moss_set_tuning(0, 0, 0)
-    assert moss.moss_get_tuning().group_min_samples_log2 == 0
+    assert moss.moss_get_tuning().group_min_samples_log2 == 0 and moss.moss_get_tuning().sort_window == 0
