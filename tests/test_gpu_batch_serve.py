@@ -196,12 +196,15 @@ def test_server_alone_and_in_mix(graphs, express):
 def test_server_express_beside_a_long_request(graphs):
     """Small requests submitted while a long request runs in the iterations take the
     express path: they finish while it is still running, with the results they have
-    alone, and so does the long request."""
+    alone, and so does the long request.  Their graph is a fresh copy without tables,
+    so its tables are built by the server's builder thread beside the long request
+    before the express thread takes them."""
     gs, handles = graphs
+    fresh = moss.Graph(gs[1])
     srv = moss.moss_server_create(0, 16, 1 << 20, iteration_samples=1 << 20)
     try:
         gid = moss.moss_server_add_graph(srv, handles[5].h)
-        sid = moss.moss_server_add_graph(srv, handles[1].h)
+        sid = moss.moss_server_add_graph(srv, fresh.h)
         t_long = moss.moss_server_submit(srv, gid, 5, 200_000_000, 7)
         small = [(sid, 4 + (i % 2), 50_000 + 1000 * i, 100 + i) for i in range(6)]
         ts = [moss.moss_server_submit(srv, *q) for q in small]
@@ -218,6 +221,7 @@ def test_server_express_beside_a_long_request(graphs):
         np.testing.assert_array_equal(a.hits_np, r.hits_np)
     finally:
         moss.moss_server_destroy(srv)
+        fresh.close()
 
 
 def test_server_memory_budget_evicts_and_rejects():
