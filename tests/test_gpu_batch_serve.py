@@ -193,6 +193,51 @@ def test_server_alone_and_in_mix(graphs, express):
         moss.moss_server_destroy(srv)
 
 
+def test_server_concurrent_clients(graphs):
+    """Four client threads submit and wait at once (the C calls release the interpreter
+    lock), small requests and large ones on shared graphs: every result equals the same
+    request alone (computed afterwards from this thread: a graph takes one direct call at
+    a time, so the clients do not make their own)."""
+    import threading
+    gs, handles = graphs
+    srv = moss.moss_server_create(0, 32, 1 << 18, iteration_samples=1 << 20, express_samples=50_000)
+    errors, served = [], []
+    try:
+        ids = [moss.moss_server_add_graph(srv, h.h) for h in handles]
+
+        def client(c):
+            try:
+                rng = np.random.Generator(np.random.PCG64(100 + c))
+                mine = []
+                for i in range(12):
+                    gi = int(rng.integers(0, len(handles)))
+                    k = 4 if rng.random() < 0.5 else 5
+                    n = int(10 ** rng.uniform(3, 6.3))
+                    seed = 1000 * c + i
+                    mine.append((gi, k, n, seed, moss.moss_server_submit(srv, ids[gi], k, n, seed)))
+                for gi, k, n, seed, t in mine:
+                    served.append(((gi, k, n, seed), moss.moss_server_wait(srv, t, 120_000)))
+            except Exception as e:  # reported below, from the test's own thread
+                errors.append(e)
+
+        threads = [threading.Thread(target=client, args=(c,)) for c in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(300)
+        assert not any(t.is_alive() for t in threads)
+        assert not errors, errors[0]
+        st = moss.moss_server_stats_get(srv)
+        assert st.completed == 48 and st.queued == 0 and st.active == 0
+    finally:
+        moss.moss_server_destroy(srv)
+    assert len(served) == 48
+    for (gi, k, n, seed), r in served:
+        a = moss.moss_estimate(handles[gi].h, k, n, seed, 0)
+        np.testing.assert_array_equal(a.hits_np, r.hits_np)
+        np.testing.assert_array_equal(a.estimate_np, r.estimate_np)
+
+
 def test_server_express_beside_a_long_request(graphs):
     """Small requests submitted while a long request runs in the iterations take the
     express path: they finish while it is still running, with the results they have
