@@ -17,7 +17,8 @@
  *  - A graph and everything built for it live on the device that was current
  *    when it was created; its work is queued on the stream given at creation
  *    (NULL = the default stream).  Calls on one graph must not overlap
- *    (MOSS_E_BUSY otherwise).
+ *    (MOSS_E_BUSY otherwise); a server holds a graph registered with it while it
+ *    builds or evicts the graph's tables.
  *  - Results are a pure function of (graph, k, n_samples, seed, flags): they do
  *    not depend on grid size, batch membership, tile size or arrival time.
  *
